@@ -184,3 +184,15 @@ def ripalm(C, R=None, params=None, x0=None, U0=None, V0=None, want_mult=False, *
     if want_mult:
         return x[0], x[1:].copy(), stats, U, V
     return x[0], x[1:].copy(), stats
+
+
+def prepare_f32(C, R, origin):
+    """The precision preparation written out: each row minus the origin in
+    FP64, rounded to nearest FP32; radii rounded to FP32; and the scale
+    L = max_i ||c_i - origin|| + r_i."""
+    C = _f64(C)
+    E = C - np.asarray(origin, dtype=np.float64)[None, :]
+    C32 = E.astype(np.float32)
+    R32 = None if R is None else _f64(R).astype(np.float32)
+    L, _, _ = check_feasible(C, R, 0.0, origin, np.inf)
+    return C32, R32, L

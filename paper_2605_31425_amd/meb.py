@@ -1,0 +1,232 @@
+"""ctypes binding of libmeb.so (include/meb.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+torch supplies device memory (tensors are passed by ``data_ptr()``) and the
+current stream.  Importing this module on a machine without the built
+library raises immediately; there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmeb.so")
+
+MEB_OK = 0
+MEB_WARN_MAXITER = 1
+MEB_F64 = 0
+MEB_F32 = 1
+MEB_MODE_FP64 = 0
+MEB_MODE_MIXED = 1
+WANT_PSI, WANT_GRAD, WANT_HESS, WANT_MULT, WANT_DMULT, WANT_KKT = 1, 2, 4, 8, 16, 32
+WANT_ALL = 63
+
+EXPORTS = ["meb_default_options", "meb_last_error", "meb_workspace_size", "meb_eval_workspace_size", "meb_solve",
+           "meb_al_eval", "meb_screen", "meb_check_feasible", "meb_prepare_f32", "meb_chol_workspace_size",
+           "meb_chol_solve"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("sigma0", ctypes.c_double), ("sigma_growth", ctypes.c_double),
+                ("sigma_max", ctypes.c_double), ("tau", ctypes.c_double), ("tol_kkt", ctypes.c_double),
+                ("tol_kkt_low", ctypes.c_double), ("tol_red", ctypes.c_double), ("eps_feas_rel", ctypes.c_double),
+                ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32), ("max_ls", ctypes.c_int32),
+                ("max_reinsert", ctypes.c_int32), ("mode", ctypes.c_int32), ("stall_outer", ctypes.c_int32),
+                ("verbose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int32 * 2), ("inner", ctypes.c_int32 * 2), ("passes", ctypes.c_int32 * 2),
+                ("kkt", ctypes.c_double * 2), ("L", ctypes.c_double), ("rbar", ctypes.c_double),
+                ("delta_max", ctypes.c_double), ("n_red", ctypes.c_int64), ("reinsert_rounds", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 4)]
+
+    def as_dict(self):
+        return dict(outer=list(self.outer), inner=list(self.inner), passes=list(self.passes), kkt=list(self.kkt),
+                    L=self.L, rbar=self.rbar, delta_max=self.delta_max, n_red=self.n_red,
+                    reinsert_rounds=self.reinsert_rounds, status=self.status, ms_total=self.ms_total,
+                    ms_phase=list(self.ms_phase))
+
+
+class MebError(RuntimeError):
+    pass
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_szp = ctypes.POINTER(ctypes.c_size_t)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise MebError(f"{LIB_PATH} is not built; run paper_2605_31425_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    L.meb_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.meb_last_error.restype = ctypes.c_char_p
+    L.meb_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Options), _szp]
+    L.meb_eval_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _szp]
+    L.meb_solve.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Options), _vp,
+                            ctypes.c_size_t, _dp, _dp, _vp, _vp, ctypes.POINTER(Stats), _vp]
+    L.meb_al_eval.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _dp, _dp,
+                              ctypes.c_double, ctypes.c_double, _dp, ctypes.c_int32, _dp, ctypes.c_uint32, _dp, _dp,
+                              _dp, _dp, _vp, _vp, _dp, _dp, _vp, ctypes.c_size_t, _vp]
+    L.meb_screen.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _dp,
+                             ctypes.c_double, _vp, _i64p, _vp, _vp, ctypes.c_size_t, _vp]
+    L.meb_check_feasible.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _dp,
+                                     ctypes.c_double, _dp, _i64p, _vp, ctypes.c_int64, _i64p, _vp, ctypes.c_size_t,
+                                     _vp]
+    L.meb_prepare_f32.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _dp, _vp, _vp, _dp, _vp, ctypes.c_size_t,
+                                  _vp]
+    L.meb_chol_workspace_size.argtypes = [ctypes.c_int32, _szp]
+    L.meb_chol_solve.argtypes = [ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    return L
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc < 0:
+        raise MebError(f"libmeb error {rc}: {lib.meb_last_error().decode()}")
+    return rc
+
+
+def options(**kw):
+    o = Options()
+    lib.meb_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "mode" and isinstance(v, str):
+            v = {"fp64": MEB_MODE_FP64, "mixed": MEB_MODE_MIXED}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float64:
+        return MEB_F64
+    if t.dtype == torch.float32:
+        return MEB_F32
+    raise MebError("centers must be float64 or float32")
+
+
+def _host(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _workspace(nbytes, device):
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def solve(C, R=None, opts=None, want_mult=False, workspace=None, **kw):
+    """meb_solve on device tensors C (m x d float64) and R (m or None).
+    Returns (r, c numpy, stats dict[, U, V tensors])."""
+    assert C.is_cuda and C.is_contiguous() and C.dim() == 2
+    m, d = C.shape
+    o = opts if opts is not None else options(**kw)
+    nb = ctypes.c_size_t()
+    _check(lib.meb_workspace_size(m, d, _dtype_code(C), ctypes.byref(o), ctypes.byref(nb)))
+    ws = workspace if workspace is not None and workspace.numel() >= nb.value else _workspace(nb.value, C.device)
+    r = ctypes.c_double()
+    c = np.empty(d)
+    U = torch.empty(m, dtype=torch.float64, device=C.device) if want_mult else None
+    V = torch.empty((m, d), dtype=torch.float64, device=C.device) if want_mult else None
+    st = Stats()
+    rc = _check(lib.meb_solve(_ptr(C), _ptr(R), m, d, _dtype_code(C), ctypes.byref(o), _ptr(ws), ws.numel(),
+                              ctypes.byref(r), c.ctypes.data_as(_dp), _ptr(U), _ptr(V), ctypes.byref(st), _stream()))
+    out = (r.value, c, dict(st.as_dict(), rc=rc))
+    return out + (U, V) if want_mult else out
+
+
+def al_eval(C, R, U, V, x, xbar, sigma, tau, direction=None, etas=(), want=WANT_ALL):
+    """meb_al_eval.  Returns a dict with psi, psi_trial, g, H, U_new, V_new, dmult, kkt."""
+    m, d = C.shape
+    dt = _dtype_code(C)
+    nb = ctypes.c_size_t()
+    _check(lib.meb_eval_workspace_size(m, d, dt, ctypes.byref(nb)))
+    ws = _workspace(nb.value, C.device)
+    xh, xp = _host(x)
+    xbh, xbp = _host(xbar)
+    dh, dp = _host(direction) if direction is not None else (None, None)
+    eh, ep = _host(etas) if len(etas) else (None, None)
+    psi = ctypes.c_double()
+    dm = ctypes.c_double()
+    pt = np.empty(max(len(etas), 1))
+    g = np.empty(d + 1)
+    H = np.empty((d + 1, d + 1))
+    kkt = np.empty(5)
+    Un = torch.empty(m, dtype=C.dtype, device=C.device) if want & WANT_MULT else None
+    Vn = torch.empty((m, d), dtype=C.dtype, device=C.device) if want & WANT_MULT else None
+    _check(lib.meb_al_eval(_ptr(C), _ptr(R), _ptr(U), _ptr(V), m, d, dt, xp, xbp, float(sigma), float(tau), dp,
+                           len(etas), ep, want, ctypes.byref(psi), pt.ctypes.data_as(_dp) if len(etas) else None,
+                           g.ctypes.data_as(_dp), H.ctypes.data_as(_dp), _ptr(Un), _ptr(Vn), ctypes.byref(dm),
+                           kkt.ctypes.data_as(_dp), _ptr(ws), ws.numel(), _stream()))
+    return dict(psi=psi.value, psi_trial=pt[:len(etas)], g=g, H=H, U=Un, V=Vn, dmult=dm.value, kkt=kkt)
+
+
+def screen(C, R, r_hat, c_hat, tol_red, want_slack=False):
+    m, d = C.shape
+    dt = _dtype_code(C)
+    nb = ctypes.c_size_t()
+    _check(lib.meb_eval_workspace_size(m, d, dt, ctypes.byref(nb)))
+    ws = _workspace(nb.value, C.device)
+    keep = torch.empty(m, dtype=torch.int64, device=C.device)
+    slack = torch.empty(m, dtype=torch.float64, device=C.device) if want_slack else None
+    n = ctypes.c_int64()
+    ch, cp = _host(c_hat)
+    _check(lib.meb_screen(_ptr(C), _ptr(R), m, d, dt, float(r_hat), cp, float(tol_red), _ptr(keep), ctypes.byref(n),
+                          _ptr(slack), _ptr(ws), ws.numel(), _stream()))
+    return keep[:n.value], slack
+
+
+def check_feasible(C, R, r, c, eps, viol_cap=None):
+    m, d = C.shape
+    dt = _dtype_code(C)
+    nb = ctypes.c_size_t()
+    _check(lib.meb_eval_workspace_size(m, d, dt, ctypes.byref(nb)))
+    ws = _workspace(nb.value, C.device)
+    cap = m if viol_cap is None else viol_cap
+    viol = torch.empty(max(cap, 1), dtype=torch.int64, device=C.device)
+    dmax = ctypes.c_double()
+    am = ctypes.c_int64()
+    nv = ctypes.c_int64()
+    ch, cp = _host(c)
+    _check(lib.meb_check_feasible(_ptr(C), _ptr(R), m, d, dt, float(r), cp, float(eps), ctypes.byref(dmax),
+                                  ctypes.byref(am), _ptr(viol) if cap > 0 else None, cap, ctypes.byref(nv), _ptr(ws),
+                                  ws.numel(), _stream()))
+    return dmax.value, am.value, viol[:min(nv.value, cap)], nv.value
+
+
+def prepare_f32(C, R, origin=None):
+    m, d = C.shape
+    nb = ctypes.c_size_t()
+    _check(lib.meb_eval_workspace_size(m, d, MEB_F64, ctypes.byref(nb)))
+    ws = _workspace(nb.value, C.device)
+    C32 = torch.empty((m, d), dtype=torch.float32, device=C.device)
+    R32 = torch.empty(m, dtype=torch.float32, device=C.device) if R is not None else None
+    L = ctypes.c_double()
+    op = _host(origin)[1] if origin is not None else None
+    _check(lib.meb_prepare_f32(_ptr(C), _ptr(R), m, d, op, _ptr(C32), _ptr(R32), ctypes.byref(L), _ptr(ws),
+                               ws.numel(), _stream()))
+    return C32, R32, L.value
+
+
+def chol_solve(H, b):
+    n = b.shape[0]
+    nb = ctypes.c_size_t()
+    _check(lib.meb_chol_workspace_size(n, ctypes.byref(nb)))
+    ws = _workspace(nb.value, H.device)
+    y = torch.empty_like(b)
+    _check(lib.meb_chol_solve(n, _ptr(H), _ptr(b), _ptr(y), _ptr(ws), ws.numel(), _stream()))
+    return y

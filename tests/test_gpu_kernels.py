@@ -1,0 +1,162 @@
+"""Per-kernel parity of the HIP path against the CPU oracle (GPU).
+
+meb_al_eval is compared with the oracle's direct per-ball evaluator on the
+same seeded inputs: FP64 to 1e-12 and FP32 to 1e-5, normwise (the error of
+each output is measured against the sum of magnitudes of the terms that
+make it up, since g -> 0 near the optimum).  The screening and feasibility
+index sets are compared exactly, except for balls whose slack lies within
+rounding of the threshold, where either decision is correct.  Sizes span
+several waves and a ragged tail; d covers every lane-group configuration.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_common import cone_multipliers, dev, gpu, near_point
+
+pytestmark = gpu
+
+SHAPES = [(1, 3), (7, 1), (130, 2), (1000, 3), (4097, 10), (3001, 17), (2500, 64), (1999, 100), (601, 129),
+          (300, 512), (150, 1001)]
+
+
+def _inst(seed, m, d, balls=True):
+    rng = np.random.default_rng(seed)
+    C = rng.normal(size=(m, d))
+    R = rng.uniform(0, 0.2, m) if balls else None
+    return rng, C, R
+
+
+@pytest.mark.parametrize("m,d", SHAPES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_al_eval_parity(m, d, dtype):
+    from paper_2605_31425_amd import meb
+    print(f"al_eval m={m} d={d} {dtype}", flush=True)
+    rng, C, R = _inst(m * 1000 + d, m, d, balls=(m % 2 == 1))
+    U, V = cone_multipliers(rng, m, d)
+    x = near_point(rng, C, R)
+    xbar = x + rng.normal(size=d + 1) * 0.01
+    direction = rng.normal(size=d + 1) * 0.02
+    sigma, tau = 3.0, 0.7
+    etas = [1.0, 0.5, 0.25, 0.125, 0.0]
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":  # the oracle sees exactly the FP32 inputs
+        C, U, V = C.astype(np.float32).astype(np.float64), U.astype(np.float32).astype(np.float64), \
+            V.astype(np.float32).astype(np.float64)
+        R = None if R is None else R.astype(np.float32).astype(np.float64)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    out = meb.al_eval(dev(C, tdt), dev(R, tdt), dev(U, tdt), dev(V, tdt), x, xbar, sigma, tau, direction=direction,
+                      etas=etas)
+    y = x + direction
+    ref = oracle.al_eval(C, R, U, V, y, xbar, sigma, tau)
+    # scales: sums of magnitudes of the terms
+    Up, Vp = ref["U"], ref["V"]
+    sg = 1.0 + np.concatenate([[np.abs(Up).sum()], np.abs(Vp).sum(0)]) + tau / sigma * np.abs(y - xbar)
+    assert np.all(np.abs(out["g"] - ref["g"]) <= tol * sg), np.abs(out["g"] - ref["g"]).max()
+    nact = ref["counts"][0] + ref["counts"][2]
+    sH = tau / sigma + sigma * max(nact, 1)
+    assert np.abs(out["H"] - ref["H"]).max() <= tol * sH
+    spsi = abs(y[0]) + sigma / 2 * (np.sum((Up / sigma) ** 2) + np.sum((Vp / sigma) ** 2)) + \
+        (np.sum(U ** 2) + np.sum(V ** 2)) / (2 * sigma) + tau / (2 * sigma) * np.sum((y - xbar) ** 2) + 1.0
+    assert abs(out["psi"] - ref["psi"]) <= tol * spsi
+    for eta, pv in zip(etas, out["psi_trial"]):
+        rt = oracle.al_eval(C, R, U, V, x + eta * direction, xbar, sigma, tau, want_h=False)
+        assert abs(pv - rt["psi"]) <= 10 * tol * spsi, (eta, pv, rt["psi"])
+    sdm = np.sum(Up ** 2) + np.sum(Vp ** 2) + np.sum(U ** 2) + np.sum(V ** 2) + 1e-300
+    assert abs(out["dmult"] - ref["dmult"]) <= tol * sdm
+    Un, Vn = out["U"].double().cpu().numpy(), out["V"].double().cpu().numpy()
+    sw = np.abs(Up).max() + 1
+    assert np.abs(Un - Up).max() <= tol * sw * 10
+    assert np.abs(Vn - Vp).max() <= tol * sw * 10
+    k_ref, parts = oracle.kkt_max(C, R, Up, Vp, y)
+    scale_k = [1 + np.abs(Up).sum(), 1 + np.abs(Vp).sum(), 1 + np.abs(y).max() + np.abs(C).max(), 1 + sw,
+               (1 + np.abs(y).max() + np.abs(C).max()) * sw]
+    for a, b, s in zip(out["kkt"], parts, scale_k):
+        assert abs(a - b) <= 10 * tol * s, (out["kkt"], parts)
+
+
+@pytest.mark.parametrize("m,d", SHAPES)
+def test_check_feasible_parity(m, d):
+    from paper_2605_31425_amd import meb
+    print(f"check m={m} d={d}", flush=True)
+    rng, C, R = _inst(7 * m + d, m, d)
+    x = near_point(rng, C, R)
+    eps = 1e-3
+    dmax, am, viol, nv = meb.check_feasible(dev(C), dev(R), x[0], x[1:], eps)
+    rd, ra, rv = oracle.check_feasible(C, R, x[0], x[1:], eps)
+    scale = np.abs(C).max() * np.sqrt(d) + 1
+    assert abs(dmax - rd) <= 1e-14 * scale
+    reach = np.linalg.norm(C - x[1:], axis=1) + R - x[0]
+    tie = np.abs(reach - reach.max()) <= 1e-14 * scale
+    assert am == ra or tie[am]
+    got = set(viol.cpu().numpy().tolist())
+    exp = set(rv.tolist())
+    border = set(np.flatnonzero(np.abs(reach - eps) <= 1e-13 * scale).tolist())
+    assert (got ^ exp) <= border
+    assert nv == len(got)
+    v = viol.cpu().numpy()
+    assert np.all(np.diff(v) > 0)
+    # a capacity smaller than the count keeps the first indices
+    if nv > 2:
+        _, _, v2, nv2 = meb.check_feasible(dev(C), dev(R), x[0], x[1:], eps, viol_cap=2)
+        assert nv2 == nv and np.array_equal(v2.cpu().numpy(), v[:2])
+
+
+@pytest.mark.parametrize("m,d", SHAPES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_screen_parity(m, d, dtype):
+    from paper_2605_31425_amd import meb
+    print(f"screen m={m} d={d} {dtype}", flush=True)
+    rng, C, R = _inst(11 * m + d, m, d, balls=(d % 2 == 0))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        C = C.astype(np.float32).astype(np.float64)
+        R = None if R is None else R.astype(np.float32).astype(np.float64)
+    x = near_point(rng, C, R)
+    tol = 0.3
+    keep, slack = meb.screen(dev(C, tdt), dev(R, tdt), x[0], x[1:], tol, want_slack=True)
+    rk, rs = oracle.screen(C, R, x[0], x[1:], tol)
+    scale = np.abs(C).max() * np.sqrt(d) + 1
+    assert np.abs(slack.cpu().numpy() - rs).max() <= 1e-14 * scale
+    border = set(np.flatnonzero(np.abs(rs - tol) <= 1e-13 * scale).tolist())
+    got = keep.cpu().numpy()
+    assert np.all(np.diff(got) > 0)
+    assert (set(got.tolist()) ^ set(rk.tolist())) <= border
+
+
+@pytest.mark.parametrize("m,d", [(1, 1), (333, 7), (5000, 100), (257, 1000)])
+def test_prepare_f32_bit_exact(m, d):
+    from paper_2605_31425_amd import meb
+    rng, C, R = _inst(m + d, m, d)
+    C = C * 50 + 1000.0  # offset data: the shift matters
+    origin = C[0].copy()
+    C32, R32, L = meb.prepare_f32(dev(C), dev(R), origin)
+    rc, rr, rL = oracle.prepare_f32(C, R, origin)
+    assert np.array_equal(C32.cpu().numpy(), rc)
+    assert np.array_equal(R32.cpu().numpy(), rr)
+    assert abs(L - rL) <= 1e-14 * rL
+
+
+@pytest.mark.parametrize("n", [1, 2, 11, 101, 141, 300])
+def test_chol_solve_parity(n):
+    from paper_2605_31425_amd import meb
+    rng = np.random.default_rng(n)
+    A = rng.normal(size=(n, n))
+    A = A @ A.T + n * np.eye(n)
+    b = rng.normal(size=n)
+    y = meb.chol_solve(dev(A), dev(b)).cpu().numpy()
+    ref = oracle.chol_solve(A, b)
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    with pytest.raises(meb.MebError):
+        meb.chol_solve(dev(-np.eye(n)), dev(b))
+
+
+def test_al_eval_deterministic_bitwise():
+    from paper_2605_31425_amd import meb
+    rng, C, R = _inst(5, 20000, 50)
+    U, V = cone_multipliers(rng, 20000, 50)
+    x = near_point(rng, C, R)
+    a = meb.al_eval(dev(C), dev(R), dev(U), dev(V), x, x, 2.0, 1.0)
+    b = meb.al_eval(dev(C), dev(R), dev(U), dev(V), x, x, 2.0, 1.0)
+    assert a["psi"] == b["psi"] and np.array_equal(a["g"], b["g"]) and np.array_equal(a["H"], b["H"])
