@@ -1,0 +1,184 @@
+"""Benchmark: time-to-solution of the minimum enclosing ball on one MI355X.
+
+Workload (default): balls, m = 1,000,000, d = 100, centers uniform in
+[-1, 1]^d, radii uniform in [0, 0.1], FP64 storage, seed 2 -- synthetic data
+of the shape the headline metric is quoted on.  One step is one complete
+meb_solve in mixed precision (FP32 preparation and screening run, FP64
+refinement of the retained balls, full FP64 feasibility check with
+reinsertion, radius fix-up), with the instance already resident in HBM.
+The plain FP64 ripALM solve of the same instance is timed beside it.
+
+Prints one JSON line.  `roofline` is the FP32 evaluation pass (the dominant
+kernel): algorithmic bytes it reads and writes (centers, radii, multipliers;
+counted on the device per launch) over its launch durations, both measured
+live with HIP events on the solve's stream during the timed steps.
+`cpu_baseline` runs the CPU oracle on a bounded sample of the same instance.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "balls_1e6_d100": dict(gen="balls_uniform", args=(1000000, 100, 2),
+                           desc="balls, m=1,000,000, d=100, centers U[-1,1]^d, radii U[0,0.1], FP64, seed 2"),
+    "points_1e4_d10": dict(gen="points_normal", args=(10000, 10, 1),
+                           desc="points, m=10,000, d=10, centers N(0,I), FP64, seed 1"),
+    "points_1e7_d10": dict(gen="points_ball_sphere", args=(10000000, 10, 4),
+                           desc="points, m=10,000,000, d=10, 90% in the unit ball, 10% on the sphere, seed 4"),
+    "balls_2e5_d1000": dict(gen="balls_normal", args=(200000, 1000, 3),
+                            desc="balls, m=200,000, d=1000, centers N(0,I), radii |N(0,0.05^2)|, seed 3"),
+}
+
+
+def golden(name):
+    p = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
+    if os.path.exists(p):
+        with open(p) as f:
+            return json.load(f)
+    return None
+
+
+def cpu_baseline(C, R, m_full, sample_m):
+    """The oracle as it stands, single-threaded, on the first sample_m balls;
+    time-to-solution scaled by m_full / sample_m (each pass is linear in m)."""
+    import oracle
+    Cs = np.ascontiguousarray(C[:sample_m])
+    Rs = None if R is None else np.ascontiguousarray(R[:sample_m])
+    t = time.perf_counter()
+    oracle.ripalm(Cs, Rs, tol=1e-8)
+    el = time.perf_counter() - t
+    return dict(value=el * m_full / sample_m, unit="s", cores=1, kind="oracle",
+                sample=f"oracle ripALM to KKT 1e-8 on the first {sample_m} balls of the same instance "
+                       f"({el:.2f} s), scaled by {m_full}/{sample_m}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="balls_1e6_d100", choices=sorted(WORKLOADS))
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=100000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              "(the path would shard the balls by rows across GPUs; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2605_31425_amd import inputs, meb
+
+    wl = WORKLOADS[a.workload]
+    gen = getattr(inputs, wl["gen"])
+    m, d, seed = wl["args"]
+    C, R = gen(m, d, seed)
+    dev = torch.device("cuda:0")
+    Cd = torch.as_tensor(C, device=dev)
+    Rd = None if R is None else torch.as_tensor(R, device=dev)
+    opts_mixed = meb.options(mode="mixed", profile=1)
+    opts_fp64 = meb.options(mode="fp64", profile=1)
+    import ctypes  # noqa: E402
+    nb = ctypes.c_size_t()
+    meb._check(meb.lib.meb_workspace_size(m, d, meb.MEB_F64, ctypes.byref(opts_mixed), ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    for _ in range(a.warmup):
+        meb.solve(Cd, Rd, opts=opts_mixed, workspace=ws)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        results.append(meb.solve(Cd, Rd, opts=opts_mixed, workspace=ws))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_mixed = (t1 - t0) * 1e3 / a.steps
+
+    # plain FP64 ripALM on the same instance
+    fp64 = []
+    nb64 = ctypes.c_size_t()
+    meb._check(meb.lib.meb_workspace_size(m, d, meb.MEB_F64, ctypes.byref(opts_fp64), ctypes.byref(nb64)))
+    ws64 = ws if nb64.value <= ws.numel() else torch.empty(nb64.value, dtype=torch.uint8, device=dev)
+    meb.solve(Cd, Rd, opts=opts_fp64, workspace=ws64)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(a.fp64_steps):
+        fp64.append(meb.solve(Cd, Rd, opts=opts_fp64, workspace=ws64))
+    torch.cuda.synchronize()
+    ms_fp64 = (time.perf_counter() - t2) * 1e3 / max(a.fp64_steps, 1)
+
+    r, c, st = results[-1]
+    g = golden(a.workload)
+    r_ref = g["r_fixed"] if g else None
+    reach = np.linalg.norm(C - c, axis=1) + (0.0 if R is None else R)
+    viol = float(reach.max() - r)
+
+    # roofline of the FP32 evaluation pass over the timed steps
+    p_ms = sum(s["pass_ms"][0] for _, _, s in results)
+    p_bytes = sum(s["pass_bytes"][0] for _, _, s in results)
+    p_launch = sum(s["pass_launches"][0] for _, _, s in results)
+    achieved = (p_bytes / 1e9) / (p_ms / 1e3) if p_ms > 0 else 0.0
+    f64_ms = sum(s["pass_ms"][1] for _, _, s in fp64)
+    f64_bytes = sum(s["pass_bytes"][1] for _, _, s in fp64)
+
+    out = {
+        "metric": "time-to-solution at 1e-8 rel. radius (mixed vs FP64); HBM GB/s; p50/p99 latency",
+        "value": ms_mixed / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_mixed,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl["desc"],
+            "mode": "mixed: FP32 screening run to KKT 1e-2, FP64 refinement to KKT 1e-8, full FP64 check",
+            "fp64_ripalm_ms": ms_fp64,
+            "speedup_mixed_vs_fp64": ms_fp64 / ms_mixed,
+            "radius": r,
+            "radius_relerr_vs_oracle": (abs(r - r_ref) / r_ref) if r_ref else None,
+            "fp64_radius_relerr_vs_oracle": (abs(fp64[-1][0] - r_ref) / r_ref) if (r_ref and fp64) else None,
+            "max_violation": viol,
+            "kept_for_fp64": st["n_red"],
+            "reinsert_rounds": st["reinsert_rounds"],
+            "passes": st["passes"],
+            "ms_phase": st["ms_phase"],
+            "fp64_pass_GBps": (f64_bytes / 1e9) / (f64_ms / 1e3) if f64_ms > 0 else None,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "pass_kernel<float> (FP32 evaluation pass over all m balls)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "launches": p_launch,
+            "avg_launch_us": (p_ms * 1e3 / p_launch) if p_launch else None,
+            "algorithmic_bytes_per_launch": (p_bytes / p_launch) if p_launch else None,
+        },
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(C, R, m, min(a.cpu_sample, m))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,7 +97,8 @@ typedef struct meb_options {
     int32_t mode;          /* MEB_MODE_FP64 or MEB_MODE_MIXED; default MEB_MODE_MIXED                */
     int32_t stall_outer;   /* stop a run after this many outer steps without halving KKT_max; 3     */
     int32_t verbose;       /* 0 = silent; 1 = one line per outer iteration on stderr                 */
-    int32_t reserved;
+    int32_t profile;       /* 1 = time every evaluation pass with HIP events (fills the pass_*
+                              fields of meb_stats); default 0                                   */
 } meb_options;
 
 /* Statistics of one meb_solve.  Index 0 = FP32 screening run (mixed mode),
@@ -116,6 +117,18 @@ typedef struct meb_stats {
     int32_t status;        /* same as the return value                          */
     double ms_total;       /* wall time of the call, ms                         */
     double ms_phase[4];    /* ms: prepare+FP32 run, screen+gather, FP64 run(s), checks */
+    /* with opts->profile: summed device time and algorithmic bytes (input rows,
+     * radii, multipliers read; multipliers written) of the evaluation-pass
+     * launches of each run, and the number of launches */
+    double pass_ms[2];
+    double pass_bytes[2];
+    int32_t pass_launches[2];
+    int32_t reserved;
+    /* rows of the rank-one Hessian contraction (balls in the third
+     * projection case), summed over the passes of each run, and the largest
+     * count of one pass */
+    double mid_rows[2];
+    double mid_rows_max[2];
 } meb_stats;
 
 /* Fills *opts with the defaults listed above.  Returns MEB_OK. */

@@ -109,6 +109,23 @@ thread_local Pinned g_pin;
 
 size_t dtype_size(int dtype) { return dtype == MEB_F64 ? 8 : 4; }
 
+// Thread-local pool of HIP events for the optional per-pass timing.
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    ~EventPool() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    hipEvent_t at(size_t i) {
+        while (ev.size() <= i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev.push_back(e);
+        }
+        return ev[i];
+    }
+};
+thread_local EventPool g_events;
+
 // ---------------------------------------------------------------------------
 // Evaluation engine: the buffers of the pass / reduce / contraction / control
 // sequence for one instance shape.
@@ -129,6 +146,11 @@ struct Engine {
     double* mid_coef = nullptr;
     int32_t* mid_cnt = nullptr;
     double* syrk = nullptr;
+    int32_t* list_idx = nullptr;
+    double* list_coef = nullptr;
+    int64_t* list_offs = nullptr;
+    int64_t* list_total = nullptr;
+    double skip_k = INFINITY;
 
     void setup(int64_t m_, int d_, int dtype_) {
         m = m_;
@@ -138,7 +160,9 @@ struct Engine {
         sl = StateLayout::make(d);
         rl = RecLayout::make(d);
         ntile = (d + syrk_tile() - 1) / syrk_tile();
-        ksplit = syrk_ksplit(d, pc.nwaves);
+        ksplit = syrk_ksplit(d);
+        // a line-search pass skips the contraction above this many rows
+        skip_k = std::max(4096.0, 16.0 * d);
     }
     template <typename A>
     void carve(A& a) {
@@ -151,6 +175,10 @@ struct Engine {
         mid_cnt = a.template take<int32_t>(pc.nwaves);
         const size_t pairs = (size_t)ntile * (ntile + 1) / 2;
         syrk = a.template take<double>((size_t)ksplit * pairs * syrk_tile() * syrk_tile());
+        list_idx = a.template take<int32_t>(cap);
+        list_coef = a.template take<double>(cap);
+        list_offs = a.template take<int64_t>(pc.nwaves);
+        list_total = a.template take<int64_t>(4);
     }
     PassArgs args(const void* C, const void* R, void* U, void* V) const {
         PassArgs a;
@@ -188,25 +216,32 @@ struct Engine {
         s.dtype = dtype;
         s.state = state;
         s.sl = sl;
-        s.mid_idx = mid_idx;
-        s.mid_coef = mid_coef;
-        s.mid_cnt = mid_cnt;
-        s.nwaves = pc.nwaves;
-        s.bw = pc.bw;
+        s.red = red;
+        s.rl = rl;
+        s.list_idx = list_idx;
+        s.list_coef = list_coef;
+        s.list_total = list_total;
+        s.skip_k = skip_k;
         s.out = syrk;
         s.ksplit = ksplit;
         s.tile = syrk_tile();
         s.ntile = ntile;
         return s;
     }
-    // pass + reduce + contraction (+ control when `control`)
-    int step(const PassArgs& a, bool control, hipStream_t s) {
-        HIPCHK(launch_pass(a, pc, s));
-        HIPCHK(launch_reduce_records(rec, pc.nwaves, rl.len, red, s));
-        if (use_syrk && a.want_mid) HIPCHK(launch_syrk(syrk_args(a.C, a.Uout ? a.Uout : a.U, a.Vout ? a.Vout : a.V), s));
-        if (control)
-            HIPCHK(launch_control(state, sl, rl, red, syrk, ksplit, syrk_tile(), ntile, use_syrk ? 1 : 0, nullptr,
-                                  s));
+    // pass + reduce + contraction (+ control when `control`); with `ev0`
+    // non-null, the pass launch is bracketed by the two events
+    int step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+        if (ev0) HIPCHK(hipEventRecord(ev0, s));
+        HIPCHK(launch_pass(a, pc, 3, s));
+        if (ev1) HIPCHK(hipEventRecord(ev1, s));
+        HIPCHK(launch_reduce_records(rec, pc.blocks, rl.len, (int64_t)pc.waves_per_block * rl.len, red, s));
+        if (use_syrk && a.want_mid) {
+            HIPCHK(launch_mid_compact(mid_cnt, pc.nwaves, pc.bw, mid_idx, mid_coef, list_offs, list_total, list_idx,
+                                      list_coef, state, s));
+            HIPCHK(launch_syrk(syrk_args(a.C, a.Uout ? a.Uout : a.U, a.Vout ? a.Vout : a.V), s));
+        }
+        if (control) HIPCHK(launch_assemble(state, sl, rl, red, syrk, ksplit, ntile, use_syrk ? 1 : 0, s));
+        if (control) HIPCHK(launch_control(state, sl, rl, red, nullptr, s));
         return MEB_OK;
     }
 };
@@ -223,28 +258,30 @@ size_t engine_bytes(int64_t m, int d, int dtype) {
 // Scan helpers (feasibility check / screening)
 // ---------------------------------------------------------------------------
 struct ScanBufs {
-    int nblocks = 0;
-    int64_t per_block = 0;
-    double* blk_max = nullptr;
-    int64_t* blk_arg = nullptr;
-    int64_t* blk_cnt = nullptr;
+    ScanCfg cfg{};
+    int64_t m = 0;
+    int d = 0;
+    double* wmax = nullptr;
+    int64_t* warg = nullptr;
+    int64_t* wcnt = nullptr;
+    int64_t* offs = nullptr;
     int64_t* seg = nullptr;
     double* out_max = nullptr;
     int64_t* out_arg = nullptr;
     int64_t* total = nullptr;
     double* cvec = nullptr;
-    void setup(int64_t m) {
-        const int64_t target = (int64_t)device_cus() * 4;
-        per_block = (m + target - 1) / target;
-        if (per_block < 256) per_block = 256;
-        nblocks = (int)((m + per_block - 1) / per_block);
+    void setup(int64_t m_, int d_) {
+        m = m_;
+        d = d_;
+        cfg = scan_config(m, d, device_cus());
     }
     template <typename A>
-    void carve(A& a, int64_t m, int d) {
-        blk_max = a.template take<double>(nblocks);
-        blk_arg = a.template take<int64_t>(nblocks);
-        blk_cnt = a.template take<int64_t>(nblocks);
-        seg = a.template take<int64_t>((size_t)m);
+    void carve(A& a) {
+        wmax = a.template take<double>(cfg.nwaves);
+        warg = a.template take<int64_t>(cfg.nwaves);
+        wcnt = a.template take<int64_t>(cfg.nwaves);
+        offs = a.template take<int64_t>(cfg.nwaves);
+        seg = a.template take<int64_t>((size_t)cfg.nwaves * cfg.bw);
         out_max = a.template take<double>(4);
         out_arg = a.template take<int64_t>(4);
         total = a.template take<int64_t>(4);
@@ -254,21 +291,23 @@ struct ScanBufs {
 
 size_t scan_bytes(int64_t m, int d) {
     ScanBufs b;
-    b.setup(m);
+    b.setup(m, d);
     Sizer s;
-    b.carve(s, m, d);
+    b.carve(s);
     return s.off;
 }
 
+// max_i (r_i + ||c - c_i|| - r) with its smallest argmax, and the ascending
+// list of {i : r_i + ||c - c_i|| - r > eps} (first viol_cap entries).
 int run_check(const void* C, const void* R, int64_t m, int d, int dtype, double r, const double* c_host, double eps,
               ScanBufs& b, double* dmax, int64_t* argmax, int64_t* viol_idx, int64_t viol_cap, int64_t* n_viol,
               hipStream_t s) {
     HIPCHK(hipMemcpyAsync(b.cvec, c_host, sizeof(double) * d, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_feasible(C, R, m, d, dtype, b.cvec, r, eps, b.blk_max, b.blk_arg, b.blk_cnt, b.seg, b.nblocks,
-                           b.per_block, s));
-    HIPCHK(launch_max_reduce(b.blk_max, b.blk_arg, b.nblocks, b.out_max, b.out_arg, s));
-    HIPCHK(launch_compact(b.seg, b.blk_cnt, b.nblocks, b.per_block, viol_idx ? viol_idx : b.seg, viol_idx ? viol_cap : 0,
-                          b.total, s));
+    HIPCHK(launch_scan(0, C, R, m, d, dtype, b.cvec, r, eps, nullptr, nullptr, nullptr, b.cfg, b.wmax, b.warg, b.wcnt,
+                       b.seg, s));
+    HIPCHK(launch_scan_finalize(b.wcnt, b.wmax, b.warg, b.cfg.nwaves, b.offs, b.total, b.out_max, b.out_arg, s));
+    if (viol_idx && viol_cap > 0)
+        HIPCHK(launch_scan_copy(b.seg, b.wcnt, b.offs, b.cfg.nwaves, b.cfg.bw, viol_idx, viol_cap, s));
     double* h = g_pin.get(3);
     if (!h) return fail(MEB_ERR_HIP, "pinned host allocation failed");
     HIPCHK(hipMemcpyAsync(h, b.out_max, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -287,8 +326,10 @@ int run_check(const void* C, const void* R, int64_t m, int d, int dtype, double 
 int run_screen(const void* C, const void* R, int64_t m, int d, int dtype, double r, const double* c_host, double tol,
                ScanBufs& b, int64_t* keep_idx, int64_t* n_keep, double* slack, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(b.cvec, c_host, sizeof(double) * d, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_screen(C, R, m, d, dtype, b.cvec, r, tol, slack, b.blk_cnt, b.seg, b.nblocks, b.per_block, s));
-    HIPCHK(launch_compact(b.seg, b.blk_cnt, b.nblocks, b.per_block, keep_idx, m, b.total, s));
+    HIPCHK(launch_scan(1, C, R, m, d, dtype, b.cvec, r, tol, slack, nullptr, nullptr, b.cfg, nullptr, nullptr, b.wcnt,
+                       b.seg, s));
+    HIPCHK(launch_scan_finalize(b.wcnt, nullptr, nullptr, b.cfg.nwaves, b.offs, b.total, nullptr, nullptr, s));
+    HIPCHK(launch_scan_copy(b.seg, b.wcnt, b.offs, b.cfg.nwaves, b.cfg.bw, keep_idx, m, s));
     double* h = g_pin.get(1);
     if (!h) return fail(MEB_ERR_HIP, "pinned host allocation failed");
     HIPCHK(hipMemcpyAsync(h, b.total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -296,6 +337,20 @@ int run_screen(const void* C, const void* R, int64_t m, int d, int dtype, double
     int64_t n;
     memcpy(&n, h, 8);
     *n_keep = n;
+    return MEB_OK;
+}
+
+// FP32 copy shifted by `origin` (device, d) and L = max_i ||c_i - origin|| + r_i.
+int run_prepare(const double* C, const double* R, int64_t m, int d, const double* origin_dev, float* C32, float* R32,
+                ScanBufs& b, double* L, hipStream_t s) {
+    HIPCHK(launch_scan(2, C, R, m, d, MEB_F64, origin_dev, 0.0, 0.0, nullptr, C32, R32, b.cfg, b.wmax, b.warg,
+                       nullptr, nullptr, s));
+    HIPCHK(launch_scan_finalize(nullptr, b.wmax, b.warg, b.cfg.nwaves, nullptr, nullptr, b.out_max, b.out_arg, s));
+    double* h = g_pin.get(1);
+    if (!h) return fail(MEB_ERR_HIP, "pinned host allocation failed");
+    HIPCHK(hipMemcpyAsync(h, b.out_max, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *L = h[0];
     return MEB_OK;
 }
 
@@ -316,6 +371,9 @@ struct RunResult {
     double sigma_end;       // raw
     int outer, inner, passes, status;
     double kkt;
+    double pass_ms = 0, pass_bytes = 0;
+    int launches = 0;
+    double sumk = 0, maxk = 0;
 };
 
 int run_ripalm(Engine& e, const void* C, const void* R, void* U, void* V, const double* x0, const RunParams& p,
@@ -352,8 +410,19 @@ int run_ripalm(Engine& e, const void* C, const void* R, void* U, void* V, const 
     const int64_t max_steps = (int64_t)o->max_outer * (o->max_inner + o->max_ls + 2) + 16;
     int64_t steps = 0;
     int last_k = -1;
+    const bool prof = o->profile != 0;
+    size_t nev = 0;
     for (;;) {
-        for (int b = 0; b < batch; ++b) CHK(e.step(a, true, s));
+        for (int b = 0; b < batch; ++b) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (prof) {
+                e0 = g_events.at(nev);
+                e1 = g_events.at(nev + 1);
+                if (!e0 || !e1) return fail(MEB_ERR_HIP, "hipEventCreate failed");
+                nev += 2;
+            }
+            CHK(e.step(a, true, s, e0, e1));
+        }
         steps += batch;
         HIPCHK(hipMemcpyAsync(hs, e.state, sizeof(double) * S_NSCALAR, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -381,6 +450,19 @@ int run_ripalm(Engine& e, const void* C, const void* R, void* U, void* V, const 
     out.passes = (int)hh[S_NPASS];
     out.kkt = hh[S_KKT];
     out.status = (int)hh[S_STATUS];
+    out.pass_bytes = hh[S_BYTES];
+    out.sumk = hh[S_SUMK];
+    out.maxk = hh[S_MAXK];
+    if (prof) {
+        double ms = 0;
+        for (size_t k = 0; k + 1 < nev; k += 2) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, g_events.at(k), g_events.at(k + 1)));
+            ms += t;
+        }
+        out.pass_ms = ms;
+        out.launches = (int)(nev / 2);
+    }
     if (out.status < 0) return fail(MEB_ERR_NUMERIC, "Newton system not positive definite");
     for (int k = 0; k < n1; ++k)
         if (!std::isfinite(out.x[k])) return fail(MEB_ERR_NUMERIC, "non-finite iterate");
@@ -407,12 +489,12 @@ struct SolveWs {
     void setup(int64_t m, int d, const meb_options* o) {
         e64.setup(m, d, MEB_F64);
         if (o->mode == MEB_MODE_MIXED) e32.setup(m, d, MEB_F32);
-        scan.setup(m);
+        scan.setup(m, d);
     }
     template <typename A>
     void carve(A& a, int64_t m, int d, const meb_options* o, bool has_r) {
         e64.carve(a);
-        scan.carve(a, m, d);
+        scan.carve(a);
         U64 = a.template take<double>((size_t)m);
         V64 = a.template take<double>((size_t)m * d);
         orig = a.template take<double>((size_t)d + 8);
@@ -473,6 +555,7 @@ int meb_default_options(meb_options* o) {
     o->mode = MEB_MODE_MIXED;
     o->stall_outer = 3;
     o->verbose = 0;
+    o->profile = 0;
     return MEB_OK;
 }
 
@@ -548,10 +631,13 @@ int meb_al_eval(const void* C, const void* R, const void* U, const void* V, int6
     a.dense_vout = 1;
     a.want_mid = (want & MEB_WANT_HESS) ? 1 : 0;
     for (int l = 0; l < NT; ++l) a.etas[l] = (l < n_eta) ? etas[l] : 0.0;
-    HIPCHK(launch_pass(a, e.pc, s));
-    HIPCHK(launch_reduce_records(e.rec, e.pc.nwaves, e.rl.len, e.red, s));
+    HIPCHK(launch_pass(a, e.pc, a.want_kkt ? 1 : 0, s));
+    HIPCHK(launch_reduce_records(e.rec, e.pc.blocks, e.rl.len, (int64_t)e.pc.waves_per_block * e.rl.len, e.red, s));
     if (want & MEB_WANT_HESS) {
+        HIPCHK(launch_mid_compact(e.mid_cnt, e.pc.nwaves, e.pc.bw, e.mid_idx, e.mid_coef, e.list_offs, e.list_total,
+                                  e.list_idx, e.list_coef, e.state, s));
         SyrkArgs sa = e.syrk_args(C, U, V);
+        sa.skip_k = INFINITY;
         HIPCHK(launch_syrk(sa, s));
     }
     // g and H into the tail of the state buffer (free in this call)
@@ -605,9 +691,9 @@ int meb_screen(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype
     CHK(meb_eval_workspace_size(m, d, dtype, &need));
     if (!ws || ws_bytes < need) return fail(MEB_ERR_WORKSPACE, "workspace too small");
     ScanBufs b;
-    b.setup(m);
+    b.setup(m, d);
     Arena ar{(char*)ws, ws_bytes, 0};
-    b.carve(ar, m, d);
+    b.carve(ar);
     return run_screen(C, R, m, d, dtype, r_hat, c_hat, tol_red, b, keep_idx, n_keep, slack, (hipStream_t)stream);
 }
 
@@ -621,9 +707,9 @@ int meb_check_feasible(const void* C, const void* R, int64_t m, int32_t d, int32
     CHK(meb_eval_workspace_size(m, d, dtype, &need));
     if (!ws || ws_bytes < need) return fail(MEB_ERR_WORKSPACE, "workspace too small");
     ScanBufs b;
-    b.setup(m);
+    b.setup(m, d);
     Arena ar{(char*)ws, ws_bytes, 0};
-    b.carve(ar, m, d);
+    b.carve(ar);
     return run_check(C, R, m, d, dtype, r, c, eps, b, delta_max, argmax, viol_cap > 0 ? viol_idx : nullptr, viol_cap,
                      n_viol, (hipStream_t)stream);
 }
@@ -637,17 +723,13 @@ int meb_prepare_f32(const double* C, const double* R, int64_t m, int32_t d, cons
     if (!ws || ws_bytes < need) return fail(MEB_ERR_WORKSPACE, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
     ScanBufs b;
-    b.setup(m);
+    b.setup(m, d);
     Arena ar{(char*)ws, ws_bytes, 0};
-    b.carve(ar, m, d);
-    if (origin)
-        HIPCHK(hipMemcpyAsync(b.cvec, origin, sizeof(double) * d, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_prepare_f32(C, R, m, d, origin ? b.cvec : nullptr, C32, R32, b.blk_max, b.nblocks, b.per_block, s));
-    std::vector<double> bm(b.nblocks);
-    HIPCHK(hipMemcpyAsync(bm.data(), b.blk_max, sizeof(double) * b.nblocks, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    b.carve(ar);
+    if (origin) HIPCHK(hipMemcpyAsync(b.cvec, origin, sizeof(double) * d, hipMemcpyHostToDevice, s));
+    else HIPCHK(launch_fill_f64(b.cvec, 0.0, d, s));
     double L = 0.0;
-    for (double v : bm) L = std::max(L, v);
+    CHK(run_prepare(C, R, m, d, b.cvec, C32, R32, b, &L, s));
     if (L_out) *L_out = L;
     return MEB_OK;
 }
@@ -711,12 +793,7 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
     double t0 = now_ms();
     if (o->mode == MEB_MODE_MIXED) {
         HIPCHK(hipMemcpyAsync(w.orig, c1.data(), sizeof(double) * d, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_prepare_f32((const double*)C, (const double*)R, m, d, w.orig, w.C32, w.R32, w.scan.blk_max,
-                                  w.scan.nblocks, w.scan.per_block, s));
-        std::vector<double> bm(w.scan.nblocks);
-        HIPCHK(hipMemcpyAsync(bm.data(), w.scan.blk_max, sizeof(double) * w.scan.nblocks, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (double v : bm) L = std::max(L, v);
+        CHK(run_prepare((const double*)C, (const double*)R, m, d, w.orig, w.C32, w.R32, w.scan, &L, s));
     } else {
         double dm;
         int64_t am, nv;
@@ -726,6 +803,7 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
     st.L = L;
     if (!std::isfinite(L)) return fail(MEB_ERR_NUMERIC, "non-finite input");
     std::vector<double> xfin(n1);
+    double mreach_mixed = -INFINITY;  // max reach at xfin, when the mixed path already computed it
     int status = MEB_OK;
     if (!(L > 0)) {
         // every ball is the point c_1
@@ -761,6 +839,11 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
         st.inner[1] = rr.inner;
         st.passes[1] = rr.passes;
         st.kkt[1] = rr.kkt;
+        st.pass_ms[1] = rr.pass_ms;
+        st.pass_bytes[1] = rr.pass_bytes;
+        st.pass_launches[1] = rr.launches;
+        st.mid_rows[1] = rr.sumk;
+        st.mid_rows_max[1] = rr.maxk;
         st.n_red = m;
         if (rr.status != 1) status = MEB_WARN_MAXITER;
         xfin = rr.x;
@@ -778,6 +861,11 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
         st.inner[0] = r1.inner;
         st.passes[0] = r1.passes;
         st.kkt[0] = r1.kkt;
+        st.pass_ms[0] = r1.pass_ms;
+        st.pass_bytes[0] = r1.pass_bytes;
+        st.pass_launches[0] = r1.launches;
+        st.mid_rows[0] = r1.sumk;
+        st.mid_rows_max[0] = r1.maxk;
         // ---- screening on the FP32 copy (FP64 arithmetic), tol_red in units of L
         const double ts = now_ms();
         std::vector<double> chat_s(d);  // shifted coordinates
@@ -802,6 +890,7 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
         xw[0] = r1.x[0];
         for (int k = 0; k < d; ++k) xw[1 + k] = c1[k] + r1.x[1 + k];
         double sigma_w = r1.sigma_end;
+        double mreach_final = INFINITY;
         std::vector<int64_t> keep_h;   // retained indices in device order
         std::vector<int64_t> keep_sorted;
         int rounds = 0;
@@ -828,6 +917,11 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
             st.inner[1] += r2.inner;
             st.passes[1] += r2.passes;
             st.kkt[1] = r2.kkt;
+            st.pass_ms[1] += r2.pass_ms;
+            st.pass_bytes[1] += r2.pass_bytes;
+            st.pass_launches[1] += r2.launches;
+            st.mid_rows[1] += r2.sumk;
+            st.mid_rows_max[1] = std::max(st.mid_rows_max[1], r2.maxk);
             if (r2.status != 1) status = MEB_WARN_MAXITER;
             xw = r2.x;
             sigma_w = r2.sigma_end;
@@ -840,6 +934,7 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
                           &nv, s));
             tc_total += now_ms() - tc;
             st.delta_max = mreach - xw[0];
+            mreach_final = mreach;
             if (nv == 0 || rounds >= o->max_reinsert) break;
             // new violators not yet retained
             std::vector<int64_t> vh(nv);
@@ -879,18 +974,22 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
         st.reinsert_rounds = rounds;
         st.n_red = n_red;
         xfin = xw;
+        mreach_mixed = mreach_final;
         if (U_out || V_out) {
             if (U_out) HIPCHK(launch_fill_f64(U_out, 0.0, m, s));
             if (V_out) HIPCHK(launch_fill_f64(V_out, 0.0, m * (int64_t)d, s));
             HIPCHK(launch_scatter_mult(w.U64, w.V64, w.keep, n_red, d, U_out, V_out, s));
         }
     }
-    // fix-up: the returned radius encloses every ball (FP64 check over all m)
-    double mreach;
-    int64_t am, nv;
-    const double tcf = now_ms();
-    CHK(run_check(C, R, m, d, dtype, 0.0, xfin.data() + 1, INFINITY, w.scan, &mreach, &am, nullptr, 0, &nv, s));
-    st.ms_phase[3] += now_ms() - tcf;
+    // fix-up: the returned radius encloses every ball (FP64 check over all m;
+    // the mixed path's last full check already holds it for this center)
+    double mreach = mreach_mixed;
+    if (!(mreach > -INFINITY)) {
+        int64_t am, nv;
+        const double tcf = now_ms();
+        CHK(run_check(C, R, m, d, dtype, 0.0, xfin.data() + 1, INFINITY, w.scan, &mreach, &am, nullptr, 0, &nv, s));
+        st.ms_phase[3] += now_ms() - tcf;
+    }
     st.rbar = xfin[0];
     st.delta_max = mreach - xfin[0];
     *r_out = std::max(xfin[0], mreach);

@@ -50,6 +50,10 @@ enum StateSlot : int {
     S_STALL,
     S_PSI,           // Psi at the current iterate (for reporting)
     S_VERBOSE,
+    S_BYTES,         // algorithmic bytes moved by the evaluation passes of this run
+    S_SUMK,          // rows of the rank-one Hessian contraction, summed over passes
+    S_MAXK,          // largest such row count of one pass
+    S_HSKIP,         // 1 if the contraction of the last pass was skipped
     S_NSCALAR = 48
 };
 
@@ -96,6 +100,7 @@ struct RecLayout {
     int dm;     // sum ||w+ - w||^2
     int rs;     // sum over non-polar of |t_i| + ||s_i||
     int ww;     // sum ||w_i||^2 of the multipliers in use
+    int bytes;  // algorithmic bytes read and written by this pass
     int ku;     // sum u of the updated multipliers (KKT)
     int kv;     // d: sum v of the updated multipliers (KKT)
     int kmax;   // 3 maxima: primal cone distance, dual cone distance, |complementarity|
@@ -113,6 +118,7 @@ struct RecLayout {
         r.dm = o; o += 1;
         r.rs = o; o += 1;
         r.ww = o; o += 1;
+        r.bytes = o; o += 1;
         r.ku = o; o += 1;
         r.kmax = o; o += 3;
         r.sv = o; o += d;
@@ -171,47 +177,63 @@ struct SyrkArgs {
     const void* U;
     int d;
     int dtype;
-    const double* state;
+    double* state;       // block 0 writes S_HSKIP
     StateLayout sl;
-    int use_next_sigma;  // unused (sigma is read from state after the pass)
-    const int32_t* mid_idx;
-    const double* mid_coef;
-    const int32_t* mid_cnt;
-    int nwaves;
-    int64_t bw;
-    double* out;         // ksplit x tiles x T x T partial blocks
+    const double* red;   // reduced record (its mid count)
+    RecLayout rl;
+    const int32_t* list_idx;   // compacted mid list (K entries)
+    const double* list_coef;
+    const int64_t* list_total; // K
+    double* out;         // ksplit x pairs x T x T partial blocks
     int ksplit;
     int tile;
     int ntile;           // tiles per dimension
+    double skip_k;       // in a line-search pass, skip when K exceeds this
 };
+
+// Concatenates the per-wave mid-list segments into one list (ascending wave
+// order): offsets by a single-block scan, then a copy.
+hipError_t launch_mid_compact(const int32_t* mid_cnt, int nwaves, int64_t bw, const int32_t* seg_idx,
+                              const double* seg_coef, int64_t* offs, int64_t* total, int32_t* out_idx,
+                              double* out_coef, const double* state, hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // Launchers (meb_kernels.hip).  All return hipError_t of the launch.
 // ----------------------------------------------------------------------------
-hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, hipStream_t s);
-hipError_t launch_reduce_records(const double* rec, int nrec, int len, double* out, hipStream_t s);
+// kind 0: evaluation; 1: evaluation + updated multipliers + KKT terms (both
+// regardless of the state's mode); 3: the solver's pass, which runs the
+// evaluation or the multiplier update (+ KKT + next evaluation) as the
+// state's mode says, and nothing when the run is done.
+hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, int kind, hipStream_t s);
+// Sums (maxima for the KKT maxima) of nrec records of len doubles, `stride`
+// doubles apart; the pass leaves one record per block at stride
+// waves_per_block * len.
+hipError_t launch_reduce_records(const double* rec, int nrec, int len, int64_t stride, double* out, hipStream_t s);
 hipError_t launch_syrk(const SyrkArgs& a, hipStream_t s);
-int syrk_ksplit(int d, int nwaves);
+int syrk_ksplit(int d);
 int syrk_tile();
-hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, const double* syrk_out,
-                          int ksplit, int tile, int ntile, int have_syrk, int* flag_host_mapped, hipStream_t s);
+hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag_host_mapped,
+                          hipStream_t s);
+hipError_t launch_assemble(double* state, StateLayout sl, RecLayout rl, const double* red, const double* syrk,
+                           int ksplit, int ntile, int have_syrk, hipStream_t s);
 hipError_t launch_eval_assemble(const double* state, StateLayout sl, RecLayout rl, const double* red,
                                 const double* syrk_out, int ksplit, int tile, int ntile, int have_syrk, double sigma,
                                 double tau, const double* x1, const double* xbar, double* out_g, double* out_H,
                                 hipStream_t s);
-hipError_t launch_feasible(const void* C, const void* R, int64_t m, int d, int dtype, const double* c, double r,
-                           double eps, double* blk_max, int64_t* blk_arg, int64_t* blk_cnt, int64_t* seg_idx,
-                           int nblocks, int64_t per_block, hipStream_t s);
-hipError_t launch_screen(const void* C, const void* R, int64_t m, int d, int dtype, const double* c, double r,
-                         double tol, double* slack, int64_t* blk_cnt, int64_t* seg_idx, int nblocks,
-                         int64_t per_block, hipStream_t s);
-hipError_t launch_compact(const int64_t* seg_idx, const int64_t* blk_cnt, int nblocks, int64_t per_block,
-                          int64_t* out, int64_t cap, int64_t* total_dev, hipStream_t s);
-hipError_t launch_max_reduce(const double* blk_max, const int64_t* blk_arg, int nblocks, double* out_max,
-                             int64_t* out_arg, hipStream_t s);
-hipError_t launch_prepare_f32(const double* C, const double* R, int64_t m, int d, const double* origin,
-                              float* C32, float* R32, double* blk_max, int nblocks, int64_t per_block,
-                              hipStream_t s);
+struct ScanCfg {
+    int G, vec, nl;
+    int64_t bw;  // rows per wave
+    int nwaves, blocks;
+};
+ScanCfg scan_config(int64_t m, int d, int num_cu);
+// mode 0: feasibility, 1: screening, 2: FP32 preparation (see meb_kernels.hip)
+hipError_t launch_scan(int mode, const void* C, const void* R, int64_t m, int d, int dtype, const double* x,
+                       double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c, double* wmax,
+                       int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s);
+hipError_t launch_scan_finalize(const int64_t* wcnt, const double* wmax, const int64_t* warg, int nw, int64_t* offs,
+                                int64_t* total, double* out_max, int64_t* out_arg, hipStream_t s);
+hipError_t launch_scan_copy(const int64_t* seg, const int64_t* wcnt, const int64_t* offs, int nw, int64_t bw,
+                            int64_t* out, int64_t cap, hipStream_t s);
 hipError_t launch_gather(const void* C, const void* R, const void* U, const void* V, int src_dtype,
                          const int64_t* idx, int64_t n, int d, double* C_out, double* R_out, double* U_out,
                          double* V_out, hipStream_t s);

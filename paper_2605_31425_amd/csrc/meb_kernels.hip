@@ -47,6 +47,24 @@ __device__ __forceinline__ double cross_group_sum(double v, int G) {
     return v;
 }
 
+template <typename T>
+__device__ __forceinline__ T wave_sum_t(T v) {
+    for (int o = WAVE >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max_t(T v) {
+    for (int o = WAVE >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T cross_group_sum_t(T v, int G) {
+    for (int o = G; o < WAVE; o <<= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = WAVE >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
     return v;
@@ -147,26 +165,44 @@ __device__ __forceinline__ BallProj<T> project(T t, T nn, T sig) {
 // Evaluation pass
 // ---------------------------------------------------------------------------
 
-template <typename T, int VEC, int NLMAX>
-__global__ __launch_bounds__(PASS_THREADS) void pass_kernel(PassArgs a, PassConfig cfg) {
+// Scalar accumulator slots of the evaluation pass (per lane, flushed to the
+// per-wave FP64 record).
+enum : int { A_SU = 0, A_Z1, A_NI, A_NM, A_SG, A_DM, A_RS, A_WW, A_KU, A_BYTES, A_N };
+
+template <typename T>
+struct FlushPeriod {
+    static constexpr int steps = 1 << 30;  // FP64 sums: no intermediate flush
+};
+template <>
+struct FlushPeriod<float> {
+    static constexpr int steps = 32;  // FP32 partial sums cover at most 32 balls per lane
+};
+
+// KIND 0: evaluation (Psi trials, gradient, Hessian parts) -- runs when the
+//         state's mode is PM_EVAL;
+// KIND 1: evaluation plus the updated multipliers and KKT terms at the same
+//         point (the single-evaluation entry point);
+// KIND 2: multiplier update at x_j, KKT terms, and the first evaluation of the
+//         next outer iteration -- runs when the mode is PM_MULT.
+// TRL: Armijo trials per lane (ceil(NT / G) rounded up to 1, 3 or 9).
+template <typename T, int VEC, int NLMAX, int KIND, int TRL>
+__device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& cfg) {
     extern __shared__ double lds[];
     const double* st = a.state;
-    const int mode = a.force_mode >= 0 ? a.force_mode : (int)st[S_MODE];
-    if (mode == PM_DONE) return;
     const int d = a.d;
     const int G = cfg.G;
     const int nl = cfg.nl;
     const StateLayout sl = a.sl;
     const RecLayout rl = a.rl;
 
-    const bool have_dir = (mode == PM_EVAL) && st[S_HAVE_DIR] != 0.0;
-    const bool is_mult = (mode == PM_MULT);
-    const bool want_kkt = is_mult || a.want_kkt;
+    const bool have_dir = (KIND != 2) && st[S_HAVE_DIR] != 0.0;
+    constexpr bool is_mult = (KIND == 2);
+    constexpr bool want_kkt = (KIND != 0);
 
-    // Current point y = x_base + dir and the direction, in LDS (FP64).
+    // the evaluation point y = x_base + dir and the direction, staged in LDS
     double* l_c = lds;
     double* l_dc = lds + d;
-    double* l_red = lds + 2 * d;  // PASS_THREADS doubles
+    double* l_red = lds + 2 * d;
     double part = 0.0;
     for (int k = threadIdx.x; k < d; k += PASS_THREADS) {
         double dk = have_dir ? st[sl.dir + 1 + k] : 0.0;
@@ -207,100 +243,178 @@ __global__ __launch_bounds__(PASS_THREADS) void pass_kernel(PassArgs a, PassConf
     const bool leader = (gl == 0);
     const int64_t wbeg = gw * cfg.bw;
     const int64_t wend = min(a.m, wbeg + cfg.bw);
+    const T es_bytes = (T)sizeof(T);
 
-    // per-lane accumulators (FP64)
-    double acc_su = 0, acc_z1 = 0, acc_ni = 0, acc_nm = 0, acc_sg = 0, acc_dm = 0, acc_rs = 0, acc_ww = 0, acc_ku = 0;
-    double mx_p = 0, mx_d = 0, mx_c = 0;
-    double tacc[NT];
+    // per-lane constants: the owned elements of y and of dir
+    int base[NLMAX];
+    bool own[NLMAX];
+    T cv[NLMAX][VEC], dv[NLMAX][VEC];
 #pragma unroll
-    for (int r = 0; r < NT; ++r) tacc[r] = 0.0;
-    double sv[NLMAX][VEC], sw[NLMAX][VEC], kv[NLMAX][VEC];
+    for (int j = 0; j < NLMAX; ++j) {
+        base[j] = (j * G + gl) * VEC;
+        own[j] = (j < nl) && (base[j] < d);
 #pragma unroll
-    for (int j = 0; j < NLMAX; ++j)
+        for (int q = 0; q < VEC; ++q) {
+            cv[j][q] = own[j] ? (T)l_c[base[j] + q] : T(0);
+            dv[j][q] = own[j] ? (T)l_dc[base[j] + q] : T(0);
+        }
+    }
+
+    // the wave's record doubles as the FP64 accumulator of the flushes
+    double* rec = a.rec + gw * rl.len;
+    for (int e = lane; e < rl.len; e += WAVE) rec[e] = 0.0;
+
+    T sacc[A_N];
+    T tacc[TRL];
+    T tam[TRL];  // 1 - eta of this lane's trials
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) sv[j][q] = sw[j][q] = kv[j][q] = 0.0;
+    for (int r = 0; r < TRL; ++r) {
+        const int l = r * G + gl;
+        tam[r] = (l < NT) ? T(1) - (T)a.etas[l] : T(1);
+    }
+    T vsv[NLMAX][VEC], vsw[NLMAX][VEC], vkv[NLMAX][VEC];
+    T mx_p = 0, mx_d = 0, mx_c = 0;
+    auto zero_acc = [&]() {
+#pragma unroll
+        for (int k = 0; k < A_N; ++k) sacc[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < TRL; ++k) tacc[k] = T(0);
+#pragma unroll
+        for (int j = 0; j < NLMAX; ++j)
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) vsv[j][q] = vsw[j][q] = vkv[j][q] = T(0);
+    };
+    auto flush = [&]() {
+        // scalars: wave sums; trials and vectors: sums across groups
+        T sred[A_N];
+#pragma unroll
+        for (int k = 0; k < A_N; ++k) sred[k] = wave_sum_t<T>(sacc[k]);
+        if (lane == 0) {
+            rec[rl.su] += (double)sred[A_SU];
+            rec[rl.z1] += (double)sred[A_Z1];
+            rec[rl.ni] += (double)sred[A_NI];
+            rec[rl.nm] += (double)sred[A_NM];
+            rec[rl.sg] += (double)sred[A_SG];
+            rec[rl.dm] += (double)sred[A_DM];
+            rec[rl.rs] += (double)sred[A_RS];
+            rec[rl.ww] += (double)sred[A_WW];
+            rec[rl.ku] += (double)sred[A_KU];
+            rec[rl.bytes] += (double)sred[A_BYTES];
+        }
+        if (have_dir) {
+#pragma unroll
+            for (int r = 0; r < TRL; ++r) {
+                const T v = cross_group_sum_t<T>(tacc[r], G);
+                const int l = r * G + lane;
+                if (lane < G && l < NT) rec[rl.trial + l] += (double)v;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NLMAX; ++j) {
+            if (j >= nl) break;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                const T a1 = cross_group_sum_t<T>(vsv[j][q], G);
+                const T a2 = cross_group_sum_t<T>(vsw[j][q], G);
+                T a3 = T(0);
+                if constexpr (want_kkt) a3 = cross_group_sum_t<T>(vkv[j][q], G);
+                if (lane < G && own[j]) {
+                    rec[rl.sv + base[j] + q] += (double)a1;
+                    rec[rl.sw + base[j] + q] += (double)a2;
+                    if constexpr (want_kkt) rec[rl.kv + base[j] + q] += (double)a3;
+                }
+            }
+        }
+        zero_acc();
+    };
+    zero_acc();
 
     int32_t mid_count = 0;
-    int32_t* mid_idx = a.mid_idx ? a.mid_idx + gw * cfg.bw : nullptr;
-    double* mid_coef = a.mid_idx ? a.mid_coef + gw * cfg.bw : nullptr;
+    int32_t* mid_idx = a.want_mid ? a.mid_idx + gw * cfg.bw : nullptr;
+    double* mid_coef = a.want_mid ? a.mid_coef + gw * cfg.bw : nullptr;
 
-    for (int64_t b0 = wbeg; b0 < wend; b0 += bpw) {
+    const int64_t chunk = (int64_t)bpw * FlushPeriod<T>::steps;
+    for (int64_t c0 = wbeg; c0 < wend; c0 += chunk) {
+    const int64_t c1 = min(wend, c0 + chunk);
+    for (int64_t b0 = c0; b0 < c1; b0 += bpw) {
         const int64_t i = b0 + gi;
         const bool active = i < wend;
         const T ri = (R && active) ? R[i] : T(0);
         const T ui = (U && active) ? U[i] : T(0);
         const bool hasv = V && (ui != T(0));
-        T e[NLMAX][VEC], vv[NLMAX][VEC], s[NLMAX][VEC];
+        T s[NLMAX][VEC], vv[NLMAX][VEC], e[NLMAX][VEC];
         T nn = 0, q = 0, ee = 0, es = 0;
 #pragma unroll
         for (int j = 0; j < NLMAX; ++j) {
-            const int base = (j * G + gl) * VEC;
-            const bool ok = active && (j < nl) && (base < d);
+            const bool ok = active && own[j];
             RowVec<T, VEC> cr, vr;
 #pragma unroll
             for (int qq = 0; qq < VEC; ++qq) cr.v[qq] = vr.v[qq] = T(0);
             if (ok) {
-                cr = load_vec<T, VEC>(C + i * d + base);
-                if (hasv) vr = load_vec<T, VEC>(V + i * d + base);
+                cr = load_vec<T, VEC>(C + i * d + base[j]);
+                if (hasv) vr = load_vec<T, VEC>(V + i * d + base[j]);
             }
 #pragma unroll
             for (int qq = 0; qq < VEC; ++qq) {
-                const T ck = ok ? (T)l_c[base + qq] : T(0);
-                e[j][qq] = ok ? cr.v[qq] - ck : T(0);
+                const T ek = ok ? cr.v[qq] - cv[j][qq] : T(0);
+                if constexpr (is_mult) e[j][qq] = ek;
                 vv[j][qq] = vr.v[qq];
-                s[j][qq] = e[j][qq] + vr.v[qq] * inv_a;
+                s[j][qq] = ek + vr.v[qq] * inv_a;
                 nn += s[j][qq] * s[j][qq];
-                if (have_dir) q += s[j][qq] * (ok ? (T)l_dc[base + qq] : T(0));
-                if (want_kkt) {
-                    ee += e[j][qq] * e[j][qq];
-                    es += e[j][qq] * s[j][qq];
+                if constexpr (KIND != 2) {
+                    if (have_dir) q += s[j][qq] * dv[j][qq];
+                }
+                if constexpr (want_kkt) {
+                    ee += ek * ek;
+                    es += ek * s[j][qq];
                 }
             }
         }
         nn = group_sum<T>(nn, G);
         if (have_dir) q = group_sum<T>(q, G);
-        if (want_kkt) {
+        if constexpr (want_kkt) {
             ee = group_sum<T>(ee, G);
             es = group_sum<T>(es, G);
         }
+        if (leader && active)
+            sacc[A_BYTES] += es_bytes * (T)(d + (R ? 1 : 0) + (U ? 1 : 0) + (hasv ? d : 0));
         const T t = ri - r1 + ui * inv_a;
         BallProj<T> pa = project<T>(t, nn, sig_a);
         if (!active) pa.cs = 1, pa.up = T(0), pa.gam = T(0), pa.Z = T(0);
 
-        // Quantities that the evaluation accumulates: point z, multipliers in use.
         T te = t, nne = nn, ue = ui;
         BallProj<T> pe = pa;
         T sig_e = sig_a;
 
-        if (want_kkt) {
+        if constexpr (want_kkt) {
             // updated multipliers w+ = sigma Pi(z) at y and the KKT terms there
             const T un = pa.up;
+            const bool wrow = Vo && (un != T(0) || a.dense_vout);
             if (leader && active) {
-                acc_ku += (double)un;
+                sacc[A_KU] += un;
                 const T tp = r1 - ri;
-                mx_p = fmax(mx_p, (double)cone_dist<T>(tp, tsqrt<T>(ee)));
-                mx_d = fmax(mx_d, (double)cone_dist<T>(un, pa.gam * pa.n));
-                mx_c = fmax(mx_c, fabs((double)(tp * un - pa.gam * es)));
+                mx_p = fmax(mx_p, cone_dist<T>(tp, tsqrt<T>(ee)));
+                mx_d = fmax(mx_d, cone_dist<T>(un, pa.gam * pa.n));
+                mx_c = fmax(mx_c, fabs(tp * un - pa.gam * es));
                 if (Uo) Uo[i] = un;
+                sacc[A_BYTES] += (Uo ? es_bytes : T(0)) + (wrow ? es_bytes * (T)d : T(0));
             }
 #pragma unroll
             for (int j = 0; j < NLMAX; ++j) {
-                const int base = (j * G + gl) * VEC;
-                const bool ok = active && (j < nl) && (base < d);
                 RowVec<T, VEC> vn;
 #pragma unroll
                 for (int qq = 0; qq < VEC; ++qq) {
                     vn.v[qq] = pa.gam * s[j][qq];
-                    kv[j][qq] += (double)vn.v[qq];
+                    vkv[j][qq] += vn.v[qq];
                 }
-                if (ok && Vo && (un != T(0) || a.dense_vout)) store_vec<T, VEC>(Vo + i * d + base, vn);
-                if (is_mult) {
-                    // the next subproblem uses w+ and sigma_{k+1}
+                if (active && own[j] && wrow) store_vec<T, VEC>(Vo + i * d + base[j], vn);
+                if constexpr (is_mult) {
 #pragma unroll
                     for (int qq = 0; qq < VEC; ++qq) vv[j][qq] = vn.v[qq];
                 }
             }
-            if (is_mult) {
+            if constexpr (is_mult) {
+                // the first evaluation of the next subproblem: w+ and sigma_{k+1}
                 ue = un;
                 sig_e = sig_b;
                 te = ri - r1 + un * inv_b;
@@ -318,58 +432,51 @@ __global__ __launch_bounds__(PASS_THREADS) void pass_kernel(PassArgs a, PassConf
             }
         }
 
-        // ---- evaluation accumulators at (y, multipliers ue/vv, sigma sig_e)
+        // ---- evaluation sums at (y, multipliers in use, sigma_e)
         if (leader && active) {
-            acc_su += (double)pe.up;
-            acc_z1 += (double)pe.Z;
-            const double du = (double)pe.up - (double)ue;
-            acc_dm += du * du;
-            acc_ww += (double)ue * (double)ue;
-            if (pe.cs != 1) acc_rs += fabs((double)te) + (double)pe.n;
-            if (pe.cs == 0) acc_ni += 1.0;
+            sacc[A_SU] += pe.up;
+            sacc[A_Z1] += pe.Z;
+            const T du = pe.up - ue;
+            sacc[A_DM] += du * du;
+            sacc[A_WW] += ue * ue;
+            if (pe.cs != 1) sacc[A_RS] += fabs(te) + pe.n;
+            if (pe.cs == 0) sacc[A_NI] += T(1);
             if (pe.cs == 2) {
-                acc_nm += 1.0;
-                acc_sg += (double)pe.gam;
+                sacc[A_NM] += T(1);
+                sacc[A_SG] += pe.gam;
             }
         }
-        const T inv_n = (pe.cs == 2) ? T(1) / pe.n : T(0);
+        // a polar ball with zero multipliers contributes nothing elementwise
+        const bool quiet = (pe.cs == 1) && (ue == T(0));
+        if (!quiet) {
+            const T inv_n = (pe.cs == 2) ? T(1) / pe.n : T(0);
+            T dmb = 0, wwb = 0;
 #pragma unroll
-        for (int j = 0; j < NLMAX; ++j)
+            for (int j = 0; j < NLMAX; ++j)
 #pragma unroll
-            for (int qq = 0; qq < VEC; ++qq) {
-                const double sk = (double)s[j][qq];
-                const double vk = (double)vv[j][qq];
-                const double vp = (double)(pe.gam * s[j][qq]);
-                sv[j][qq] += vp;
-                sw[j][qq] += (double)(s[j][qq] * inv_n);
-                acc_dm += (vp - vk) * (vp - vk);
-                acc_ww += vk * vk;
-                (void)sk;
-            }
-        // Armijo trials along the segment x_base + eta dir: lane gl takes
-        // trials gl, gl + G, ...
-        if (active) {
-#pragma unroll
-            for (int r = 0; r < NT; ++r) {
-                const int l = r * G + gl;
-                if (r * G >= NT) break;
-                if (l < NT) {
-                    T Zl;
-                    if (have_dir) {
-                        const T am = T(1) - (T)a.etas[l];
-                        const T tl = te + am * dirr;
-                        T n2 = nne + T(2) * am * q + am * am * dc2;
-                        n2 = n2 > T(0) ? n2 : T(0);
-                        Zl = project<T>(tl, n2, sig_e).Z;
-                    } else {
-                        Zl = pe.Z;
-                    }
-                    tacc[r] += (double)Zl;
+                for (int qq = 0; qq < VEC; ++qq) {
+                    const T vp = pe.gam * s[j][qq];
+                    const T dvk = vp - vv[j][qq];
+                    vsv[j][qq] += vp;
+                    vsw[j][qq] += s[j][qq] * inv_n;
+                    dmb += dvk * dvk;
+                    wwb += vv[j][qq] * vv[j][qq];
                 }
+            sacc[A_DM] += dmb;
+            sacc[A_WW] += wwb;
+        }
+        // Armijo trials along x_base + eta dir: lane gl takes trials gl, gl + G, ...
+        if (have_dir && active) {
+#pragma unroll
+            for (int r = 0; r < TRL; ++r) {
+                const T am = tam[r];
+                const T tl = te + am * dirr;
+                T n2 = nne + T(2) * am * q + am * am * dc2;
+                n2 = n2 > T(0) ? n2 : T(0);
+                if (r * G + gl < NT) tacc[r] += project<T>(tl, n2, sig_e).Z;
             }
         }
-        // mid list for the rank-one Hessian contraction:
-        // coef_i = -sigma t_i / (2 n_i^3) multiplies s_i s_i^T
+        // mid list of the rank-one Hessian part: coef_i = -sigma t_i / (2 n_i^3)
         if (a.want_mid) {
             const bool is_mid = active && pe.cs == 2;
             const unsigned long long bal = __ballot(is_mid && leader);
@@ -383,71 +490,54 @@ __global__ __launch_bounds__(PASS_THREADS) void pass_kernel(PassArgs a, PassConf
             mid_count += __popcll(bal);
         }
     }
-
-    // ---- wave-level reduction and the per-wave record
-    double* rec = a.rec + gw * rl.len;
-    acc_su = wave_sum(acc_su);
-    acc_z1 = wave_sum(acc_z1);
-    acc_ni = wave_sum(acc_ni);
-    acc_nm = wave_sum(acc_nm);
-    acc_sg = wave_sum(acc_sg);
-    acc_dm = wave_sum(acc_dm);
-    acc_rs = wave_sum(acc_rs);
-    acc_ww = wave_sum(acc_ww);
-    acc_ku = wave_sum(acc_ku);
-    mx_p = wave_max(mx_p);
-    mx_d = wave_max(mx_d);
-    mx_c = wave_max(mx_c);
-#pragma unroll
-    for (int r = 0; r < NT; ++r) tacc[r] = cross_group_sum(tacc[r], G);
-#pragma unroll
-    for (int j = 0; j < NLMAX; ++j)
-#pragma unroll
-        for (int qq = 0; qq < VEC; ++qq) {
-            sv[j][qq] = cross_group_sum(sv[j][qq], G);
-            sw[j][qq] = cross_group_sum(sw[j][qq], G);
-            kv[j][qq] = cross_group_sum(kv[j][qq], G);
-        }
+    flush();
+    }
+    const T mp = wave_max_t<T>(mx_p), md = wave_max_t<T>(mx_d), mc = wave_max_t<T>(mx_c);
     if (lane == 0) {
-        rec[rl.su] = acc_su;
-        rec[rl.z1] = acc_z1;
-        rec[rl.ni] = acc_ni;
-        rec[rl.nm] = acc_nm;
-        rec[rl.sg] = acc_sg;
-        rec[rl.dm] = acc_dm;
-        rec[rl.rs] = acc_rs;
-        rec[rl.ww] = acc_ww;
-        rec[rl.ku] = acc_ku;
-        rec[rl.kmax + 0] = mx_p;
-        rec[rl.kmax + 1] = mx_d;
-        rec[rl.kmax + 2] = mx_c;
+        rec[rl.kmax + 0] = (double)mp;
+        rec[rl.kmax + 1] = (double)md;
+        rec[rl.kmax + 2] = (double)mc;
         if (a.mid_cnt) a.mid_cnt[gw] = mid_count;
     }
-    if (lane < G) {
+    // combine the block's wave records into the first one, in wave order
+    __syncthreads();
+    double* r0 = a.rec + (int64_t)blockIdx.x * WPB * rl.len;
+    for (int e = threadIdx.x; e < rl.len; e += PASS_THREADS) {
+        const bool ismax = e >= rl.kmax && e < rl.kmax + 3;
+        double v = r0[e];
 #pragma unroll
-        for (int r = 0; r < NT; ++r) {
-            const int l = r * G + lane;
-            if (r * G >= NT) break;
-            if (l < NT) rec[rl.trial + l] = tacc[r];
+        for (int w = 1; w < WPB; ++w) {
+            const double x = r0[w * rl.len + e];
+            v = ismax ? fmax(v, x) : v + x;
         }
-#pragma unroll
-        for (int j = 0; j < NLMAX; ++j) {
-            const int base = (j * G + lane) * VEC;
-            if (j < nl && base < d) {
-#pragma unroll
-                for (int qq = 0; qq < VEC; ++qq) {
-                    rec[rl.sv + base + qq] = sv[j][qq];
-                    rec[rl.sw + base + qq] = sw[j][qq];
-                    rec[rl.kv + base + qq] = kv[j][qq];
-                }
-            }
-        }
+        r0[e] = v;
     }
+}
+
+// The solver's pass: evaluation or multiplier update, as the device state says.
+template <typename T, int VEC, int NLMAX, int TRL>
+__global__ __launch_bounds__(PASS_THREADS) void pass_kernel(PassArgs a, PassConfig cfg) {
+    const int mode = (int)a.state[S_MODE];
+    if (mode == PM_EVAL)
+        pass_body<T, VEC, NLMAX, 0, TRL>(a, cfg);
+    else if (mode == PM_MULT)
+        pass_body<T, VEC, NLMAX, 2, TRL>(a, cfg);
+}
+
+// A single evaluation (KIND 0) or evaluation with the updated multipliers and
+// KKT terms (KIND 1), independent of the state's mode.
+template <typename T, int VEC, int NLMAX, int KIND, int TRL>
+__global__ __launch_bounds__(PASS_THREADS) void pass_eval_kernel(PassArgs a, PassConfig cfg) {
+    pass_body<T, VEC, NLMAX, KIND, TRL>(a, cfg);
 }
 
 PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     PassConfig c;
     c.vec = (d % 2 == 0) ? 2 : 1;
+    // up to 4 loads (4 VEC elements) per lane when a ball has fewer than 64
+    // lanes: enough work per lane to amortize the cross-lane reduction of
+    // each ball, few enough to keep registers low.  Longer rows use 64 lanes
+    // and 8 or 16 loads.
     const int per_lane_target = 4;
     int need = (d + c.vec * per_lane_target - 1) / (c.vec * per_lane_target);
     int G = 1;
@@ -471,28 +561,49 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     return c;
 }
 
-template <typename T, int VEC, int NLMAX>
+// kind 0 / 1: pass_eval_kernel; kind 3: the solver's pass_kernel
+template <typename T, int VEC, int NLMAX, int KIND, int TRL>
 static hipError_t launch_pass_t(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
     size_t lds = sizeof(double) * (2 * (size_t)a.d + PASS_THREADS);
-    hipLaunchKernelGGL((pass_kernel<T, VEC, NLMAX>), dim3(cfg.blocks), dim3(PASS_THREADS), lds, s, a, cfg);
+    if constexpr (KIND == 3)
+        hipLaunchKernelGGL((pass_kernel<T, VEC, NLMAX, TRL>), dim3(cfg.blocks), dim3(PASS_THREADS), lds, s, a, cfg);
+    else
+        hipLaunchKernelGGL((pass_eval_kernel<T, VEC, NLMAX, KIND, TRL>), dim3(cfg.blocks), dim3(PASS_THREADS), lds, s,
+                           a, cfg);
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_pass_T(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
-    if (cfg.vec == 2) {
-        if (cfg.nlmax == 4) return launch_pass_t<T, 2, 4>(a, cfg, s);
-        if (cfg.nlmax == 8) return launch_pass_t<T, 2, 8>(a, cfg, s);
-        return launch_pass_t<T, 2, 16>(a, cfg, s);
-    }
-    if (cfg.nlmax == 4) return launch_pass_t<T, 1, 4>(a, cfg, s);
-    if (cfg.nlmax == 8) return launch_pass_t<T, 1, 8>(a, cfg, s);
-    return launch_pass_t<T, 1, 16>(a, cfg, s);
+// kernels that evaluate Armijo trials need one trial slot per G lanes
+template <typename T, int VEC, int KIND>
+static hipError_t launch_pass_small(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
+    if (cfg.G >= 16) return launch_pass_t<T, VEC, 4, KIND, 1>(a, cfg, s);
+    if (cfg.G >= 4) return launch_pass_t<T, VEC, 4, KIND, 3>(a, cfg, s);
+    return launch_pass_t<T, VEC, 4, KIND, 9>(a, cfg, s);
 }
 
-hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
-    if (a.dtype == 0) return launch_pass_T<double>(a, cfg, s);
-    return launch_pass_T<float>(a, cfg, s);
+template <typename T, int KIND>
+static hipError_t launch_pass_K(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
+    // nlmax 8 and 16 are used only with G = 64 lanes per ball
+    if (cfg.vec == 2) {
+        if (cfg.nlmax == 4) return launch_pass_small<T, 2, KIND>(a, cfg, s);
+        if (cfg.nlmax == 8) return launch_pass_t<T, 2, 8, KIND, 1>(a, cfg, s);
+        return launch_pass_t<T, 2, 16, KIND, 1>(a, cfg, s);
+    }
+    if (cfg.nlmax == 4) return launch_pass_small<T, 1, KIND>(a, cfg, s);
+    if (cfg.nlmax == 8) return launch_pass_t<T, 1, 8, KIND, 1>(a, cfg, s);
+    return launch_pass_t<T, 1, 16, KIND, 1>(a, cfg, s);
+}
+
+template <typename T>
+static hipError_t launch_pass_T(const PassArgs& a, const PassConfig& cfg, int kind, hipStream_t s) {
+    if (kind == 0) return launch_pass_K<T, 0>(a, cfg, s);
+    if (kind == 1) return launch_pass_K<T, 1>(a, cfg, s);
+    return launch_pass_K<T, 3>(a, cfg, s);
+}
+
+hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, int kind, hipStream_t s) {
+    if (a.dtype == 0) return launch_pass_T<double>(a, cfg, kind, s);
+    return launch_pass_T<float>(a, cfg, kind, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -503,20 +614,31 @@ hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, hipStream_t s) 
 
 constexpr int RED_SLICE = 32;
 
-__global__ __launch_bounds__(256) void reduce_stage1(const double* rec, int nrec, int len, int max_lo, int max_hi,
-                                                     double* part) {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    const int sl = blockIdx.y;
+// Stage 1: block (x, y) sums entries [64 x, 64 x + 64) over the records of
+// slice y; its four waves take records w = 4 k + wave, then combine in wave
+// order.  Records are `stride` doubles apart.
+__global__ __launch_bounds__(256) void reduce_stage1(const double* rec, int nrec, int len, int64_t stride, int max_lo,
+                                                     int max_hi, double* part) {
+    __shared__ double sp[4][64];
+    const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int sub = threadIdx.x >> 6;
     const int per = (nrec + gridDim.y - 1) / gridDim.y;
-    const int w0 = sl * per, w1 = min(nrec, w0 + per);
-    if (e >= len) return;
+    const int w0 = blockIdx.y * per, w1 = min(nrec, w0 + per);
     const bool ismax = (e >= max_lo && e < max_hi);
-    double acc = ismax ? 0.0 : 0.0;
-    for (int w = w0; w < w1; ++w) {
-        const double v = rec[(size_t)w * len + e];
-        acc = ismax ? fmax(acc, v) : acc + v;
+    double acc = 0.0;
+    if (e < len) {
+        for (int w = w0 + sub; w < w1; w += 4) {
+            const double v = rec[(int64_t)w * stride + e];
+            acc = ismax ? fmax(acc, v) : acc + v;
+        }
     }
-    part[(size_t)sl * len + e] = acc;
+    sp[sub][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (threadIdx.x < 64 && e < len) {
+        double v = sp[0][threadIdx.x];
+        for (int k = 1; k < 4; ++k) v = ismax ? fmax(v, sp[k][threadIdx.x]) : v + sp[k][threadIdx.x];
+        part[(size_t)blockIdx.y * len + e] = v;
+    }
 }
 
 __global__ __launch_bounds__(256) void reduce_stage2(const double* part, int nslice, int len, int max_lo, int max_hi,
@@ -532,16 +654,18 @@ __global__ __launch_bounds__(256) void reduce_stage2(const double* part, int nsl
     out[e] = acc;
 }
 
-hipError_t launch_reduce_records(const double* rec, int nrec, int len, double* out, hipStream_t s) {
+hipError_t launch_reduce_records(const double* rec, int nrec, int len, int64_t stride, double* out, hipStream_t s) {
     // `out` must have room for (RED_SLICE + 1) * len doubles: the slice
     // partials live after the result.  The three maxima sit at a fixed
     // offset ahead of the d-dependent vector parts of the record.
     const RecLayout rl = RecLayout::make(0);
     const int max_lo = rl.kmax, max_hi = rl.kmax + 3;
-    int nslice = nrec < RED_SLICE ? nrec : RED_SLICE;
+    int nslice = (nrec + 15) / 16;
+    if (nslice > RED_SLICE) nslice = RED_SLICE;
+    if (nslice < 1) nslice = 1;
     double* part = out + len;
-    dim3 g1((len + 255) / 256, nslice);
-    hipLaunchKernelGGL(reduce_stage1, g1, dim3(256), 0, s, rec, nrec, len, max_lo, max_hi, part);
+    dim3 g1((len + 63) / 64, nslice);
+    hipLaunchKernelGGL(reduce_stage1, g1, dim3(256), 0, s, rec, nrec, len, stride, max_lo, max_hi, part);
     hipLaunchKernelGGL(reduce_stage2, dim3((len + 255) / 256), dim3(256), 0, s, part, nslice, len, max_lo, max_hi,
                        out);
     return hipGetLastError();
@@ -555,92 +679,142 @@ hipError_t launch_reduce_records(const double* rec, int nrec, int len, double* o
 // ---------------------------------------------------------------------------
 
 constexpr int SYRK_T = 32;
-constexpr int SYRK_KB = 32;  // mid balls staged per step
+constexpr int SYRK_KB = 32;     // mid balls staged per step
+constexpr int SYRK_KSPLIT = 8;  // blocks along the mid list per tile pair
 
 int syrk_tile() { return SYRK_T; }
 
-int syrk_ksplit(int d, int nwaves) {
-    int nt = (d + SYRK_T - 1) / SYRK_T;
-    int pairs = nt * (nt + 1) / 2;
-    int ks = 512 / pairs;
-    if (ks < 1) ks = 1;
-    if (ks > nwaves) ks = nwaves;
-    return ks;
+int syrk_ksplit(int d) {
+    (void)d;
+    return SYRK_KSPLIT;
 }
 
+// Per-wave mid counts -> exclusive offsets and total, then the copy into one
+// list.  Skipped when the run is done.
+__global__ __launch_bounds__(1024) void mid_scan_kernel(const int32_t* cnt, int nw, int64_t* offs, int64_t* total,
+                                                        const double* st) {
+    __shared__ int64_t sc[1024];
+    if ((int)st[S_MODE] == PM_DONE) return;
+    const int t = threadIdx.x;
+    const int per = (nw + 1023) / 1024;
+    const int w0 = t * per, w1 = min(nw, w0 + per);
+    int64_t c = 0;
+    for (int w = w0; w < w1; ++w) c += cnt[w];
+    sc[t] = c;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t v = t >= o ? sc[t - o] : 0;
+        __syncthreads();
+        sc[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t > 0 ? sc[t - 1] : 0;
+    for (int w = w0; w < w1; ++w) {
+        offs[w] = run;
+        run += cnt[w];
+    }
+    if (t == 1023) *total = sc[1023];
+}
+
+__global__ __launch_bounds__(256) void mid_copy_kernel(const int32_t* cnt, int nw, int64_t bw, const int32_t* si,
+                                                       const double* sc, const int64_t* offs, int32_t* oi,
+                                                       double* oc, const double* st) {
+    if ((int)st[S_MODE] == PM_DONE) return;
+    const int lane = lane_id();
+    const int64_t w = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (w >= nw) return;
+    const int64_t n = cnt[w], off = offs[w];
+    for (int64_t k = lane; k < n; k += WAVE) {
+        oi[off + k] = si[w * bw + k];
+        oc[off + k] = sc[w * bw + k];
+    }
+}
+
+hipError_t launch_mid_compact(const int32_t* mid_cnt, int nwaves, int64_t bw, const int32_t* seg_idx,
+                              const double* seg_coef, int64_t* offs, int64_t* total, int32_t* out_idx,
+                              double* out_coef, const double* state, hipStream_t s) {
+    hipLaunchKernelGGL(mid_scan_kernel, dim3(1), dim3(1024), 0, s, mid_cnt, nwaves, offs, total, state);
+    hipLaunchKernelGGL(mid_copy_kernel, dim3((nwaves + 3) / 4), dim3(256), 0, s, mid_cnt, nwaves, bw, seg_idx,
+                       seg_coef, offs, out_idx, out_coef, state);
+    return hipGetLastError();
+}
+
+// Rank-one Hessian part  sum_{i in mid} coef_i s_i s_i^T  with FP64
+// accumulation over the compacted mid list, tiled T x T over the upper
+// triangle of the d x d block; blockIdx.y splits the list evenly.  s_i is
+// recomputed from C and V exactly as the pass computed it.  In a line-search
+// pass with more than skip_k rows the contraction is skipped (block 0 sets
+// S_HSKIP) and the control step re-evaluates if it needs this H.
 template <typename T>
 __global__ __launch_bounds__(256) void syrk_kernel(SyrkArgs a) {
     __shared__ double sI[SYRK_KB][SYRK_T + 1];
     __shared__ double sJ[SYRK_KB][SYRK_T + 1];
     __shared__ double cf[SYRK_KB];
     __shared__ int32_t ix[SYRK_KB];
-    const double* st = a.state;
+    double* st = a.state;
     const int mode = (int)st[S_MODE];
     if (mode == PM_DONE) return;
     const int d = a.d;
     const StateLayout sl = a.sl;
     const bool have_dir = (mode == PM_EVAL) && st[S_HAVE_DIR] != 0.0;
+    const int64_t K = *a.list_total;
+    const bool skip = have_dir && (double)K > a.skip_k;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) st[S_HSKIP] = skip ? 1.0 : 0.0;
+    if (skip) return;
     const double sig = (mode == PM_MULT) ? st[S_SIGMA_NEXT] : st[S_SIGMA];
     const T inv = (T)(1.0 / sig);
-    // tile pair from blockIdx.x (upper triangle, row-major)
     int p = blockIdx.x, I = 0;
     while (p >= a.ntile - I) {
         p -= a.ntile - I;
         ++I;
     }
     const int J = I + p;
-    const int ks = blockIdx.y;
-    const int per = (a.nwaves + a.ksplit - 1) / a.ksplit;
-    const int w0 = ks * per, w1 = min(a.nwaves, w0 + per);
+    const int64_t per = (K + a.ksplit - 1) / a.ksplit;
+    const int64_t k0 = (int64_t)blockIdx.y * per, k1 = min(K, k0 + per);
     const T* C = static_cast<const T*>(a.C);
     const T* V = static_cast<const T*>(a.V);
     const T* U = static_cast<const T*>(a.U);
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     double acc[2][2] = {{0, 0}, {0, 0}};
-    for (int w = w0; w < w1; ++w) {
-        const int cnt = a.mid_cnt[w];
-        const int32_t* idx = a.mid_idx + (int64_t)w * a.bw;
-        const double* coef = a.mid_coef + (int64_t)w * a.bw;
-        for (int k0 = 0; k0 < cnt; k0 += SYRK_KB) {
-            const int nk = min(SYRK_KB, cnt - k0);
-            __syncthreads();
-            if (threadIdx.x < SYRK_KB) {
-                ix[threadIdx.x] = threadIdx.x < nk ? idx[k0 + threadIdx.x] : 0;
-                cf[threadIdx.x] = threadIdx.x < nk ? coef[k0 + threadIdx.x] : 0.0;
+    for (int64_t kb = k0; kb < k1; kb += SYRK_KB) {
+        const int nk = (int)min((int64_t)SYRK_KB, k1 - kb);
+        __syncthreads();
+        if (threadIdx.x < SYRK_KB) {
+            ix[threadIdx.x] = threadIdx.x < nk ? a.list_idx[kb + threadIdx.x] : 0;
+            cf[threadIdx.x] = threadIdx.x < nk ? a.list_coef[kb + threadIdx.x] : 0.0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < SYRK_KB * SYRK_T * 2; e += 256) {
+            const int which = e / (SYRK_KB * SYRK_T);
+            const int r = (e / SYRK_T) % SYRK_KB;
+            const int cc = e % SYRK_T;
+            const int col = (which ? J : I) * SYRK_T + cc;
+            double v = 0.0;
+            if (r < nk && col < d) {
+                const int64_t i = ix[r];
+                const T ck = (T)(st[sl.xb + 1 + col] + (have_dir ? st[sl.dir + 1 + col] : 0.0));
+                const T ek = C[i * d + col] - ck;
+                const T vk = (V && U && U[i] != T(0)) ? V[i * d + col] : T(0);
+                v = (double)(ek + vk * inv);
             }
-            __syncthreads();
-            for (int e = threadIdx.x; e < SYRK_KB * SYRK_T * 2; e += 256) {
-                const int which = e / (SYRK_KB * SYRK_T);
-                const int r = (e / SYRK_T) % SYRK_KB;
-                const int cc = e % SYRK_T;
-                const int col = (which ? J : I) * SYRK_T + cc;
-                double v = 0.0;
-                if (r < nk && col < d) {
-                    const int64_t i = ix[r];
-                    const T ck = (T)(st[sl.xb + 1 + col] + (have_dir ? st[sl.dir + 1 + col] : 0.0));
-                    const T ek = C[i * d + col] - ck;
-                    const T vk = (V && U && U[i] != T(0)) ? V[i * d + col] : T(0);
-                    v = (double)(ek + vk * inv);
-                }
-                if (which)
-                    sJ[r][cc] = v;
-                else
-                    sI[r][cc] = v;
-            }
-            __syncthreads();
-            for (int r = 0; r < nk; ++r) {
-                const double c = cf[r];
-                const double a0 = sI[r][ty], a1 = sI[r][ty + 16];
-                const double b0 = sJ[r][tx] * c, b1 = sJ[r][tx + 16] * c;
-                acc[0][0] += a0 * b0;
-                acc[0][1] += a0 * b1;
-                acc[1][0] += a1 * b0;
-                acc[1][1] += a1 * b1;
-            }
+            if (which)
+                sJ[r][cc] = v;
+            else
+                sI[r][cc] = v;
+        }
+        __syncthreads();
+        for (int r = 0; r < nk; ++r) {
+            const double c = cf[r];
+            const double a0 = sI[r][ty], a1 = sI[r][ty + 16];
+            const double b0 = sJ[r][tx] * c, b1 = sJ[r][tx + 16] * c;
+            acc[0][0] += a0 * b0;
+            acc[0][1] += a0 * b1;
+            acc[1][0] += a1 * b0;
+            acc[1][1] += a1 * b1;
         }
     }
     const int npairs = gridDim.x;
-    double* out = a.out + ((size_t)ks * npairs + blockIdx.x) * SYRK_T * SYRK_T;
+    double* out = a.out + ((size_t)blockIdx.y * npairs + blockIdx.x) * SYRK_T * SYRK_T;
     out[ty * SYRK_T + tx] = acc[0][0];
     out[ty * SYRK_T + tx + 16] = acc[0][1];
     out[(ty + 16) * SYRK_T + tx] = acc[1][0];
@@ -702,65 +876,245 @@ __device__ void assemble_H(int d, const RecLayout& rl, const double* red, const 
     }
 }
 
+// Parallel assembly of H into the state (one thread per entry).  Runs after
+// the contraction and before the control step; it is a no-op when the run is
+// done.  The control step reads H only when it takes a Newton step.
+__global__ __launch_bounds__(256) void assemble_kernel(double* st, StateLayout sl, RecLayout rl, const double* red,
+                                                       const double* syrk, int ksplit, int ntile, int have_syrk) {
+    const int mode = (int)st[S_MODE];
+    if (mode == PM_DONE) return;
+    if (have_syrk && st[S_HSKIP] != 0.0) return;
+    const double sigma = (mode == PM_MULT) ? st[S_SIGMA_NEXT] : st[S_SIGMA];
+    const double tau = st[S_TAU];
+    const int d = sl.n1 - 1, n1 = sl.n1;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n1 * n1) return;
+    const int a = e / n1, b = e % n1;
+    const double base = tau / sigma + sigma * red[rl.ni];
+    double v;
+    if (a == 0 && b == 0) {
+        v = base + 0.5 * sigma * red[rl.nm];
+    } else if (a == 0 || b == 0) {
+        v = 0.5 * sigma * red[rl.sw + (a == 0 ? b : a) - 1];
+    } else {
+        const int k = a - 1, l = b - 1;
+        v = (k == l) ? base + red[rl.sg] : 0.0;
+        if (have_syrk) {
+            int kk = k, ll = l;
+            if (kk / SYRK_T > ll / SYRK_T) {
+                const int t = kk;
+                kk = ll;
+                ll = t;
+            }
+            const int I = kk / SYRK_T, J = ll / SYRK_T;
+            const int npairs = ntile * (ntile + 1) / 2;
+            const int pidx = I * ntile - I * (I - 1) / 2 + (J - I);
+            const int ia = kk % SYRK_T, ib = ll % SYRK_T;
+            double sacc = 0.0;
+            for (int ks = 0; ks < ksplit; ++ks)
+                sacc += syrk[((size_t)ks * npairs + pidx) * SYRK_T * SYRK_T + ia * SYRK_T + ib];
+            v += sacc;
+        }
+    }
+    st[sl.H + e] = v;
+}
+
+hipError_t launch_assemble(double* state, StateLayout sl, RecLayout rl, const double* red, const double* syrk,
+                           int ksplit, int ntile, int have_syrk, hipStream_t s) {
+    const int n = sl.n1 * sl.n1;
+    hipLaunchKernelGGL(assemble_kernel, dim3((n + 255) / 256), dim3(256), 0, s, state, sl, rl, red, syrk, ksplit,
+                       ntile, have_syrk);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Cholesky solve of H y = b in one workgroup (FP64).  The matrix is held in
 // LDS when it fits (n <= 143 on gfx950), otherwise it is factorized in
 // place in global memory.
 // ---------------------------------------------------------------------------
 
-template <bool IN_LDS>
-__device__ int chol_solve_block(int n, double* A, double* b, double* lds_mat, double* lds_vec) {
-    double* M = IN_LDS ? lds_mat : A;
-    if (IN_LDS) {
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] = A[e];
-    }
-    for (int e = threadIdx.x; e < n; e += blockDim.x) lds_vec[e] = b[e];
+// Cholesky factorization M = L L^T in place (lower triangle, row-major n x n,
+// M in LDS or global memory), blocked right-looking with panels of CB
+// columns: wave 0 factors the CB x CB diagonal block (lanes own rows, no
+// block barrier), all threads then solve the panel below it row by row, and
+// update the trailing lower triangle in a 2-D thread layout.  Three block
+// barriers per panel instead of two per column.  rdiag receives 1 / L_jj.
+// Then the two triangular solves for b by wave 0 alone: lane l owns rows l,
+// l + 64, ...; each step broadcasts the new unknown with a lane shuffle.
+// Returns -1 if a pivot is not positive.
+constexpr int CB = 16;
+
+template <int MAXR>
+__device__ int chol_solve_block(int n, double* M, double* b, double* rdiag) {
     __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    if (tid == 0) bad = 0;
     __syncthreads();
-    // right-looking factorization, lower triangle: M = L L^T
+    for (int j0 = 0; j0 < n; j0 += CB) {
+        const int nb = min(CB, n - j0);
+        // (a) diagonal block by wave 0: lane r < nb owns row j0 + r
+        if (tid < WAVE) {
+            const int r = tid;
+            for (int c = 0; c < nb; ++c) {
+                const int jc = j0 + c;
+                double ajj = M[jc * n + jc];
+                // every lane reads the pivot after the owner's last update:
+                // the wave executes in lockstep, LDS/global order within a wave
+                const bool ok = ajj > 0.0;
+                if (!ok) {
+                    if (r == 0) bad = 1;
+                    break;
+                }
+                const double ljj = sqrt(ajj);
+                const double rl = 1.0 / ljj;
+                if (r == c) {
+                    M[jc * n + jc] = ljj;
+                    rdiag[jc] = rl;
+                }
+                if (r > c && r < nb) M[(j0 + r) * n + jc] *= rl;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (r > c && r < nb) {
+                    const double lrc = M[(j0 + r) * n + jc];
+                    for (int k = c + 1; k <= r; ++k) M[(j0 + r) * n + j0 + k] -= lrc * M[(j0 + k) * n + jc];
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+        }
+        __syncthreads();
+        if (bad) return -1;
+        // (b) panel below: row i solves L_ib L_bb^T = A_ib (forward in the block)
+        for (int i = j0 + nb + tid; i < n; i += nth) {
+            for (int c = 0; c < nb; ++c) {
+                double v = M[i * n + j0 + c];
+                for (int k = 0; k < c; ++k) v -= M[i * n + j0 + k] * M[(j0 + c) * n + j0 + k];
+                M[i * n + j0 + c] = v * rdiag[j0 + c];
+            }
+        }
+        __syncthreads();
+        // (c) trailing lower triangle: A_ik -= sum_c L_ic L_kc
+        const int rem = n - j0 - nb;
+        if (rem > 0) {
+            const int tx = tid & 31, ty = tid >> 5, nty = nth >> 5;
+            for (int ii = ty; ii < rem; ii += nty) {
+                const int i = j0 + nb + ii;
+                double li[CB];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) li[c] = c < nb ? M[i * n + j0 + c] : 0.0;
+                for (int kk = tx; kk <= ii; kk += 32) {
+                    const int k = j0 + nb + kk;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int c = 0; c < CB; ++c)
+                        if (c < nb) acc += li[c] * M[k * n + j0 + c];
+                    M[i * n + k] -= acc;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid < WAVE) {
+        const int lane = tid;
+        double bv[MAXR];
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) {
+            const int row = lane + r * WAVE;
+            bv[r] = row < n ? b[row] : 0.0;
+        }
+        // forward: L y = b
+        for (int j = 0; j < n; ++j) {
+            const int owner = j & (WAVE - 1), slot = j / WAVE;
+            double mine = 0.0;
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r)
+                if (r == slot) mine = bv[r];
+            const double yj = __shfl(mine * rdiag[j], owner, WAVE);
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                const int row = lane + r * WAVE;
+                if (row == j) bv[r] = yj;
+                else if (row > j && row < n) bv[r] -= M[row * n + j] * yj;
+            }
+        }
+        // backward: L^T x = y
+        for (int i = n - 1; i >= 0; --i) {
+            const int owner = i & (WAVE - 1), slot = i / WAVE;
+            double mine = 0.0;
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r)
+                if (r == slot) mine = bv[r];
+            const double xi = __shfl(mine * rdiag[i], owner, WAVE);
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                const int row = lane + r * WAVE;
+                if (row == i) bv[r] = xi;
+                else if (row < i) bv[r] -= M[i * n + row] * xi;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) {
+            const int row = lane + r * WAVE;
+            if (row < n) b[row] = bv[r];
+        }
+    }
+    __syncthreads();
+    return 0;
+}
+
+// Solve with n above the register budget of the wave-level solves: the
+// triangular solves by the whole block, column oriented.
+__device__ int chol_solve_block_large(int n, double* M, double* b, double* vec) {
+    __shared__ int bad;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int tx = tid & 31, ty = tid >> 5, nty = nth >> 5;
+    if (tid == 0) bad = 0;
+    for (int e = tid; e < n; e += nth) vec[e] = b[e];
+    __syncthreads();
     for (int j = 0; j < n; ++j) {
         const double ajj = M[j * n + j];
         if (!(ajj > 0.0)) {
-            if (threadIdx.x == 0) bad = 1;
+            if (tid == 0) bad = 1;
             __syncthreads();
             break;
         }
         const double ljj = sqrt(ajj);
+        for (int i = j + 1 + tid; i < n; i += nth) M[i * n + j] /= ljj;
         __syncthreads();
-        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) M[i * n + j] /= ljj;
-        __syncthreads();
-        if (threadIdx.x == 0) M[j * n + j] = ljj;
-        // trailing update of the lower triangle
-        const int rem = n - j - 1;
-        for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-            const int ii = j + 1 + e / rem, kk = j + 1 + e % rem;
-            if (kk <= ii) M[ii * n + kk] -= M[ii * n + j] * M[kk * n + j];
+        if (tid == 0) M[j * n + j] = ljj;
+        for (int ii = j + 1 + ty; ii < n; ii += nty) {
+            const double lij = M[ii * n + j];
+            for (int kk = j + 1 + tx; kk <= ii; kk += 32) M[ii * n + kk] -= lij * M[kk * n + j];
         }
         __syncthreads();
     }
     if (bad) return -1;
-    // forward: L y = b (column oriented)
     for (int j = 0; j < n; ++j) {
+        const double yj = vec[j] / M[j * n + j];
         __syncthreads();
-        const double yj = lds_vec[j] / M[j * n + j];
+        if (tid == 0) vec[j] = yj;
+        for (int i = j + 1 + tid; i < n; i += nth) vec[i] -= M[i * n + j] * yj;
         __syncthreads();
-        if (threadIdx.x == 0) lds_vec[j] = yj;
-        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) lds_vec[i] -= M[i * n + j] * yj;
     }
-    __syncthreads();
-    // backward: L^T x = y (row i of L^T is column i of L)
     for (int i = n - 1; i >= 0; --i) {
+        const double xi = vec[i] / M[i * n + i];
         __syncthreads();
-        const double xi = lds_vec[i] / M[i * n + i];
+        if (tid == 0) vec[i] = xi;
+        for (int k = tid; k < i; k += nth) vec[k] -= M[i * n + k] * xi;
         __syncthreads();
-        if (threadIdx.x == 0) lds_vec[i] = xi;
-        for (int k = threadIdx.x; k < i; k += blockDim.x) lds_vec[k] -= M[i * n + k] * xi;
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n; e += blockDim.x) b[e] = lds_vec[e];
+    for (int e = tid; e < n; e += nth) b[e] = vec[e];
     __syncthreads();
     return 0;
+}
+
+// n <= 192: wave-level triangular solves with 3 rows per lane
+constexpr int CHOL_WAVE_MAX_N = 192;
+
+// vec: scratch of at least n doubles (LDS preferred)
+__device__ int chol_solve_any(int n, double* M, double* b, double* vec) {
+    if (n <= CHOL_WAVE_MAX_N) return chol_solve_block<3>(n, M, b, vec);
+    return chol_solve_block_large(n, M, b, vec);
 }
 
 // Kernels that take more than 64 KiB of dynamic LDS opt in once per size.
@@ -777,10 +1131,14 @@ constexpr int CTRL_CHOL_LDS_MAX_N = 136;
 __global__ __launch_bounds__(CTRL_THREADS) void chol_solve_kernel(int n, double* A, double* b, int* info) {
     extern __shared__ double sm[];
     int rc;
-    if (n <= CHOL_LDS_MAX_N)
-        rc = chol_solve_block<true>(n, A, b, sm + n, sm);
-    else
-        rc = chol_solve_block<false>(n, A, b, nullptr, sm);
+    if (n <= CHOL_LDS_MAX_N) {
+        double* M = sm + n;
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] = A[e];
+        __syncthreads();
+        rc = chol_solve_any(n, M, b, sm);
+    } else {
+        rc = chol_solve_any(n, A, b, sm);
+    }
     if (threadIdx.x == 0) *info = rc;
 }
 
@@ -813,8 +1171,7 @@ __device__ double block_sum(double v, double* scratch) {
 }
 
 __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, StateLayout sl, RecLayout rl,
-                                                               const double* red, const double* syrk, int ksplit,
-                                                               int ntile, int have_syrk, int* flag) {
+                                                               const double* red, int* flag) {
     extern __shared__ double sm[];
     double* scratch = sm;                                        // max(CTRL_THREADS, n1)
     double* lmat = sm + (CTRL_THREADS > sl.n1 ? CTRL_THREADS : sl.n1);  // Cholesky matrix when it fits
@@ -836,7 +1193,15 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
     if (threadIdx.x == 0) s_next = 0;
     __syncthreads();
 
-    if (threadIdx.x == 0) st[S_NPASS] += 1.0;
+    if (threadIdx.x == 0) {
+        st[S_NPASS] += 1.0;
+        st[S_BYTES] += red[rl.bytes];
+        st[S_SUMK] += red[rl.nm];
+        st[S_MAXK] = fmax(st[S_MAXK], red[rl.nm]);
+        if (st[S_VERBOSE] >= 2.0)
+            printf("[meb] pass %d mode %d K %.0f NI %.0f have_dir %d\n", (int)st[S_NPASS], mode, red[rl.nm],
+                   red[rl.ni], (int)st[S_HAVE_DIR]);
+    }
 
     if (mode == PM_MULT) {
         // KKT_max at x_j with the updated multipliers (Section 5), lengths / L
@@ -877,7 +1242,9 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
         }
         __syncthreads();
         // auxiliary update (alpha, beta) <- (alpha, beta) - sigma_k g^{k+1}  (Algorithm 1)
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) ab[k] -= sigma * gb[k];
+        // in units normalized by L the update reads ab -= (sigma L) g; in raw
+        // units that is ab -= sigma L^2 g
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) ab[k] -= sigma * L * L * gb[k];
         __syncthreads();
         if (s_next) {
             if (threadIdx.x == 0 && flag) *flag = 1;
@@ -923,7 +1290,13 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
                     break;
                 }
             }
-            if (acc == 0) {
+            if (acc == 0 && st[S_HSKIP] != 0.0) {
+                // full step, but its Hessian contraction was skipped:
+                // move there and evaluate again
+                s_next = 2;
+                s_eta = 1.0;
+                st[S_HAVE_DIR] = 0.0;
+            } else if (acc == 0) {
                 s_next = 0;  // full step: record is at x_base + dir
                 st[S_PSI] = psi0;
             } else {
@@ -999,35 +1372,24 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
         if (threadIdx.x == 0 && flag) *flag = 1;
         return;
     }
-    // Newton direction: H dir = -g
+    // Newton direction: H dir = -g, H assembled by assemble_kernel
+    for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = -gb[k];
+    int rc;
     if (n1 <= CTRL_CHOL_LDS_MAX_N) {
-        assemble_H(d, rl, red, syrk, ksplit, ntile, have_syrk, sgm, tau, lmat);
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = -gb[k];
+        for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) lmat[e] = H[e];
         __syncthreads();
-        double* vec = lmat + n1 * n1;
-        // factorize from LDS directly
-        int rc = chol_solve_block<false>(n1, lmat, dir, nullptr, vec);
-        if (rc != 0) {
-            if (threadIdx.x == 0) {
-                st[S_STATUS] = -1.0;
-                st[S_MODE] = (double)PM_DONE;
-                if (flag) *flag = 1;
-            }
-            return;
-        }
+        rc = chol_solve_any(n1, lmat, dir, scratch);
     } else {
-        assemble_H(d, rl, red, syrk, ksplit, ntile, have_syrk, sgm, tau, H);
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = -gb[k];
         __syncthreads();
-        int rc = chol_solve_block<false>(n1, H, dir, nullptr, scratch);
-        if (rc != 0) {
-            if (threadIdx.x == 0) {
-                st[S_STATUS] = -1.0;
-                st[S_MODE] = (double)PM_DONE;
-                if (flag) *flag = 1;
-            }
-            return;
+        rc = chol_solve_any(n1, H, dir, scratch);
+    }
+    if (rc != 0) {
+        if (threadIdx.x == 0) {
+            st[S_STATUS] = -1.0;
+            st[S_MODE] = (double)PM_DONE;
+            if (flag) *flag = 1;
         }
+        return;
     }
     double pgd = 0.0;
     for (int k = threadIdx.x; k < n1; k += blockDim.x) pgd += gb[k] * dir[k];
@@ -1041,16 +1403,13 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
     }
 }
 
-hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, const double* syrk_out,
-                          int ksplit, int tile, int ntile, int have_syrk, int* flag, hipStream_t s) {
-    (void)tile;
+hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag, hipStream_t s) {
     const int n1 = sl.n1;
     size_t lds = sizeof(double) * (size_t)(CTRL_THREADS > n1 ? CTRL_THREADS : n1);
     if (n1 <= CTRL_CHOL_LDS_MAX_N) lds += sizeof(double) * (size_t)(n1 * n1 + n1);
     hipError_t ea = ensure_dynamic_lds((const void*)control_kernel, lds);
     if (ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(control_kernel, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, rl, red, syrk_out, ksplit,
-                       ntile, have_syrk, flag);
+    hipLaunchKernelGGL(control_kernel, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, rl, red, flag);
     return hipGetLastError();
 }
 
@@ -1083,85 +1442,97 @@ hipError_t launch_eval_assemble(const double* state, StateLayout sl, RecLayout r
 }
 
 // ---------------------------------------------------------------------------
-// Feasibility check and screening scans (FP64 arithmetic).  One wave per
-// row for simplicity of the exact distance; each block covers a contiguous
-// range and writes its local violator / keep list in ascending order into
-// its own segment, so the final lists are deterministic.
+// Streaming scans over all balls in FP64 arithmetic: the feasibility check
+// (reach_i = r_i + ||c - c_i|| against r), the screening slack, and the
+// FP32 preparation.  G lanes per row as in the evaluation pass; each wave
+// streams a contiguous range and writes its hits, in ascending order, into
+// its own segment; a single-block scan then computes segment offsets and the
+// global maximum, and a copy kernel concatenates the segments.
 // ---------------------------------------------------------------------------
 
 constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_WPB = SCAN_THREADS / WAVE;
 
-template <typename T>
-__device__ __forceinline__ double row_dist(const T* row, const double* c, int d, int G, int gl) {
-    double acc = 0.0;
-    for (int k = gl; k < d; k += G) {
-        const double e = c[k] - (double)row[k];
-        acc += e * e;
-    }
-    return sqrt(group_sum<double>(acc, G));
+ScanCfg scan_config(int64_t m, int d, int num_cu) {
+    ScanCfg c;
+    c.vec = (d % 2 == 0) ? 2 : 1;
+    int need = (d + c.vec * 4 - 1) / (c.vec * 4);
+    int G = 1;
+    while (G < need && G < 64) G <<= 1;
+    c.G = G;
+    c.nl = (d + G * c.vec - 1) / (G * c.vec);
+    const int bpw = WAVE / G;
+    int64_t steps = (m + bpw - 1) / bpw;
+    int64_t maxw = (int64_t)num_cu * 8;
+    int64_t w = steps < maxw ? steps : maxw;
+    if (w < 1) w = 1;
+    c.bw = ((steps + w - 1) / w) * bpw;
+    int64_t waves = (m + c.bw - 1) / c.bw;
+    c.blocks = (int)((waves + SCAN_WPB - 1) / SCAN_WPB);
+    c.nwaves = c.blocks * SCAN_WPB;
+    return c;
 }
 
-template <typename T, bool SCREEN>
+// MODE 0: feasibility (hit: reach - r > thr; keeps max reach - r and argmax)
+// MODE 1: screening (value r - r_i - ||c - c_i||; hit: value <= thr)
+// MODE 2: FP32 preparation (writes float(c_i - x) and float(r_i); keeps max)
+template <typename T, int VEC, int MODE>
 __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T* R, int64_t m, int d,
-                                                            const double* cdev, double r, double thr,
-                                                            double* slack, double* blk_max, int64_t* blk_arg,
-                                                            int64_t* blk_cnt, int64_t* seg_idx, int64_t per_block,
-                                                            int G) {
-    extern __shared__ double lc[];
-    __shared__ int s_cnt[SCAN_THREADS / WAVE];
-    __shared__ double s_max[SCAN_THREADS / WAVE];
-    __shared__ int64_t s_arg[SCAN_THREADS / WAVE];
-    for (int k = threadIdx.x; k < d; k += SCAN_THREADS) lc[k] = cdev[k];
+                                                            const double* xdev, double r, double thr,
+                                                            double* slack, float* C32, float* R32, ScanCfg cfg,
+                                                            double* wmax, int64_t* warg, int64_t* wcnt,
+                                                            int64_t* seg) {
+    extern __shared__ double lx[];
+    for (int k = threadIdx.x; k < d; k += SCAN_THREADS) lx[k] = xdev ? xdev[k] : 0.0;
     __syncthreads();
+    const int G = cfg.G, nl = cfg.nl;
     const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    const int64_t gw = (int64_t)blockIdx.x * SCAN_WPB + wid;
     const int gi = lane / G, gl = lane % G, bpw = WAVE / G;
-    const int64_t b0 = (int64_t)blockIdx.x * per_block;
-    const int64_t b1 = min(m, b0 + per_block);
-    int64_t base_out = b0;
-    int64_t count = 0;
+    const int64_t wbeg = gw * cfg.bw, wend = min(m, wbeg + cfg.bw);
     double best = -INFINITY;
     int64_t barg = INT64_MAX;
-    const int step = SCAN_THREADS / G;  // balls per block step
-    for (int64_t s0 = b0; s0 < b1; s0 += step) {
-        const int64_t i = s0 + wid * bpw + gi;
-        const bool act = i < b1;
-        double val = 0.0;
-        bool hit = false;
-        if (act) {
-            const double dist = row_dist<T>(C + i * d, lc, d, G, gl);
-            const double ri = R ? (double)R[i] : 0.0;
-            if (SCREEN) {
-                val = r - ri - dist;
-                hit = val <= thr;
-                if (slack && gl == 0) slack[i] = val;
-            } else {
-                val = ri + dist - r;
-                hit = val > thr;
+    int64_t count = 0;
+    for (int64_t b0 = wbeg; b0 < wend; b0 += bpw) {
+        const int64_t i = b0 + gi;
+        const bool act = i < wend;
+        double acc = 0.0;
+        for (int j = 0; j < nl; ++j) {
+            const int base = (j * G + gl) * VEC;
+            if (act && base < d) {
+                const RowVec<T, VEC> cr = load_vec<T, VEC>(C + i * d + base);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) {
+                    const double e = (double)cr.v[q] - lx[base + q];
+                    acc += e * e;
+                    if (MODE == 2) C32[i * d + base + q] = (float)e;
+                }
             }
         }
-        if (!SCREEN && act && gl == 0) {
-            if (val > best || (val == best && i < barg)) {
+        const double dist = sqrt(group_sum<double>(acc, G));
+        const double ri = (R && act) ? (double)R[i] : 0.0;
+        double val;
+        bool hit;
+        if (MODE == 1) {
+            val = r - ri - dist;
+            hit = act && val <= thr;
+            if (slack && act && gl == 0) slack[i] = val;
+        } else {
+            val = ri + dist - r;
+            hit = (MODE == 0) && act && val > thr;
+            if (MODE == 2 && R32 && act && gl == 0) R32[i] = (float)ri;
+            if (act && (val > best || (val == best && i < barg))) {
                 best = val;
                 barg = i;
             }
         }
-        // ordered compaction within the block step: waves in order, lanes in order
-        const unsigned long long bal = __ballot(hit && act && gl == 0);
-        if (lane == 0) s_cnt[wid] = __popcll(bal);
-        __syncthreads();
-        int off = 0;
-        for (int w = 0; w < wid; ++w) off += s_cnt[w];
-        int tot = 0;
-        for (int w = 0; w < SCAN_THREADS / WAVE; ++w) tot += s_cnt[w];
-        if (hit && act && gl == 0) {
-            const int pos = off + __popcll(bal & ((1ull << lane) - 1ull));
-            seg_idx[base_out + count + pos] = i;
+        if (MODE != 2) {
+            const unsigned long long bal = __ballot(hit && gl == 0);
+            if (hit && gl == 0) seg[wbeg + count + __popcll(bal & ((1ull << lane) - 1ull))] = i;
+            count += __popcll(bal);
         }
-        count += tot;
-        __syncthreads();
     }
-    if (!SCREEN) {
-        // block max with smallest index on ties
+    if (MODE != 1) {
         for (int o = WAVE / 2; o > 0; o >>= 1) {
             const double ov = __shfl_xor(best, o, WAVE);
             const int64_t oa = __shfl_xor(barg, o, WAVE);
@@ -1170,159 +1541,126 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T*
                 barg = oa;
             }
         }
-        if (lane == 0) {
-            s_max[wid] = best;
-            s_arg[wid] = barg;
+    }
+    if (lane == 0) {
+        if (wmax) wmax[gw] = best;
+        if (warg) warg[gw] = barg;
+        if (wcnt) wcnt[gw] = count;
+    }
+}
+
+// Exclusive prefix of the per-wave counts (into offs), the total, and the
+// maximum with the smallest index on ties.  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void scan_finalize(const int64_t* wcnt, const double* wmax, const int64_t* warg,
+                                                      int nw, int64_t* offs, int64_t* total, double* out_max,
+                                                      int64_t* out_arg) {
+    __shared__ int64_t sc[1024];
+    __shared__ double sm[1024];
+    __shared__ int64_t sa[1024];
+    const int t = threadIdx.x;
+    const int per = (nw + 1023) / 1024;
+    const int w0 = t * per, w1 = min(nw, w0 + per);
+    int64_t c = 0;
+    double bm = -INFINITY;
+    int64_t ba = INT64_MAX;
+    for (int w = w0; w < w1; ++w) {
+        if (wcnt) c += wcnt[w];
+        if (wmax && (wmax[w] > bm || (wmax[w] == bm && warg[w] < ba))) {
+            bm = wmax[w];
+            ba = warg[w];
+        }
+    }
+    sc[t] = c;
+    sm[t] = bm;
+    sa[t] = ba;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the per-thread counts
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t v = t >= o ? sc[t - o] : 0;
+        __syncthreads();
+        sc[t] += v;
+        __syncthreads();
+    }
+    if (wcnt) {
+        int64_t run = t > 0 ? sc[t - 1] : 0;
+        for (int w = w0; w < w1; ++w) {
+            offs[w] = run;
+            run += wcnt[w];
+        }
+        if (t == 1023 && total) *total = sc[1023];
+    }
+    for (int o = 512; o > 0; o >>= 1) {
+        if (t < o && (sm[t + o] > sm[t] || (sm[t + o] == sm[t] && sa[t + o] < sa[t]))) {
+            sm[t] = sm[t + o];
+            sa[t] = sa[t + o];
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double bm = s_max[0];
-            int64_t ba = s_arg[0];
-            for (int w = 1; w < SCAN_THREADS / WAVE; ++w)
-                if (s_max[w] > bm || (s_max[w] == bm && s_arg[w] < ba)) {
-                    bm = s_max[w];
-                    ba = s_arg[w];
-                }
-            blk_max[blockIdx.x] = bm;
-            blk_arg[blockIdx.x] = ba;
-        }
     }
-    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = count;
-}
-
-static int scan_group(int d) {
-    int G = 1;
-    while (G < d && G < 64) G <<= 1;
-    return G;
-}
-
-hipError_t launch_feasible(const void* C, const void* R, int64_t m, int d, int dtype, const double* c, double r,
-                           double eps, double* blk_max, int64_t* blk_arg, int64_t* blk_cnt, int64_t* seg_idx,
-                           int nblocks, int64_t per_block, hipStream_t s) {
-    const int G = scan_group(d);
-    size_t lds = sizeof(double) * d;
-    if (dtype == 0)
-        hipLaunchKernelGGL((scan_kernel<double, false>), dim3(nblocks), dim3(SCAN_THREADS), lds, s,
-                           (const double*)C, (const double*)R, m, d, c, r, eps, nullptr, blk_max, blk_arg, blk_cnt,
-                           seg_idx, per_block, G);
-    else
-        hipLaunchKernelGGL((scan_kernel<float, false>), dim3(nblocks), dim3(SCAN_THREADS), lds, s,
-                           (const float*)C, (const float*)R, m, d, c, r, eps, nullptr, blk_max, blk_arg, blk_cnt,
-                           seg_idx, per_block, G);
-    return hipGetLastError();
-}
-
-hipError_t launch_screen(const void* C, const void* R, int64_t m, int d, int dtype, const double* c, double r,
-                         double tol, double* slack, int64_t* blk_cnt, int64_t* seg_idx, int nblocks,
-                         int64_t per_block, hipStream_t s) {
-    const int G = scan_group(d);
-    size_t lds = sizeof(double) * d;
-    if (dtype == 0)
-        hipLaunchKernelGGL((scan_kernel<double, true>), dim3(nblocks), dim3(SCAN_THREADS), lds, s,
-                           (const double*)C, (const double*)R, m, d, c, r, tol, slack, nullptr, nullptr, blk_cnt,
-                           seg_idx, per_block, G);
-    else
-        hipLaunchKernelGGL((scan_kernel<float, true>), dim3(nblocks), dim3(SCAN_THREADS), lds, s, (const float*)C,
-                           (const float*)R, m, d, c, r, tol, slack, nullptr, nullptr, blk_cnt, seg_idx, per_block,
-                           G);
-    return hipGetLastError();
-}
-
-// Concatenates the per-block segments in block order.  One block per
-// segment; each computes its output offset from the counts before it.
-__global__ __launch_bounds__(256) void compact_kernel(const int64_t* seg_idx, const int64_t* blk_cnt, int nblocks,
-                                                      int64_t per_block, int64_t* out, int64_t cap,
-                                                      int64_t* total) {
-    __shared__ int64_t s_off;
-    const int b = blockIdx.x;
-    if (threadIdx.x == 0) {
-        int64_t off = 0;
-        for (int k = 0; k < b; ++k) off += blk_cnt[k];
-        s_off = off;
-        if (b == nblocks - 1 && total) *total = off + blk_cnt[b];
+    if (t == 0) {
+        if (out_max) *out_max = sm[0];
+        if (out_arg) *out_arg = sa[0];
     }
-    __syncthreads();
-    const int64_t off = s_off, cnt = blk_cnt[b];
-    for (int64_t k = threadIdx.x; k < cnt; k += 256) {
+}
+
+// Concatenation of the wave segments (one wave per segment).
+__global__ __launch_bounds__(256) void scan_copy(const int64_t* seg, const int64_t* wcnt, const int64_t* offs,
+                                                 int nw, int64_t bw, int64_t* out, int64_t cap) {
+    const int lane = lane_id();
+    const int64_t w = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (w >= nw) return;
+    const int64_t cnt = wcnt[w], off = offs[w];
+    for (int64_t k = lane; k < cnt; k += WAVE) {
         const int64_t pos = off + k;
-        if (pos < cap) out[pos] = seg_idx[(int64_t)b * per_block + k];
+        if (pos < cap) out[pos] = seg[w * bw + k];
     }
 }
 
-hipError_t launch_compact(const int64_t* seg_idx, const int64_t* blk_cnt, int nblocks, int64_t per_block,
-                          int64_t* out, int64_t cap, int64_t* total_dev, hipStream_t s) {
-    hipLaunchKernelGGL(compact_kernel, dim3(nblocks), dim3(256), 0, s, seg_idx, blk_cnt, nblocks, per_block, out, cap,
-                       total_dev);
+template <int MODE>
+static hipError_t launch_scan_t(const void* C, const void* R, int64_t m, int d, int dtype, const double* x,
+                                double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c,
+                                double* wmax, int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s) {
+    const size_t lds = sizeof(double) * d;
+    if (dtype == 0) {
+        if (c.vec == 2)
+            hipLaunchKernelGGL((scan_kernel<double, 2, MODE>), dim3(c.blocks), dim3(SCAN_THREADS), lds, s,
+                               (const double*)C, (const double*)R, m, d, x, r, thr, slack, C32, R32, c, wmax, warg,
+                               wcnt, seg);
+        else
+            hipLaunchKernelGGL((scan_kernel<double, 1, MODE>), dim3(c.blocks), dim3(SCAN_THREADS), lds, s,
+                               (const double*)C, (const double*)R, m, d, x, r, thr, slack, C32, R32, c, wmax, warg,
+                               wcnt, seg);
+    } else {
+        if (c.vec == 2)
+            hipLaunchKernelGGL((scan_kernel<float, 2, MODE>), dim3(c.blocks), dim3(SCAN_THREADS), lds, s,
+                               (const float*)C, (const float*)R, m, d, x, r, thr, slack, C32, R32, c, wmax, warg,
+                               wcnt, seg);
+        else
+            hipLaunchKernelGGL((scan_kernel<float, 1, MODE>), dim3(c.blocks), dim3(SCAN_THREADS), lds, s,
+                               (const float*)C, (const float*)R, m, d, x, r, thr, slack, C32, R32, c, wmax, warg,
+                               wcnt, seg);
+    }
     return hipGetLastError();
 }
 
-__global__ void max_reduce_kernel(const double* bm, const int64_t* ba, int n, double* out_max, int64_t* out_arg) {
-    if (threadIdx.x != 0) return;
-    double b = -INFINITY;
-    int64_t a = INT64_MAX;
-    for (int k = 0; k < n; ++k)
-        if (bm[k] > b || (bm[k] == b && ba[k] < a)) {
-            b = bm[k];
-            a = ba[k];
-        }
-    *out_max = b;
-    *out_arg = a;
+hipError_t launch_scan(int mode, const void* C, const void* R, int64_t m, int d, int dtype, const double* x,
+                       double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c, double* wmax,
+                       int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s) {
+    if (mode == 0) return launch_scan_t<0>(C, R, m, d, dtype, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, s);
+    if (mode == 1) return launch_scan_t<1>(C, R, m, d, dtype, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, s);
+    return launch_scan_t<2>(C, R, m, d, 0, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, s);
 }
 
-hipError_t launch_max_reduce(const double* blk_max, const int64_t* blk_arg, int nblocks, double* out_max,
-                             int64_t* out_arg, hipStream_t s) {
-    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(64), 0, s, blk_max, blk_arg, nblocks, out_max, out_arg);
+hipError_t launch_scan_finalize(const int64_t* wcnt, const double* wmax, const int64_t* warg, int nw, int64_t* offs,
+                                int64_t* total, double* out_max, int64_t* out_arg, hipStream_t s) {
+    hipLaunchKernelGGL(scan_finalize, dim3(1), dim3(1024), 0, s, wcnt, wmax, warg, nw, offs, total, out_max,
+                       out_arg);
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Precision preparation: C32 = float(C - origin), R32 = float(R), and the
-// block maxima of ||c_i - origin|| + r_i in FP64.
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(SCAN_THREADS) void prepare_kernel(const double* C, const double* R, int64_t m, int d,
-                                                               const double* origin, float* C32, float* R32,
-                                                               double* blk_max, int64_t per_block, int G) {
-    extern __shared__ double lo[];
-    __shared__ double s_max[SCAN_THREADS / WAVE];
-    for (int k = threadIdx.x; k < d; k += SCAN_THREADS) lo[k] = origin ? origin[k] : 0.0;
-    __syncthreads();
-    const int lane = lane_id(), wid = threadIdx.x / WAVE;
-    const int gi = lane / G, gl = lane % G, bpw = WAVE / G;
-    const int64_t b0 = (int64_t)blockIdx.x * per_block;
-    const int64_t b1 = min(m, b0 + per_block);
-    double best = 0.0;
-    const int step = SCAN_THREADS / G;
-    for (int64_t s0 = b0; s0 < b1; s0 += step) {
-        const int64_t i = s0 + wid * bpw + gi;
-        if (i < b1) {
-            double acc = 0.0;
-            for (int k = gl; k < d; k += G) {
-                const double e = C[i * d + k] - lo[k];
-                C32[i * d + k] = (float)e;
-                acc += e * e;
-            }
-            const double dist = sqrt(group_sum<double>(acc, G));
-            const double ri = R ? R[i] : 0.0;
-            if (R && gl == 0) R32[i] = (float)ri;
-            best = fmax(best, dist + ri);
-        }
-    }
-    best = wave_max(best);
-    if (lane == 0) s_max[wid] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double b = s_max[0];
-        for (int w = 1; w < SCAN_THREADS / WAVE; ++w) b = fmax(b, s_max[w]);
-        blk_max[blockIdx.x] = b;
-    }
-}
-
-hipError_t launch_prepare_f32(const double* C, const double* R, int64_t m, int d, const double* origin, float* C32,
-                              float* R32, double* blk_max, int nblocks, int64_t per_block, hipStream_t s) {
-    const int G = scan_group(d);
-    hipLaunchKernelGGL(prepare_kernel, dim3(nblocks), dim3(SCAN_THREADS), sizeof(double) * d, s, C, R, m, d, origin,
-                       C32, R32, blk_max, per_block, G);
+hipError_t launch_scan_copy(const int64_t* seg, const int64_t* wcnt, const int64_t* offs, int nw, int64_t bw,
+                            int64_t* out, int64_t cap, hipStream_t s) {
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_copy, dim3((nw + 3) / 4), dim3(256), 0, s, seg, wcnt, offs, nw, bw, out, cap);
     return hipGetLastError();
 }
 

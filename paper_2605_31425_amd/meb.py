@@ -34,20 +34,25 @@ class Options(ctypes.Structure):
                 ("tol_kkt_low", ctypes.c_double), ("tol_red", ctypes.c_double), ("eps_feas_rel", ctypes.c_double),
                 ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32), ("max_ls", ctypes.c_int32),
                 ("max_reinsert", ctypes.c_int32), ("mode", ctypes.c_int32), ("stall_outer", ctypes.c_int32),
-                ("verbose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("outer", ctypes.c_int32 * 2), ("inner", ctypes.c_int32 * 2), ("passes", ctypes.c_int32 * 2),
                 ("kkt", ctypes.c_double * 2), ("L", ctypes.c_double), ("rbar", ctypes.c_double),
                 ("delta_max", ctypes.c_double), ("n_red", ctypes.c_int64), ("reinsert_rounds", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 4)]
+                ("status", ctypes.c_int32), ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 4),
+                ("pass_ms", ctypes.c_double * 2), ("pass_bytes", ctypes.c_double * 2),
+                ("pass_launches", ctypes.c_int32 * 2), ("reserved", ctypes.c_int32),
+                ("mid_rows", ctypes.c_double * 2), ("mid_rows_max", ctypes.c_double * 2)]
 
     def as_dict(self):
         return dict(outer=list(self.outer), inner=list(self.inner), passes=list(self.passes), kkt=list(self.kkt),
                     L=self.L, rbar=self.rbar, delta_max=self.delta_max, n_red=self.n_red,
                     reinsert_rounds=self.reinsert_rounds, status=self.status, ms_total=self.ms_total,
-                    ms_phase=list(self.ms_phase))
+                    ms_phase=list(self.ms_phase), pass_ms=list(self.pass_ms), pass_bytes=list(self.pass_bytes),
+                    pass_launches=list(self.pass_launches), mid_rows=list(self.mid_rows),
+                    mid_rows_max=list(self.mid_rows_max))
 
 
 class MebError(RuntimeError):
