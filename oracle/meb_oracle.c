@@ -31,6 +31,9 @@
 
 typedef long double acc_t;
 
+/* reading: relative margin of the starting radius above L (see orc_ripalm) */
+#define ORC_START_MARGIN 0x1p-10
+
 /* ------------------------------------------------------------------------ */
 /* Second-order cone primitives (Section 2, closed-form projection).        */
 /* ------------------------------------------------------------------------ */
@@ -432,7 +435,12 @@ int orc_ripalm(int64_t m, int d, const double* C, const double* R, const orc_par
         x[0] = x0[0] / L;
         for (int k = 0; k < d; ++k) x[1 + k] = (x0[1 + k] - C[k]) / L;
     } else {
-        x[0] = 1.0;
+        /* Algorithm 1 admits any starting point.  (1, 0) in normalized units
+         * would put the ball that attains L exactly on the boundary between
+         * the polar and the third projection case, where the generalized
+         * Jacobian is set-valued and rounding picks the case; a radius a
+         * little above L keeps every ball strictly polar at the start. */
+        x[0] = 1.0 + ORC_START_MARGIN;
         for (int k = 0; k < d; ++k) x[1 + k] = 0.0;
     }
     memcpy(ab, x, sizeof(double) * n1);

@@ -166,8 +166,9 @@ def test_kkt_certificate(kind):
     assert st["kkt"] <= 1e-9
     _certificate(C, R, r, c, U, V, 1e-8)
     # the fixed-up radius is feasible and within the KKT level of rbar
+    # (numpy's norm rounds differently from the oracle's by an ulp or two)
     reach = np.linalg.norm(C - c, axis=1) + (0 if R is None else R)
-    assert st["r_fixed"] >= reach.max()
+    assert st["r_fixed"] >= reach.max() * (1 - 8 * np.finfo(float).eps)
     assert st["r_fixed"] - r <= 1e-8 * r
 
 
