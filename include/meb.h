@@ -96,7 +96,8 @@ typedef struct meb_options {
     int32_t max_reinsert;  /* reinsertion rounds of the mixed path; default 20                       */
     int32_t mode;          /* MEB_MODE_FP64 or MEB_MODE_MIXED; default MEB_MODE_MIXED                */
     int32_t stall_outer;   /* stop a run after this many outer steps without halving KKT_max; 3     */
-    int32_t verbose;       /* 0 = silent; 1 = one line per outer iteration on stderr                 */
+    int32_t verbose;       /* 0 = silent; 1 = one line per outer iteration on stderr; 2 = also one
+                              line per evaluation pass and Newton step (device printf)          */
     int32_t profile;       /* 1 = time every evaluation pass with HIP events (fills the pass_*
                               fields of meb_stats); default 0                                   */
 } meb_options;
@@ -229,6 +230,80 @@ int meb_prepare_f32(const double* C, const double* R, int64_t m, int32_t d, cons
  * Returns MEB_ERR_NUMERIC if a pivot is not positive. */
 int meb_chol_workspace_size(int32_t n, size_t* bytes);
 int meb_chol_solve(int32_t n, const double* H, const double* b, double* y, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Multi-instance server (continuous batching).  Not part of the paper; it
+ * serves a stream of independent MEB requests on one GPU.
+ *
+ * Requests are admitted first-in first-out whenever a slot is free and the
+ * request's workspace (meb_workspace_size with the server's options) fits in
+ * the caller's device pool; the head of the queue waits for room, so no
+ * request starves.  An engine thread (one HIP stream, created on the device
+ * current at meb_server_create) runs each admitted request as the same
+ * phase sequence as meb_solve and steps all requests that are inside a
+ * ripALM run together: one launch per kernel covers every such request, each
+ * with the blocks, arithmetic and reduction order it has alone, so a result
+ * is bitwise the same as meb_solve's on the same input and options, whatever
+ * else is in flight.
+ * ------------------------------------------------------------------------ */
+typedef struct meb_server meb_server;
+
+typedef struct meb_server_result {
+    int64_t ticket;       /* from meb_server_submit                            */
+    int64_t tag;          /* the caller's tag                                  */
+    int64_t m;
+    int32_t d;
+    int32_t status;       /* meb_solve's return value for this request         */
+    double r;             /* radius (feasible by construction)                 */
+    double t_submit_ms;   /* server clock (ms, steady clock) at submission     */
+    double t_admit_ms;    /* ... at admission                                  */
+    double t_done_ms;     /* ... at completion                                 */
+    meb_stats stats;      /* as meb_solve's; ms_total = t_done - t_admit       */
+    char message[128];    /* error text when status < 0                        */
+} meb_server_result;
+
+typedef struct meb_server_stats {
+    int64_t submitted, completed, failed;
+    int32_t queued, active;
+    uint64_t pool_used, pool_peak, pool_capacity; /* bytes of the job region  */
+    int64_t ticks;                                 /* batched solver steps     */
+    double mean_tick_items;                        /* requests per tick        */
+    char message[128];                             /* fatal engine error       */
+} meb_server_stats;
+
+/* Creates a server over `pool` (device, 256-byte aligned, caller-owned, kept
+ * until meb_server_destroy returns).  A table of max_active entries sits at
+ * the start of the pool; the rest holds the requests' workspaces.  max_active
+ * in [1, 1024] bounds the requests in flight; max_d bounds d of a request.
+ * opts (nullable = defaults) apply to every request; profile must be 0. */
+int meb_server_create(void* pool, size_t pool_bytes, const meb_options* opts, int32_t max_active, int32_t max_d,
+                      meb_server** out);
+
+/* Queues one request; returns at once.  C (m x d) and R (m, nullable =
+ * points) are FP64 device arrays whose contents must be complete when the
+ * call is made (synchronize the stream that wrote them) and must stay
+ * unchanged until the request's result has been polled.  c_out (host, d
+ * doubles, nullable) receives the center at completion.  Returns
+ * MEB_ERR_WORKSPACE if the request can never fit in the pool. */
+int meb_server_submit(meb_server* srv, const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
+                      int64_t tag, double* c_out, int64_t* ticket);
+
+/* Moves up to `cap` completed results into out[0 .. *n_out), in completion
+ * order, waiting up to wait_ms for the first one when none is ready. */
+int meb_server_poll(meb_server* srv, meb_server_result* out, int32_t cap, int32_t wait_ms, int32_t* n_out);
+
+int meb_server_info(meb_server* srv, meb_server_stats* info);
+
+/* Finishes every submitted request, then stops the engine and frees the
+ * server (not the pool).  Results not yet polled are dropped. */
+int meb_server_destroy(meb_server* srv);
+
+/* The server's admission policy on a simulated clock: request i arrives at
+ * arrival[i] (non-decreasing), needs bytes[i] of a pool of pool_bytes and
+ * holds it for service[i] after admission.  Outputs t_admit, t_done and the
+ * pool offset of each request.  For testing the policy without a GPU. */
+int meb_sched_simulate(int32_t n, const double* arrival, const double* service, const uint64_t* bytes,
+                       uint64_t pool_bytes, int32_t max_active, double* t_admit, double* t_done, uint64_t* offset);
 
 #ifdef __cplusplus
 }

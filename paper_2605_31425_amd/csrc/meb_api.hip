@@ -1,12 +1,12 @@
-// Host side of libmeb.so: the C ABI of include/meb.h, workspace carving, and
-// the drivers of plain FP64 ripALM and of the mixed-precision reduction.
+// Host side of libmeb.so: the C ABI of include/meb.h, workspace carving, the
+// scan helpers, and the solve as a resumable job with its synchronous driver.
 //
 // A ripALM run is a device-resident state machine.  The host enqueues a fixed
 // sequence per Newton step -- evaluation pass, record reduction, rank-one
-// Hessian contraction, control step -- and the control kernel decides on the
-// device what the next pass computes (Armijo trials along the Newton
-// direction, a plain re-evaluation, or the multiplier update fused with the
-// first evaluation of the next outer iteration).  The host only polls the
+// Hessian contraction, assembly, control step -- and the control kernel
+// decides on the device what the next pass computes (Armijo trials along the
+// Newton direction, a plain re-evaluation, or the multiplier update fused with
+// the first evaluation of the next outer iteration).  The host only polls the
 // state's scalar header every few steps to learn when the run has ended.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -14,63 +14,25 @@
 #include <string.h>
 
 #include <algorithm>
-#include <iterator>
 #include <chrono>
+#include <iterator>
 #include <string>
 #include <vector>
 
-#include "../../include/meb.h"
-#include "meb_internal.h"
+#include "meb_host.h"
 
-using namespace meb;
+namespace meb {
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
 }
 
-#define HIPCHK(expr)                                                                              \
-    do {                                                                                          \
-        hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess) return fail(MEB_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-#define CHK(expr)                  \
-    do {                           \
-        int rc_ = (expr);          \
-        if (rc_ < 0) return rc_;   \
-    } while (0)
-
-constexpr size_t ALIGN = 256;
-
-inline size_t al(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
-
-struct Arena {
-    char* base;
-    size_t size;
-    size_t off;
-    template <typename T>
-    T* take(size_t n) {
-        size_t o = al(off);
-        off = o + al(n * sizeof(T));
-        return reinterpret_cast<T*>(base + o);
-    }
-    bool ok() const { return off <= size; }
-};
-
-// Counting arena: computes the size of a carving without memory.
-struct Sizer {
-    size_t off = 0;
-    template <typename T>
-    T* take(size_t n) {
-        off = al(off) + al(n * sizeof(T));
-        return nullptr;
-    }
-};
+const char* last_error_text() { return g_err.c_str(); }
 
 int device_cus() {
     static int cus[64] = {0};
@@ -87,7 +49,186 @@ int device_cus() {
     return cus[dev];
 }
 
-// Thread-local pinned staging for small device-to-host reads.
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+void Engine::setup(int64_t m_, int d_, int dtype_) {
+    m = m_;
+    d = d_;
+    dtype = dtype_;
+    pc = choose_pass_config(m, d, dtype, device_cus());
+    sl = StateLayout::make(d);
+    rl = RecLayout::make(d);
+    ntile = (d + syrk_tile() - 1) / syrk_tile();
+    ksplit = syrk_ksplit(d);
+    // a line-search pass skips the contraction above this many rows
+    skip_k = std::max(4096.0, 16.0 * d);
+}
+
+PassArgs Engine::args(const void* C, const void* R, void* U, void* V) const {
+    PassArgs a;
+    memset(&a, 0, sizeof(a));
+    a.C = C;
+    a.R = R;
+    a.U = U;
+    a.V = V;
+    a.Uout = U;
+    a.Vout = V;
+    a.m = m;
+    a.d = d;
+    a.dtype = dtype;
+    a.state = state;
+    a.sl = sl;
+    a.rl = rl;
+    a.rec = rec;
+    a.mid_idx = mid_idx;
+    a.mid_coef = mid_coef;
+    a.mid_cnt = mid_cnt;
+    a.force_mode = -1;
+    a.want_kkt = 0;
+    a.want_mid = 1;
+    a.dense_vout = 0;
+    for (int l = 0; l < NT; ++l) a.etas[l] = solver_eta(l);
+    return a;
+}
+
+SyrkArgs Engine::syrk_args(const void* C, const void* U, const void* V) const {
+    SyrkArgs s;
+    memset(&s, 0, sizeof(s));
+    s.C = C;
+    s.U = U;
+    s.V = V;
+    s.d = d;
+    s.dtype = dtype;
+    s.state = state;
+    s.sl = sl;
+    s.red = red;
+    s.rl = rl;
+    s.list_idx = list_idx;
+    s.list_coef = list_coef;
+    s.list_total = list_total;
+    s.skip_k = skip_k;
+    s.out = syrk;
+    s.ksplit = ksplit;
+    s.tile = syrk_tile();
+    s.ntile = ntile;
+    return s;
+}
+
+BatchItem Engine::item(const PassArgs& a, int* flag) const {
+    BatchItem it;
+    memset(&it, 0, sizeof(it));
+    it.pa = a;
+    it.pc = pc;
+    it.sa = syrk_args(a.C, a.Uout ? a.Uout : a.U, a.Vout ? a.Vout : a.V);
+    it.red = red;
+    it.list_offs = list_offs;
+    it.flag = flag;
+    it.ksplit = ksplit;
+    it.ntile = ntile;
+    it.use_syrk = use_syrk ? 1 : 0;
+    return it;
+}
+
+int Engine::step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (ev0) HIPCHK(hipEventRecord(ev0, s));
+    HIPCHK(launch_pass(a, pc, s));
+    if (ev1) HIPCHK(hipEventRecord(ev1, s));
+    HIPCHK(launch_reduce_records(rec, pc.blocks, rl.len, (int64_t)pc.waves_per_block * rl.len, red, s));
+    if (use_syrk && a.want_mid) {
+        HIPCHK(launch_mid_compact(mid_cnt, pc.nwaves, pc.bw, mid_idx, mid_coef, list_offs, list_total, list_idx,
+                                  list_coef, state, s));
+        HIPCHK(launch_syrk(syrk_args(a.C, a.Uout ? a.Uout : a.U, a.Vout ? a.Vout : a.V), s));
+    }
+    if (control) HIPCHK(launch_assemble(state, sl, rl, red, syrk, ksplit, ntile, use_syrk ? 1 : 0, s));
+    if (control) HIPCHK(launch_control(state, sl, rl, red, nullptr, s));
+    return MEB_OK;
+}
+
+size_t engine_bytes(int64_t m, int d, int dtype) {
+    Engine e;
+    e.setup(m, d, dtype);
+    Sizer sz;
+    e.carve(sz);
+    return sz.off;
+}
+
+// ---------------------------------------------------------------------------
+// Scans
+// ---------------------------------------------------------------------------
+void ScanBufs::setup(int64_t m_, int d_) {
+    m = m_;
+    d = d_;
+    cfg = scan_config(m, d, device_cus());
+}
+
+size_t scan_bytes(int64_t m, int d) {
+    ScanBufs b;
+    b.setup(m, d);
+    Sizer s;
+    b.carve(s);
+    return s.off;
+}
+
+// max_i (r_i + ||c - c_i|| - r) with its smallest argmax, and the ascending
+// list of {i : r_i + ||c - c_i|| - r > eps} (first viol_cap entries).
+int enq_check(const void* C, const void* R, int64_t m, int d, int dtype, double r, const double* c_dev, double eps,
+              ScanBufs& b, int64_t* viol_idx, int64_t viol_cap, double* out, hipStream_t s) {
+    HIPCHK(launch_scan(0, C, R, m, d, dtype, c_dev, r, eps, nullptr, nullptr, nullptr, b.cfg, b.wmax, b.warg, b.wcnt,
+                       b.seg, s));
+    HIPCHK(launch_scan_finalize(b.wcnt, b.wmax, b.warg, b.cfg.nwaves, b.offs, b.total(), b.out_max(), b.out_arg(), s));
+    if (viol_idx && viol_cap > 0)
+        HIPCHK(launch_scan_copy(b.seg, b.wcnt, b.offs, b.cfg.nwaves, b.cfg.bw, viol_idx, viol_cap, s));
+    HIPCHK(hipMemcpyAsync(out, b.res, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    return MEB_OK;
+}
+
+// I_red = {i : r - r_i - ||c - c_i|| <= tol}, ascending.
+int enq_screen(const void* C, const void* R, int64_t m, int d, int dtype, double r, const double* c_dev, double tol,
+               ScanBufs& b, int64_t* keep_idx, double* slack, double* out, hipStream_t s) {
+    HIPCHK(launch_scan(1, C, R, m, d, dtype, c_dev, r, tol, slack, nullptr, nullptr, b.cfg, nullptr, nullptr, b.wcnt,
+                       b.seg, s));
+    HIPCHK(launch_scan_finalize(b.wcnt, nullptr, nullptr, b.cfg.nwaves, b.offs, b.total(), nullptr, nullptr, s));
+    HIPCHK(launch_scan_copy(b.seg, b.wcnt, b.offs, b.cfg.nwaves, b.cfg.bw, keep_idx, m, s));
+    HIPCHK(hipMemcpyAsync(out, b.res, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    return MEB_OK;
+}
+
+// FP32 copy shifted by `origin` (device, d) and L = max_i ||c_i - origin|| + r_i.
+int enq_prepare(const double* C, const double* R, int64_t m, int d, const double* origin_dev, float* C32, float* R32,
+                ScanBufs& b, double* out, hipStream_t s) {
+    HIPCHK(launch_scan(2, C, R, m, d, MEB_F64, origin_dev, 0.0, 0.0, nullptr, C32, R32, b.cfg, b.wmax, b.warg,
+                       nullptr, nullptr, s));
+    HIPCHK(launch_scan_finalize(nullptr, b.wmax, b.warg, b.cfg.nwaves, nullptr, nullptr, b.out_max(), b.out_arg(), s));
+    HIPCHK(hipMemcpyAsync(out, b.res, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    return MEB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Solve workspace
+// ---------------------------------------------------------------------------
+void SolveWs::setup(int64_t m, int d, const meb_options* o) {
+    e64.setup(m, d, MEB_F64);
+    if (o->mode == MEB_MODE_MIXED) e32.setup(m, d, MEB_F32);
+    scan.setup(m, d);
+}
+
+size_t solve_ws_bytes(int64_t m, int d, const meb_options* o) {
+    SolveWs w;
+    w.setup(m, d, o);
+    Sizer s;
+    w.carve(s, m, d, o, true);
+    return s.off + ALIGN;
+}
+
+namespace {
+
+// Thread-local pinned staging for the synchronous entry points.
 struct Pinned {
     double* buf = nullptr;
     size_t cap = 0;
@@ -107,8 +248,6 @@ struct Pinned {
 };
 thread_local Pinned g_pin;
 
-size_t dtype_size(int dtype) { return dtype == MEB_F64 ? 8 : 4; }
-
 // Thread-local pool of HIP events for the optional per-pass timing.
 struct EventPool {
     std::vector<hipEvent_t> ev;
@@ -126,391 +265,429 @@ struct EventPool {
 };
 thread_local EventPool g_events;
 
-// ---------------------------------------------------------------------------
-// Evaluation engine: the buffers of the pass / reduce / contraction / control
-// sequence for one instance shape.
-// ---------------------------------------------------------------------------
-struct Engine {
-    int64_t m = 0;
-    int d = 0;
-    int dtype = 0;
-    PassConfig pc{};
-    StateLayout sl{};
-    RecLayout rl{};
-    int ntile = 0, ksplit = 0;
-    bool use_syrk = true;
-    double* state = nullptr;
-    double* rec = nullptr;
-    double* red = nullptr;
-    int32_t* mid_idx = nullptr;
-    double* mid_coef = nullptr;
-    int32_t* mid_cnt = nullptr;
-    double* syrk = nullptr;
-    int32_t* list_idx = nullptr;
-    double* list_coef = nullptr;
-    int64_t* list_offs = nullptr;
-    int64_t* list_total = nullptr;
-    double skip_k = INFINITY;
-
-    void setup(int64_t m_, int d_, int dtype_) {
-        m = m_;
-        d = d_;
-        dtype = dtype_;
-        pc = choose_pass_config(m, d, dtype, device_cus());
-        sl = StateLayout::make(d);
-        rl = RecLayout::make(d);
-        ntile = (d + syrk_tile() - 1) / syrk_tile();
-        ksplit = syrk_ksplit(d);
-        // a line-search pass skips the contraction above this many rows
-        skip_k = std::max(4096.0, 16.0 * d);
-    }
-    template <typename A>
-    void carve(A& a) {
-        state = a.template take<double>(sl.len);
-        rec = a.template take<double>((size_t)pc.nwaves * rl.len);
-        red = a.template take<double>((size_t)(32 + 1) * rl.len);
-        const size_t cap = (size_t)pc.nwaves * (size_t)pc.bw;
-        mid_idx = a.template take<int32_t>(cap);
-        mid_coef = a.template take<double>(cap);
-        mid_cnt = a.template take<int32_t>(pc.nwaves);
-        const size_t pairs = (size_t)ntile * (ntile + 1) / 2;
-        syrk = a.template take<double>((size_t)ksplit * pairs * syrk_tile() * syrk_tile());
-        list_idx = a.template take<int32_t>(cap);
-        list_coef = a.template take<double>(cap);
-        list_offs = a.template take<int64_t>(pc.nwaves);
-        list_total = a.template take<int64_t>(4);
-    }
-    PassArgs args(const void* C, const void* R, void* U, void* V) const {
-        PassArgs a;
-        memset(&a, 0, sizeof(a));
-        a.C = C;
-        a.R = R;
-        a.U = U;
-        a.V = V;
-        a.Uout = U;
-        a.Vout = V;
-        a.m = m;
-        a.d = d;
-        a.dtype = dtype;
-        a.state = state;
-        a.sl = sl;
-        a.rl = rl;
-        a.rec = rec;
-        a.mid_idx = mid_idx;
-        a.mid_coef = mid_coef;
-        a.mid_cnt = mid_cnt;
-        a.force_mode = -1;
-        a.want_kkt = 0;
-        a.want_mid = 1;
-        a.dense_vout = 0;
-        for (int l = 0; l < NT; ++l) a.etas[l] = solver_eta(l);
-        return a;
-    }
-    SyrkArgs syrk_args(const void* C, const void* U, const void* V) const {
-        SyrkArgs s;
-        memset(&s, 0, sizeof(s));
-        s.C = C;
-        s.U = U;
-        s.V = V;
-        s.d = d;
-        s.dtype = dtype;
-        s.state = state;
-        s.sl = sl;
-        s.red = red;
-        s.rl = rl;
-        s.list_idx = list_idx;
-        s.list_coef = list_coef;
-        s.list_total = list_total;
-        s.skip_k = skip_k;
-        s.out = syrk;
-        s.ksplit = ksplit;
-        s.tile = syrk_tile();
-        s.ntile = ntile;
-        return s;
-    }
-    // pass + reduce + contraction (+ control when `control`); with `ev0`
-    // non-null, the pass launch is bracketed by the two events
-    int step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-        if (ev0) HIPCHK(hipEventRecord(ev0, s));
-        HIPCHK(launch_pass(a, pc, 3, s));
-        if (ev1) HIPCHK(hipEventRecord(ev1, s));
-        HIPCHK(launch_reduce_records(rec, pc.blocks, rl.len, (int64_t)pc.waves_per_block * rl.len, red, s));
-        if (use_syrk && a.want_mid) {
-            HIPCHK(launch_mid_compact(mid_cnt, pc.nwaves, pc.bw, mid_idx, mid_coef, list_offs, list_total, list_idx,
-                                      list_coef, state, s));
-            HIPCHK(launch_syrk(syrk_args(a.C, a.Uout ? a.Uout : a.U, a.Vout ? a.Vout : a.V), s));
-        }
-        if (control) HIPCHK(launch_assemble(state, sl, rl, red, syrk, ksplit, ntile, use_syrk ? 1 : 0, s));
-        if (control) HIPCHK(launch_control(state, sl, rl, red, nullptr, s));
-        return MEB_OK;
-    }
-};
-
-size_t engine_bytes(int64_t m, int d, int dtype) {
-    Engine e;
-    e.setup(m, d, dtype);
-    Sizer sz;
-    e.carve(sz);
-    return sz.off;
+// grows a pinned int64 buffer (contents are not kept)
+int grow_pinned(int64_t*& p, size_t& cap, size_t n) {
+    if (n <= cap) return MEB_OK;
+    if (p) HIPCHK(hipHostFree(p));
+    p = nullptr;
+    cap = 0;
+    HIPCHK(hipHostMalloc((void**)&p, std::max<size_t>(n, 16) * sizeof(int64_t), hipHostMallocDefault));
+    cap = std::max<size_t>(n, 16);
+    return MEB_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Scan helpers (feasibility check / screening)
-// ---------------------------------------------------------------------------
-struct ScanBufs {
-    ScanCfg cfg{};
-    int64_t m = 0;
-    int d = 0;
-    double* wmax = nullptr;
-    int64_t* warg = nullptr;
-    int64_t* wcnt = nullptr;
-    int64_t* offs = nullptr;
-    int64_t* seg = nullptr;
-    double* out_max = nullptr;
-    int64_t* out_arg = nullptr;
-    int64_t* total = nullptr;
-    double* cvec = nullptr;
-    void setup(int64_t m_, int d_) {
-        m = m_;
-        d = d_;
-        cfg = scan_config(m, d, device_cus());
-    }
-    template <typename A>
-    void carve(A& a) {
-        wmax = a.template take<double>(cfg.nwaves);
-        warg = a.template take<int64_t>(cfg.nwaves);
-        wcnt = a.template take<int64_t>(cfg.nwaves);
-        offs = a.template take<int64_t>(cfg.nwaves);
-        seg = a.template take<int64_t>((size_t)cfg.nwaves * cfg.bw);
-        out_max = a.template take<double>(4);
-        out_arg = a.template take<int64_t>(4);
-        total = a.template take<int64_t>(4);
-        cvec = a.template take<double>((size_t)d + 8);
-    }
-};
-
-size_t scan_bytes(int64_t m, int d) {
-    ScanBufs b;
-    b.setup(m, d);
-    Sizer s;
-    b.carve(s);
-    return s.off;
-}
-
-// max_i (r_i + ||c - c_i|| - r) with its smallest argmax, and the ascending
-// list of {i : r_i + ||c - c_i|| - r > eps} (first viol_cap entries).
+// synchronous wrappers of the scans for the public entry points
 int run_check(const void* C, const void* R, int64_t m, int d, int dtype, double r, const double* c_host, double eps,
               ScanBufs& b, double* dmax, int64_t* argmax, int64_t* viol_idx, int64_t viol_cap, int64_t* n_viol,
               hipStream_t s) {
-    HIPCHK(hipMemcpyAsync(b.cvec, c_host, sizeof(double) * d, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_scan(0, C, R, m, d, dtype, b.cvec, r, eps, nullptr, nullptr, nullptr, b.cfg, b.wmax, b.warg, b.wcnt,
-                       b.seg, s));
-    HIPCHK(launch_scan_finalize(b.wcnt, b.wmax, b.warg, b.cfg.nwaves, b.offs, b.total, b.out_max, b.out_arg, s));
-    if (viol_idx && viol_cap > 0)
-        HIPCHK(launch_scan_copy(b.seg, b.wcnt, b.offs, b.cfg.nwaves, b.cfg.bw, viol_idx, viol_cap, s));
-    double* h = g_pin.get(3);
+    double* h = g_pin.get((size_t)d + 8);
     if (!h) return fail(MEB_ERR_HIP, "pinned host allocation failed");
-    HIPCHK(hipMemcpyAsync(h, b.out_max, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(h + 1, b.out_arg, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(h + 2, b.total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    memcpy(h + 8, c_host, sizeof(double) * d);
+    HIPCHK(hipMemcpyAsync(b.cvec, h + 8, sizeof(double) * d, hipMemcpyHostToDevice, s));
+    CHK(enq_check(C, R, m, d, dtype, r, b.cvec, eps, b, viol_idx, viol_cap, h, s));
     HIPCHK(hipStreamSynchronize(s));
     if (dmax) *dmax = h[0];
-    int64_t a, n;
-    memcpy(&a, h + 1, 8);
-    memcpy(&n, h + 2, 8);
-    if (argmax) *argmax = a;
-    if (n_viol) *n_viol = n;
+    if (argmax) *argmax = word_i64(h + 1);
+    if (n_viol) *n_viol = word_i64(h + 2);
     return MEB_OK;
 }
 
 int run_screen(const void* C, const void* R, int64_t m, int d, int dtype, double r, const double* c_host, double tol,
                ScanBufs& b, int64_t* keep_idx, int64_t* n_keep, double* slack, hipStream_t s) {
-    HIPCHK(hipMemcpyAsync(b.cvec, c_host, sizeof(double) * d, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_scan(1, C, R, m, d, dtype, b.cvec, r, tol, slack, nullptr, nullptr, b.cfg, nullptr, nullptr, b.wcnt,
-                       b.seg, s));
-    HIPCHK(launch_scan_finalize(b.wcnt, nullptr, nullptr, b.cfg.nwaves, b.offs, b.total, nullptr, nullptr, s));
-    HIPCHK(launch_scan_copy(b.seg, b.wcnt, b.offs, b.cfg.nwaves, b.cfg.bw, keep_idx, m, s));
-    double* h = g_pin.get(1);
+    double* h = g_pin.get((size_t)d + 8);
     if (!h) return fail(MEB_ERR_HIP, "pinned host allocation failed");
-    HIPCHK(hipMemcpyAsync(h, b.total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    memcpy(h + 8, c_host, sizeof(double) * d);
+    HIPCHK(hipMemcpyAsync(b.cvec, h + 8, sizeof(double) * d, hipMemcpyHostToDevice, s));
+    CHK(enq_screen(C, R, m, d, dtype, r, b.cvec, tol, b, keep_idx, slack, h, s));
     HIPCHK(hipStreamSynchronize(s));
-    int64_t n;
-    memcpy(&n, h, 8);
-    *n_keep = n;
+    *n_keep = word_i64(h + 2);
     return MEB_OK;
 }
 
-// FP32 copy shifted by `origin` (device, d) and L = max_i ||c_i - origin|| + r_i.
-int run_prepare(const double* C, const double* R, int64_t m, int d, const double* origin_dev, float* C32, float* R32,
-                ScanBufs& b, double* L, hipStream_t s) {
-    HIPCHK(launch_scan(2, C, R, m, d, MEB_F64, origin_dev, 0.0, 0.0, nullptr, C32, R32, b.cfg, b.wmax, b.warg,
-                       nullptr, nullptr, s));
-    HIPCHK(launch_scan_finalize(nullptr, b.wmax, b.warg, b.cfg.nwaves, nullptr, nullptr, b.out_max, b.out_arg, s));
-    double* h = g_pin.get(1);
-    if (!h) return fail(MEB_ERR_HIP, "pinned host allocation failed");
-    HIPCHK(hipMemcpyAsync(h, b.out_max, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    *L = h[0];
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Job
+// ---------------------------------------------------------------------------
+constexpr double EPS64 = 2.220446049250313e-16;
+constexpr double START_MARGIN = 0x1p-10;  // relative margin of the starting radius above L
+constexpr double EPS32 = 5.9604644775390625e-08;
+
+Job::~Job() {
+    if (viol_h) (void)hipHostFree(viol_h);
+    if (keep_pin) (void)hipHostFree(keep_pin);
+}
+
+int Job::init(const void* C_, const void* R_, int64_t m_, int d_, const meb_options* o_, void* ws, size_t ws_bytes,
+              double* pin_base, double* U_out_, double* V_out_) {
+    C = C_;
+    R = R_;
+    m = m_;
+    d = d_;
+    o = *o_;
+    U_out = U_out_;
+    V_out = V_out_;
+    w.setup(m, d, &o);
+    Arena ar{(char*)ws, ws_bytes, 0};
+    w.carve(ar, m, d, &o, R != nullptr);
+    if (!ar.ok()) return fail(MEB_ERR_WORKSPACE, "workspace too small");
+    pin.carve(pin_base, d);
+    memset(&st, 0, sizeof(st));
+    ph = JobPhase::Start;
+    t_start = now_ms();
     return MEB_OK;
 }
 
-// ---------------------------------------------------------------------------
-// One ripALM run on (C, R) with multipliers (U, V) in `dtype`.
-// ---------------------------------------------------------------------------
-struct RunParams {
-    double L;
-    double sigma_raw;  // first penalty of this run
-    double tau_raw;
-    double tol;
-    double eps;
-    const meb_options* o;
-};
+int Job::start(hipStream_t s) {
+    // scale L = max_i ||c_i - c_1|| + r_i around the first center (read on
+    // the device from row 0), and in mixed mode the shifted FP32 copy
+    t_mark = now_ms();
+    const double* c1_dev = static_cast<const double*>(C);
+    if (o.mode == MEB_MODE_MIXED)
+        CHK(enq_prepare((const double*)C, (const double*)R, m, d, c1_dev, w.C32, w.R32, w.scan, pin.scal, s));
+    else
+        CHK(enq_check(C, R, m, d, MEB_F64, 0.0, c1_dev, INFINITY, w.scan, nullptr, 0, pin.scal, s));
+    HIPCHK(hipMemcpyAsync(pin.c1, C, sizeof(double) * d, hipMemcpyDeviceToHost, s));
+    ph = JobPhase::WaitPrep;
+    return MEB_OK;
+}
 
-struct RunResult {
-    std::vector<double> x;  // d + 1
-    double sigma_end;       // raw
-    int outer, inner, passes, status;
-    double kkt;
-    double pass_ms = 0, pass_bytes = 0;
-    int launches = 0;
-    double sumk = 0, maxk = 0;
-};
-
-int run_ripalm(Engine& e, const void* C, const void* R, void* U, void* V, const double* x0, const RunParams& p,
-               RunResult& out, hipStream_t s) {
-    const int n1 = e.d + 1;
-    const meb_options* o = p.o;
-    std::vector<double> h(e.sl.len, 0.0);
+int Job::begin_run(int id, Engine& eng, const void* Cr, const void* Rr, void* U, void* V, const double* x0,
+                   double sigma_raw, double tol, double eps, hipStream_t s) {
+    const int n1 = d + 1;
+    const StateLayout& sl = eng.sl;
+    double* h = pin.init;
+    memset(h, 0, sizeof(double) * sl.H);
     h[S_MODE] = PM_EVAL;
-    h[S_SIGMA] = p.sigma_raw;
-    h[S_SIGMA_NEXT] = std::min(p.sigma_raw * o->sigma_growth, o->sigma_max / p.L);
-    h[S_TAU] = p.tau_raw;
-    h[S_L] = p.L;
-    h[S_RHO] = o->rho;
-    h[S_TOL] = p.tol;
-    h[S_GROWTH] = o->sigma_growth;
-    h[S_SIGMA_MAX] = o->sigma_max / p.L;
-    h[S_MAX_OUTER] = o->max_outer;
-    h[S_MAX_INNER] = o->max_inner;
-    h[S_MAX_LS] = o->max_ls;
-    h[S_STALL_OUTER] = o->stall_outer;
-    h[S_EPS] = p.eps;
+    h[S_SIGMA] = sigma_raw;
+    h[S_SIGMA_NEXT] = std::min(sigma_raw * o.sigma_growth, o.sigma_max / L);
+    h[S_TAU] = tau_raw;
+    h[S_L] = L;
+    h[S_RHO] = o.rho;
+    h[S_TOL] = tol;
+    h[S_GROWTH] = o.sigma_growth;
+    h[S_SIGMA_MAX] = o.sigma_max / L;
+    h[S_MAX_OUTER] = o.max_outer;
+    h[S_MAX_INNER] = o.max_inner;
+    h[S_MAX_LS] = o.max_ls;
+    h[S_STALL_OUTER] = o.stall_outer;
+    h[S_EPS] = eps;
     h[S_BEST_KKT] = INFINITY;
-    h[S_VERBOSE] = o->verbose;
+    h[S_VERBOSE] = o.verbose;
     for (int k = 0; k < n1; ++k) {
-        h[e.sl.xb + k] = x0[k];
-        h[e.sl.xbar + k] = x0[k];
-        h[e.sl.ab + k] = x0[k];
+        h[sl.xb + k] = x0[k];
+        h[sl.xbar + k] = x0[k];
+        h[sl.ab + k] = x0[k];
     }
-    HIPCHK(hipMemcpyAsync(e.state, h.data(), sizeof(double) * e.sl.len, hipMemcpyHostToDevice, s));
-    PassArgs a = e.args(C, R, U, V);
-    double* hs = g_pin.get(S_NSCALAR);
-    if (!hs) return fail(MEB_ERR_HIP, "pinned host allocation failed");
-    const int batch = 4;
-    const int64_t max_steps = (int64_t)o->max_outer * (o->max_inner + o->max_ls + 2) + 16;
-    int64_t steps = 0;
-    int last_k = -1;
-    const bool prof = o->profile != 0;
-    size_t nev = 0;
-    for (;;) {
-        for (int b = 0; b < batch; ++b) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (prof) {
-                e0 = g_events.at(nev);
-                e1 = g_events.at(nev + 1);
-                if (!e0 || !e1) return fail(MEB_ERR_HIP, "hipEventCreate failed");
-                nev += 2;
-            }
-            CHK(e.step(a, true, s, e0, e1));
-        }
-        steps += batch;
-        HIPCHK(hipMemcpyAsync(hs, e.state, sizeof(double) * S_NSCALAR, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (o->verbose && (int)hs[S_K] != last_k) {
-            last_k = (int)hs[S_K];
-            fprintf(stderr, "[meb] k=%d sigma=%.3e kkt=%.3e passes=%d newton=%d\n", (int)hs[S_K], hs[S_SIGMA],
-                    hs[S_KKT], (int)hs[S_NPASS], (int)hs[S_NINNER]);
-        }
-        if ((int)hs[S_MODE] == PM_DONE) break;
-        if (steps > max_steps) {
-            hs[S_STATUS] = 2.0;
-            break;
-        }
-    }
-    out.x.resize(n1);
-    HIPCHK(hipMemcpyAsync(g_pin.get(S_NSCALAR + n1) + S_NSCALAR, e.state + e.sl.xb, sizeof(double) * n1,
-                          hipMemcpyDeviceToHost, s));
-    double* hh = g_pin.get(S_NSCALAR + n1);
-    HIPCHK(hipMemcpyAsync(hh, e.state, sizeof(double) * S_NSCALAR, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int k = 0; k < n1; ++k) out.x[k] = hh[S_NSCALAR + k];
-    out.sigma_end = hh[S_SIGMA];
-    out.outer = (int)hh[S_K];
-    out.inner = (int)hh[S_NINNER];
-    out.passes = (int)hh[S_NPASS];
-    out.kkt = hh[S_KKT];
-    out.status = (int)hh[S_STATUS];
-    out.pass_bytes = hh[S_BYTES];
-    out.sumk = hh[S_SUMK];
-    out.maxk = hh[S_MAXK];
-    if (prof) {
-        double ms = 0;
-        for (size_t k = 0; k + 1 < nev; k += 2) {
-            float t = 0.f;
-            HIPCHK(hipEventElapsedTime(&t, g_events.at(k), g_events.at(k + 1)));
-            ms += t;
-        }
-        out.pass_ms = ms;
-        out.launches = (int)(nev / 2);
-    }
-    if (out.status < 0) return fail(MEB_ERR_NUMERIC, "Newton system not positive definite");
-    for (int k = 0; k < n1; ++k)
-        if (!std::isfinite(out.x[k])) return fail(MEB_ERR_NUMERIC, "non-finite iterate");
+    // H is assembled before any Newton step reads it
+    HIPCHK(hipMemcpyAsync(eng.state, h, sizeof(double) * sl.H, hipMemcpyHostToDevice, s));
+    pa = eng.args(Cr, Rr, U, V);
+    e = &eng;
+    run_id = id;
+    steps = 0;
+    max_steps = (int64_t)o.max_outer * (o.max_inner + o.max_ls + 2) + 16;
+    forced_end = false;
+    run_pass_ms = 0;
+    run_launches = 0;
+    last_k = -1;
+    t_run = now_ms();
+    ph = JobPhase::Run;
     return MEB_OK;
 }
 
-// ---------------------------------------------------------------------------
-// meb_solve workspace
-// ---------------------------------------------------------------------------
-struct SolveWs {
-    Engine e32, e64;   // FP32 run on all m; FP64 run (all m, or the reduced set)
-    ScanBufs scan;
-    float* C32 = nullptr;
-    float* R32 = nullptr;
-    float* U32 = nullptr;
-    float* V32 = nullptr;
-    double* U64 = nullptr;
-    double* V64 = nullptr;
-    double* Cred = nullptr;
-    double* Rred = nullptr;
-    int64_t* keep = nullptr;  // retained indices (device)
-    int64_t* viol = nullptr;  // violated indices (device)
-    double* orig = nullptr;   // d
-    void setup(int64_t m, int d, const meb_options* o) {
-        e64.setup(m, d, MEB_F64);
-        if (o->mode == MEB_MODE_MIXED) e32.setup(m, d, MEB_F32);
-        scan.setup(m, d);
+int Job::end_run(hipStream_t s) {
+    // the scalar header and the iterate are contiguous in the state
+    HIPCHK(hipMemcpyAsync(pin.hdr, e->state, sizeof(double) * (S_NSCALAR + d + 1), hipMemcpyDeviceToHost, s));
+    ph = JobPhase::WaitRunEnd;
+    return MEB_OK;
+}
+
+int Job::screen(hipStream_t s) {
+    // FP32 copy, FP64 arithmetic; coordinates shifted by c_1
+    for (int k = 0; k < d; ++k) pin.cvec[k] = x1[1 + k];
+    HIPCHK(hipMemcpyAsync(w.scan.cvec, pin.cvec, sizeof(double) * d, hipMemcpyHostToDevice, s));
+    CHK(enq_screen(w.C32, R ? (const void*)w.R32 : nullptr, m, d, MEB_F32, x1[0], w.scan.cvec, tol_red, w.scan, w.keep,
+                   nullptr, pin.scal, s));
+    ph = JobPhase::WaitScreen;
+    return MEB_OK;
+}
+
+int Job::start_fp64_reduced(hipStream_t s) {
+    // the FP64 engine was carved for m balls; re-carve it for the reduced
+    // size inside the same region (the carving grows with m)
+    Engine& eng = w.e64;
+    char* region = (char*)eng.state;
+    const size_t region_bytes = engine_bytes(m, d, MEB_F64);
+    if (engine_bytes(n_red, d, MEB_F64) > region_bytes) return fail(MEB_ERR_WORKSPACE, "reduced engine does not fit");
+    eng.setup(n_red, d, MEB_F64);
+    Arena sub{region, region_bytes, 0};
+    eng.carve(sub);
+    return begin_run(1, eng, w.Cred, R ? (const void*)w.Rred : nullptr, w.U64, w.V64, xw.data(), sigma_w, o.tol_kkt,
+                     EPS64, s);
+}
+
+int Job::check(hipStream_t s) {
+    // full FP64 check: reach_i = r_i + ||c - c_i||; violated if reach_i - rbar > eps
+    t_check = now_ms();
+    const double eps_feas = o.eps_feas_rel * (1.0 + xw[0]);
+    for (int k = 0; k < d; ++k) pin.cvec[k] = xw[1 + k];
+    HIPCHK(hipMemcpyAsync(w.scan.cvec, pin.cvec, sizeof(double) * d, hipMemcpyHostToDevice, s));
+    CHK(enq_check(C, R, m, d, MEB_F64, 0.0, w.scan.cvec, xw[0] + eps_feas, w.scan, w.viol, m, pin.scal, s));
+    ph = JobPhase::WaitCheck;
+    return MEB_OK;
+}
+
+int Job::finish_mixed(hipStream_t s) {
+    st.ms_phase[2] = tr_total;
+    st.ms_phase[3] = tc_total;
+    st.reinsert_rounds = rounds;
+    st.n_red = n_red;
+    xfin = xw;
+    if (U_out || V_out) {
+        if (U_out) HIPCHK(launch_fill_f64(U_out, 0.0, m, s));
+        if (V_out) HIPCHK(launch_fill_f64(V_out, 0.0, m * (int64_t)d, s));
+        HIPCHK(launch_scatter_mult(w.U64, w.V64, w.keep, n_red, d, U_out, V_out, s));
     }
-    template <typename A>
-    void carve(A& a, int64_t m, int d, const meb_options* o, bool has_r) {
-        e64.carve(a);
-        scan.carve(a);
-        U64 = a.template take<double>((size_t)m);
-        V64 = a.template take<double>((size_t)m * d);
-        orig = a.template take<double>((size_t)d + 8);
-        if (o->mode == MEB_MODE_MIXED) {
-            e32.carve(a);
-            C32 = a.template take<float>((size_t)m * d);
-            R32 = has_r ? a.template take<float>((size_t)m) : nullptr;
-            U32 = a.template take<float>((size_t)m);
-            V32 = a.template take<float>((size_t)m * d);
-            Cred = a.template take<double>((size_t)m * d);
-            Rred = a.template take<double>((size_t)m);
-            keep = a.template take<int64_t>((size_t)m);
-            viol = a.template take<int64_t>((size_t)m);
+    finish();
+    return MEB_OK;
+}
+
+void Job::finish() {
+    // fix-up: the returned radius encloses every ball
+    st.rbar = xfin[0];
+    st.delta_max = mreach - xfin[0];
+    r_out = std::max(xfin[0], mreach);
+    st.status = status;
+    ph = JobPhase::Done;
+}
+
+int Job::on_ready(hipStream_t s) {
+    const int n1 = d + 1;
+    switch (ph) {
+        case JobPhase::WaitPrep: {
+            L = pin.scal[0];
+            c1.assign(pin.c1, pin.c1 + d);
+            st.L = L;
+            if (!std::isfinite(L)) return fail(MEB_ERR_NUMERIC, "non-finite input");
+            if (!(L > 0)) {
+                // every ball is the point c_1
+                xfin.assign(n1, 0.0);
+                for (int k = 0; k < d; ++k) xfin[1 + k] = c1[k];
+                mreach = 0.0;
+                if (U_out) HIPCHK(launch_fill_f64(U_out, 0.0, m, s));
+                if (V_out) HIPCHK(launch_fill_f64(V_out, 0.0, m * (int64_t)d, s));
+                if (U_out) {
+                    pin.scal[7] = 1.0;
+                    HIPCHK(hipMemcpyAsync(U_out, pin.scal + 7, sizeof(double), hipMemcpyHostToDevice, s));
+                }
+                finish();
+                return MEB_OK;
+            }
+            tau_raw = o.tau / (L * L);
+            sigma0_raw = o.sigma0 / L;
+            // start a little above L: at (L, c_1) the ball attaining L sits
+            // exactly on the boundary between the polar and the third
+            // projection case, where rounding would pick the Jacobian
+            std::vector<double> x0(n1, 0.0);
+            x0[0] = L * (1.0 + START_MARGIN);
+            if (o.mode == MEB_MODE_FP64) {
+                HIPCHK(launch_fill_f64(w.U64, 0.0, m, s));
+                for (int k = 0; k < d; ++k) x0[1 + k] = c1[k];
+                return begin_run(1, w.e64, C, R, w.U64, w.V64, x0.data(), sigma0_raw, o.tol_kkt, EPS64, s);
+            }
+            // FP32 run on all m balls, shifted by c_1
+            HIPCHK(launch_fill_bytes_zero(w.U32, sizeof(float) * (size_t)m, s));
+            return begin_run(0, w.e32, w.C32, R ? (const void*)w.R32 : nullptr, w.U32, w.V32, x0.data(), sigma0_raw,
+                             o.tol_kkt_low, EPS32, s);
+        }
+        case JobPhase::WaitRunEnd: {
+            const double* hh = pin.hdr;
+            std::vector<double> x(pin.x, pin.x + n1);
+            int rstatus = (int)hh[S_STATUS];
+            if (forced_end && (int)hh[S_MODE] != PM_DONE) rstatus = 2;
+            const int r = run_id;
+            if (r == 0) {
+                st.outer[0] = (int)hh[S_K];
+                st.inner[0] = (int)hh[S_NINNER];
+                st.passes[0] = (int)hh[S_NPASS];
+                st.kkt[0] = hh[S_KKT];
+                st.pass_ms[0] = run_pass_ms;
+                st.pass_bytes[0] = hh[S_BYTES];
+                st.pass_launches[0] = run_launches;
+                st.mid_rows[0] = hh[S_SUMK];
+                st.mid_rows_max[0] = hh[S_MAXK];
+            } else {
+                st.outer[1] += (int)hh[S_K];
+                st.inner[1] += (int)hh[S_NINNER];
+                st.passes[1] += (int)hh[S_NPASS];
+                st.kkt[1] = hh[S_KKT];
+                st.pass_ms[1] += run_pass_ms;
+                st.pass_bytes[1] += hh[S_BYTES];
+                st.pass_launches[1] += run_launches;
+                st.mid_rows[1] += hh[S_SUMK];
+                st.mid_rows_max[1] = std::max(st.mid_rows_max[1], hh[S_MAXK]);
+            }
+            if (rstatus < 0) return fail(MEB_ERR_NUMERIC, "Newton system not positive definite");
+            for (int k = 0; k < n1; ++k)
+                if (!std::isfinite(x[k])) return fail(MEB_ERR_NUMERIC, "non-finite iterate");
+            if (r == 0) {
+                x1 = x;
+                sigma1 = hh[S_SIGMA];
+                st.ms_phase[0] = now_ms() - t_mark;
+                t_mark = now_ms();
+                tol_red = o.tol_red * L;
+                screen_tries = 0;
+                return screen(s);
+            }
+            if (rstatus != 1) status = MEB_WARN_MAXITER;
+            if (o.mode == MEB_MODE_FP64) {
+                st.ms_phase[2] = now_ms() - t_run;
+                st.n_red = m;
+                xfin = x;
+                if (U_out || V_out) HIPCHK(launch_dense_mult(w.U64, w.V64, MEB_F64, m, d, U_out, V_out, s));
+                fixup_only = true;
+                t_check = now_ms();
+                for (int k = 0; k < d; ++k) pin.cvec[k] = xfin[1 + k];
+                HIPCHK(hipMemcpyAsync(w.scan.cvec, pin.cvec, sizeof(double) * d, hipMemcpyHostToDevice, s));
+                CHK(enq_check(C, R, m, d, MEB_F64, 0.0, w.scan.cvec, INFINITY, w.scan, nullptr, 0, pin.scal, s));
+                ph = JobPhase::WaitCheck;
+                return MEB_OK;
+            }
+            tr_total += now_ms() - t_run;
+            xw = x;
+            sigma_w = hh[S_SIGMA];
+            return check(s);
+        }
+        case JobPhase::WaitScreen: {
+            n_red = word_i64(pin.scal + 2);
+            if (n_red == 0) {
+                if (++screen_tries >= 8) return fail(MEB_ERR_NUMERIC, "screening retained no ball");
+                tol_red = tol_red < 0 ? 0.0 : std::max(4.0 * tol_red, 1e-6 * L);
+                return screen(s);
+            }
+            // gather retained rows (FP64 data) and the FP32 multipliers as warm start
+            HIPCHK(launch_gather(C, R, nullptr, nullptr, MEB_F64, w.keep, n_red, d, w.Cred, R ? w.Rred : nullptr,
+                                 nullptr, nullptr, s));
+            HIPCHK(launch_gather(nullptr, nullptr, w.U32, w.V32, MEB_F32, w.keep, n_red, d, nullptr, nullptr, w.U64,
+                                 w.V64, s));
+            st.ms_phase[1] = now_ms() - t_mark;
+            xw.assign(n1, 0.0);
+            xw[0] = x1[0];
+            for (int k = 0; k < d; ++k) xw[1 + k] = c1[k] + x1[1 + k];
+            sigma_w = sigma1;
+            rounds = 0;
+            keep_h.clear();
+            keep_sorted.clear();
+            return start_fp64_reduced(s);
+        }
+        case JobPhase::WaitCheck: {
+            const double mr = pin.scal[0];
+            if (fixup_only) {
+                mreach = mr;
+                st.ms_phase[3] += now_ms() - t_check;
+                finish();
+                return MEB_OK;
+            }
+            tc_total += now_ms() - t_check;
+            n_viol = word_i64(pin.scal + 2);
+            st.delta_max = mr - xw[0];
+            mreach = mr;
+            if (n_viol == 0 || rounds >= o.max_reinsert) return finish_mixed(s);
+            // new violators not yet retained: bring both lists to the host
+            CHK(grow_pinned(viol_h, viol_cap, (size_t)n_viol));
+            HIPCHK(hipMemcpyAsync(viol_h, w.viol, sizeof(int64_t) * n_viol, hipMemcpyDeviceToHost, s));
+            if (keep_h.empty()) {
+                CHK(grow_pinned(keep_pin, keep_cap, (size_t)n_red));
+                HIPCHK(hipMemcpyAsync(keep_pin, w.keep, sizeof(int64_t) * n_red, hipMemcpyDeviceToHost, s));
+            }
+            ph = JobPhase::WaitViol;
+            return MEB_OK;
+        }
+        case JobPhase::WaitViol: {
+            if (keep_h.empty()) {
+                keep_h.assign(keep_pin, keep_pin + n_red);
+                keep_sorted = keep_h;  // screening output is ascending
+            }
+            std::vector<int64_t> add;
+            std::set_difference(viol_h, viol_h + n_viol, keep_sorted.begin(), keep_sorted.end(),
+                                std::back_inserter(add));
+            if (add.empty()) return finish_mixed(s);
+            rounds++;
+            // append the new balls at the end of the reduced problem (zero multipliers)
+            const int64_t na = (int64_t)add.size();
+            memcpy(viol_h, add.data(), sizeof(int64_t) * na);
+            HIPCHK(hipMemcpyAsync(w.viol, viol_h, sizeof(int64_t) * na, hipMemcpyHostToDevice, s));
+            HIPCHK(launch_gather(C, R, nullptr, nullptr, MEB_F64, w.viol, na, d, w.Cred + (size_t)n_red * d,
+                                 R ? w.Rred + n_red : nullptr, nullptr, nullptr, s));
+            HIPCHK(launch_fill_f64(w.U64 + n_red, 0.0, na, s));
+            keep_h.insert(keep_h.end(), add.begin(), add.end());
+            {
+                std::vector<int64_t> ms;
+                ms.reserve(keep_sorted.size() + add.size());
+                std::merge(keep_sorted.begin(), keep_sorted.end(), add.begin(), add.end(), std::back_inserter(ms));
+                keep_sorted.swap(ms);
+            }
+            CHK(grow_pinned(keep_pin, keep_cap, keep_h.size()));
+            memcpy(keep_pin, keep_h.data(), sizeof(int64_t) * keep_h.size());
+            HIPCHK(hipMemcpyAsync(w.keep, keep_pin, sizeof(int64_t) * keep_h.size(), hipMemcpyHostToDevice, s));
+            n_red += na;
+            return start_fp64_reduced(s);
+        }
+        default:
+            return fail(MEB_ERR_ARG, "job is not waiting for a readback");
+    }
+}
+
+int drive_sync(Job& j, hipStream_t s) {
+    CHK(j.start(s));
+    const bool prof = j.o.profile != 0;
+    size_t nev = 0;
+    while (!j.done()) {
+        if (j.stepping()) {
+            const int batch = 4;
+            for (int b = 0; b < batch; ++b) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (prof) {
+                    e0 = g_events.at(nev);
+                    e1 = g_events.at(nev + 1);
+                    if (!e0 || !e1) return fail(MEB_ERR_HIP, "hipEventCreate failed");
+                    nev += 2;
+                }
+                CHK(j.e->step(j.pa, true, s, e0, e1));
+            }
+            j.steps += batch;
+            HIPCHK(hipMemcpyAsync(j.pin.hdr, j.e->state, sizeof(double) * S_NSCALAR, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const double* hs = j.pin.hdr;
+            if (j.o.verbose && (int)hs[S_K] != j.last_k) {
+                j.last_k = (int)hs[S_K];
+                fprintf(stderr, "[meb] k=%d sigma=%.3e kkt=%.3e passes=%d newton=%d\n", (int)hs[S_K], hs[S_SIGMA],
+                        hs[S_KKT], (int)hs[S_NPASS], (int)hs[S_NINNER]);
+            }
+            const bool ended = (int)hs[S_MODE] == PM_DONE;
+            if (ended || j.steps > j.max_steps) {
+                if (prof) {
+                    double ms = 0;
+                    for (size_t k = 0; k + 1 < nev; k += 2) {
+                        float t = 0.f;
+                        HIPCHK(hipEventElapsedTime(&t, g_events.at(k), g_events.at(k + 1)));
+                        ms += t;
+                    }
+                    j.run_pass_ms = ms;
+                    j.run_launches = (int)(nev / 2);
+                    nev = 0;
+                }
+                j.forced_end = !ended;
+                CHK(j.end_run(s));
+            }
+        } else {
+            HIPCHK(hipStreamSynchronize(s));
+            CHK(j.on_ready(s));
         }
     }
-};
+    HIPCHK(hipStreamSynchronize(s));
+    return MEB_OK;
+}
 
 int check_common(const void* C, int64_t m, int32_t d, int32_t dtype) {
     if (!C) return fail(MEB_ERR_ARG, "C is NULL");
@@ -524,12 +701,17 @@ int check_common(const void* C, int64_t m, int32_t d, int32_t dtype) {
     return MEB_OK;
 }
 
-double now_ms() {
-    using namespace std::chrono;
-    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+int check_solve_options(const meb_options* o) {
+    if (!(o->rho >= 0 && o->rho < 1)) return fail(MEB_ERR_ARG, "rho must be in [0, 1)");
+    if (!(o->sigma0 > 0) || !(o->tau > 0) || !(o->sigma_growth >= 1) || !(o->sigma_max >= o->sigma0))
+        return fail(MEB_ERR_ARG, "bad sigma / tau options");
+    if (o->mode != MEB_MODE_FP64 && o->mode != MEB_MODE_MIXED) return fail(MEB_ERR_ARG, "bad mode");
+    return MEB_OK;
 }
 
-}  // namespace
+}  // namespace meb
+
+using namespace meb;
 
 // ===========================================================================
 // C ABI
@@ -559,7 +741,7 @@ int meb_default_options(meb_options* o) {
     return MEB_OK;
 }
 
-const char* meb_last_error(void) { return g_err.c_str(); }
+const char* meb_last_error(void) { return last_error_text(); }
 
 int meb_workspace_size(int64_t m, int32_t d, int32_t dtype, const meb_options* opts, size_t* bytes) {
     if (!bytes) return fail(MEB_ERR_ARG, "bytes is NULL");
@@ -567,12 +749,7 @@ int meb_workspace_size(int64_t m, int32_t d, int32_t dtype, const meb_options* o
     if (dtype != MEB_F64 && dtype != MEB_F32) return fail(MEB_ERR_ARG, "bad dtype");
     meb_options def;
     meb_default_options(&def);
-    const meb_options* o = opts ? opts : &def;
-    SolveWs w;
-    w.setup(m, d, o);
-    Sizer s;
-    w.carve(s, m, d, o, true);
-    *bytes = s.off + ALIGN;
+    *bytes = solve_ws_bytes(m, d, opts ? opts : &def);
     return MEB_OK;
 }
 
@@ -631,7 +808,7 @@ int meb_al_eval(const void* C, const void* R, const void* U, const void* V, int6
     a.dense_vout = 1;
     a.want_mid = (want & MEB_WANT_HESS) ? 1 : 0;
     for (int l = 0; l < NT; ++l) a.etas[l] = (l < n_eta) ? etas[l] : 0.0;
-    HIPCHK(launch_pass(a, e.pc, a.want_kkt ? 1 : 0, s));
+    HIPCHK(launch_pass(a, e.pc, s));
     HIPCHK(launch_reduce_records(e.rec, e.pc.blocks, e.rl.len, (int64_t)e.pc.waves_per_block * e.rl.len, e.red, s));
     if (want & MEB_WANT_HESS) {
         HIPCHK(launch_mid_compact(e.mid_cnt, e.pc.nwaves, e.pc.bw, e.mid_idx, e.mid_coef, e.list_offs, e.list_total,
@@ -726,11 +903,17 @@ int meb_prepare_f32(const double* C, const double* R, int64_t m, int32_t d, cons
     b.setup(m, d);
     Arena ar{(char*)ws, ws_bytes, 0};
     b.carve(ar);
-    if (origin) HIPCHK(hipMemcpyAsync(b.cvec, origin, sizeof(double) * d, hipMemcpyHostToDevice, s));
-    else HIPCHK(launch_fill_f64(b.cvec, 0.0, d, s));
-    double L = 0.0;
-    CHK(run_prepare(C, R, m, d, b.cvec, C32, R32, b, &L, s));
-    if (L_out) *L_out = L;
+    double* h = g_pin.get((size_t)d + 8);
+    if (!h) return fail(MEB_ERR_HIP, "pinned host allocation failed");
+    if (origin) {
+        memcpy(h + 8, origin, sizeof(double) * d);
+        HIPCHK(hipMemcpyAsync(b.cvec, h + 8, sizeof(double) * d, hipMemcpyHostToDevice, s));
+    } else {
+        HIPCHK(launch_fill_f64(b.cvec, 0.0, d, s));
+    }
+    CHK(enq_prepare(C, R, m, d, b.cvec, C32, R32, b, h, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (L_out) *L_out = h[0];
     return MEB_OK;
 }
 
@@ -768,237 +951,22 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
     meb_options def;
     meb_default_options(&def);
     const meb_options* o = opts ? opts : &def;
-    if (!(o->rho >= 0 && o->rho < 1)) return fail(MEB_ERR_ARG, "rho must be in [0, 1)");
-    if (!(o->sigma0 > 0) || !(o->tau > 0) || !(o->sigma_growth >= 1) || !(o->sigma_max >= o->sigma0))
-        return fail(MEB_ERR_ARG, "bad sigma / tau options");
-    if (o->mode != MEB_MODE_FP64 && o->mode != MEB_MODE_MIXED) return fail(MEB_ERR_ARG, "bad mode");
+    CHK(check_solve_options(o));
     if (dtype != MEB_F64) return fail(MEB_ERR_ARG, "meb_solve needs FP64 input");
     size_t need;
     CHK(meb_workspace_size(m, d, dtype, o, &need));
     if (!ws || ws_bytes < need) return fail(MEB_ERR_WORKSPACE, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
-    const int n1 = d + 1;
-    meb_stats st;
-    memset(&st, 0, sizeof(st));
-    SolveWs w;
-    w.setup(m, d, o);
-    Arena ar{(char*)ws, ws_bytes, 0};
-    w.carve(ar, m, d, o, R != nullptr);
-
-    // origin c_1 and scale L = max_i ||c_i - c_1|| + r_i
-    std::vector<double> c1(d);
-    HIPCHK(hipMemcpyAsync(c1.data(), C, sizeof(double) * d, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    double L = 0.0;
-    double t0 = now_ms();
-    if (o->mode == MEB_MODE_MIXED) {
-        HIPCHK(hipMemcpyAsync(w.orig, c1.data(), sizeof(double) * d, hipMemcpyHostToDevice, s));
-        CHK(run_prepare((const double*)C, (const double*)R, m, d, w.orig, w.C32, w.R32, w.scan, &L, s));
-    } else {
-        double dm;
-        int64_t am, nv;
-        CHK(run_check(C, R, m, d, dtype, 0.0, c1.data(), INFINITY, w.scan, &dm, &am, nullptr, 0, &nv, s));
-        L = dm;
-    }
-    st.L = L;
-    if (!std::isfinite(L)) return fail(MEB_ERR_NUMERIC, "non-finite input");
-    std::vector<double> xfin(n1);
-    double mreach_mixed = -INFINITY;  // max reach at xfin, when the mixed path already computed it
-    int status = MEB_OK;
-    if (!(L > 0)) {
-        // every ball is the point c_1
-        xfin[0] = 0.0;
-        for (int k = 0; k < d; ++k) xfin[1 + k] = c1[k];
-        if (U_out) HIPCHK(launch_fill_f64(U_out, 0.0, m, s));
-        if (V_out) HIPCHK(launch_fill_f64(V_out, 0.0, m * (int64_t)d, s));
-        if (U_out) {
-            const double one = 1.0;
-            HIPCHK(hipMemcpyAsync(U_out, &one, sizeof(double), hipMemcpyHostToDevice, s));
-        }
-        HIPCHK(hipStreamSynchronize(s));
-        *r_out = 0.0;
-        memcpy(c_out, c1.data(), sizeof(double) * d);
-        st.ms_total = now_ms() - t_start;
-        if (stats) *stats = st;
-        return MEB_OK;
-    }
-    const double tau_raw = o->tau / (L * L);
-    const double sigma0_raw = o->sigma0 / L;
-
-    if (o->mode == MEB_MODE_FP64) {
-        HIPCHK(launch_fill_f64(w.U64, 0.0, m, s));
-        std::vector<double> x0(n1);
-        x0[0] = L;
-        for (int k = 0; k < d; ++k) x0[1 + k] = c1[k];
-        RunParams p{L, sigma0_raw, tau_raw, o->tol_kkt, 2.220446049250313e-16, o};
-        RunResult rr;
-        const double tr = now_ms();
-        CHK(run_ripalm(w.e64, C, R, w.U64, w.V64, x0.data(), p, rr, s));
-        st.ms_phase[2] = now_ms() - tr;
-        st.outer[1] = rr.outer;
-        st.inner[1] = rr.inner;
-        st.passes[1] = rr.passes;
-        st.kkt[1] = rr.kkt;
-        st.pass_ms[1] = rr.pass_ms;
-        st.pass_bytes[1] = rr.pass_bytes;
-        st.pass_launches[1] = rr.launches;
-        st.mid_rows[1] = rr.sumk;
-        st.mid_rows_max[1] = rr.maxk;
-        st.n_red = m;
-        if (rr.status != 1) status = MEB_WARN_MAXITER;
-        xfin = rr.x;
-        if (U_out || V_out) HIPCHK(launch_dense_mult(w.U64, w.V64, MEB_F64, m, d, U_out, V_out, s));
-    } else {
-        // ---- phase 1: FP32 run on all m balls, shifted by c_1
-        HIPCHK(launch_fill_bytes_zero(w.U32, sizeof(float) * (size_t)m, s));
-        std::vector<double> x0(n1, 0.0);
-        x0[0] = L;
-        RunParams p1{L, sigma0_raw, tau_raw, o->tol_kkt_low, 5.9604644775390625e-08, o};
-        RunResult r1;
-        CHK(run_ripalm(w.e32, w.C32, R ? (const void*)w.R32 : nullptr, w.U32, w.V32, x0.data(), p1, r1, s));
-        st.ms_phase[0] = now_ms() - t0;
-        st.outer[0] = r1.outer;
-        st.inner[0] = r1.inner;
-        st.passes[0] = r1.passes;
-        st.kkt[0] = r1.kkt;
-        st.pass_ms[0] = r1.pass_ms;
-        st.pass_bytes[0] = r1.pass_bytes;
-        st.pass_launches[0] = r1.launches;
-        st.mid_rows[0] = r1.sumk;
-        st.mid_rows_max[0] = r1.maxk;
-        // ---- screening on the FP32 copy (FP64 arithmetic), tol_red in units of L
-        const double ts = now_ms();
-        std::vector<double> chat_s(d);  // shifted coordinates
-        for (int k = 0; k < d; ++k) chat_s[k] = r1.x[1 + k];
-        double tol_red = o->tol_red * L;
-        int64_t n_red = 0;
-        for (int tries = 0; tries < 8; ++tries) {
-            CHK(run_screen(w.C32, R ? (const void*)w.R32 : nullptr, m, d, MEB_F32, r1.x[0], chat_s.data(), tol_red,
-                           w.scan, w.keep, &n_red, nullptr, s));
-            if (n_red > 0) break;
-            tol_red = tol_red < 0 ? 0.0 : std::max(4.0 * tol_red, 1e-6 * L);
-        }
-        if (n_red == 0) return fail(MEB_ERR_NUMERIC, "screening retained no ball");
-        // gather retained rows (FP64 data) and the FP32 multipliers as warm start
-        HIPCHK(launch_gather(C, R, nullptr, nullptr, MEB_F64, w.keep, n_red, d, w.Cred, R ? w.Rred : nullptr,
-                             nullptr, nullptr, s));
-        HIPCHK(launch_gather(nullptr, nullptr, w.U32, w.V32, MEB_F32, w.keep, n_red, d, nullptr, nullptr, w.U64,
-                             w.V64, s));
-        st.ms_phase[1] = now_ms() - ts;
-        // ---- phase 2: FP64 run(s) on the retained set, with reinsertion
-        std::vector<double> xw(n1);
-        xw[0] = r1.x[0];
-        for (int k = 0; k < d; ++k) xw[1 + k] = c1[k] + r1.x[1 + k];
-        double sigma_w = r1.sigma_end;
-        double mreach_final = INFINITY;
-        std::vector<int64_t> keep_h;   // retained indices in device order
-        std::vector<int64_t> keep_sorted;
-        int rounds = 0;
-        double tr_total = 0, tc_total = 0;
-        for (;;) {
-            // the FP64 engine was carved for m balls; re-carve it for the
-            // reduced size inside the same region (the carving grows with m)
-            Engine& e = w.e64;
-            char* region = (char*)e.state;
-            const size_t region_bytes = engine_bytes(m, d, MEB_F64);
-            if (engine_bytes(n_red, d, MEB_F64) > region_bytes)
-                return fail(MEB_ERR_WORKSPACE, "reduced engine does not fit");
-            e.setup(n_red, d, MEB_F64);
-            {
-                Arena sub{region, region_bytes, 0};
-                e.carve(sub);
-            }
-            RunParams p2{L, sigma_w, tau_raw, o->tol_kkt, 2.220446049250313e-16, o};
-            RunResult r2;
-            const double tr = now_ms();
-            CHK(run_ripalm(e, w.Cred, R ? (const void*)w.Rred : nullptr, w.U64, w.V64, xw.data(), p2, r2, s));
-            tr_total += now_ms() - tr;
-            st.outer[1] += r2.outer;
-            st.inner[1] += r2.inner;
-            st.passes[1] += r2.passes;
-            st.kkt[1] = r2.kkt;
-            st.pass_ms[1] += r2.pass_ms;
-            st.pass_bytes[1] += r2.pass_bytes;
-            st.pass_launches[1] += r2.launches;
-            st.mid_rows[1] += r2.sumk;
-            st.mid_rows_max[1] = std::max(st.mid_rows_max[1], r2.maxk);
-            if (r2.status != 1) status = MEB_WARN_MAXITER;
-            xw = r2.x;
-            sigma_w = r2.sigma_end;
-            // full FP64 check: reach_i = r_i + ||c - c_i||; violated if reach_i - rbar > eps
-            const double tc = now_ms();
-            const double eps_feas = o->eps_feas_rel * (1.0 + xw[0]);
-            double mreach;
-            int64_t am, nv;
-            CHK(run_check(C, R, m, d, MEB_F64, 0.0, xw.data() + 1, xw[0] + eps_feas, w.scan, &mreach, &am, w.viol, m,
-                          &nv, s));
-            tc_total += now_ms() - tc;
-            st.delta_max = mreach - xw[0];
-            mreach_final = mreach;
-            if (nv == 0 || rounds >= o->max_reinsert) break;
-            // new violators not yet retained
-            std::vector<int64_t> vh(nv);
-            HIPCHK(hipMemcpyAsync(vh.data(), w.viol, sizeof(int64_t) * nv, hipMemcpyDeviceToHost, s));
-            if (keep_h.empty()) {
-                keep_h.resize(n_red);
-                HIPCHK(hipMemcpyAsync(keep_h.data(), w.keep, sizeof(int64_t) * n_red, hipMemcpyDeviceToHost, s));
-            }
-            HIPCHK(hipStreamSynchronize(s));
-            if (keep_sorted.empty()) keep_sorted = keep_h;  // screening output is ascending
-            std::vector<int64_t> add;
-            std::set_difference(vh.begin(), vh.end(), keep_sorted.begin(), keep_sorted.end(), std::back_inserter(add));
-            if (add.empty()) break;
-            rounds++;
-            // append the new balls at the end of the reduced problem (zero multipliers)
-            HIPCHK(hipMemcpyAsync(w.viol, add.data(), sizeof(int64_t) * add.size(), hipMemcpyHostToDevice, s));
-            const int64_t na = (int64_t)add.size();
-            HIPCHK(launch_gather(C, R, nullptr, nullptr, MEB_F64, w.viol, na, d, w.Cred + (size_t)n_red * d,
-                                 R ? w.Rred + n_red : nullptr, nullptr, nullptr, s));
-            HIPCHK(launch_fill_f64(w.U64 + n_red, 0.0, na, s));
-            std::vector<int64_t> merged;
-            merged.reserve(keep_h.size() + add.size());
-            merged.insert(merged.end(), keep_h.begin(), keep_h.end());
-            merged.insert(merged.end(), add.begin(), add.end());
-            keep_h.swap(merged);
-            {
-                std::vector<int64_t> ms;
-                ms.reserve(keep_sorted.size() + add.size());
-                std::merge(keep_sorted.begin(), keep_sorted.end(), add.begin(), add.end(), std::back_inserter(ms));
-                keep_sorted.swap(ms);
-            }
-            HIPCHK(hipMemcpyAsync(w.keep, keep_h.data(), sizeof(int64_t) * keep_h.size(), hipMemcpyHostToDevice, s));
-            n_red += na;
-        }
-        st.ms_phase[2] = tr_total;
-        st.ms_phase[3] = tc_total;
-        st.reinsert_rounds = rounds;
-        st.n_red = n_red;
-        xfin = xw;
-        mreach_mixed = mreach_final;
-        if (U_out || V_out) {
-            if (U_out) HIPCHK(launch_fill_f64(U_out, 0.0, m, s));
-            if (V_out) HIPCHK(launch_fill_f64(V_out, 0.0, m * (int64_t)d, s));
-            HIPCHK(launch_scatter_mult(w.U64, w.V64, w.keep, n_red, d, U_out, V_out, s));
-        }
-    }
-    // fix-up: the returned radius encloses every ball (FP64 check over all m;
-    // the mixed path's last full check already holds it for this center)
-    double mreach = mreach_mixed;
-    if (!(mreach > -INFINITY)) {
-        int64_t am, nv;
-        const double tcf = now_ms();
-        CHK(run_check(C, R, m, d, dtype, 0.0, xfin.data() + 1, INFINITY, w.scan, &mreach, &am, nullptr, 0, &nv, s));
-        st.ms_phase[3] += now_ms() - tcf;
-    }
-    st.rbar = xfin[0];
-    st.delta_max = mreach - xfin[0];
-    *r_out = std::max(xfin[0], mreach);
-    memcpy(c_out, xfin.data() + 1, sizeof(double) * d);
-    HIPCHK(hipStreamSynchronize(s));
-    st.status = status;
-    st.ms_total = now_ms() - t_start;
-    if (stats) *stats = st;
-    return status;
+    double* pin = g_pin.get(JobPin::doubles(d));
+    if (!pin) return fail(MEB_ERR_HIP, "pinned host allocation failed");
+    Job j;
+    CHK(j.init(C, R, m, d, o, ws, ws_bytes, pin, U_out, V_out));
+    CHK(drive_sync(j, s));
+    *r_out = j.r_out;
+    memcpy(c_out, j.xfin.data() + 1, sizeof(double) * d);
+    j.st.ms_total = now_ms() - t_start;
+    if (stats) *stats = j.st;
+    return j.status;
 }
 
 }  // extern "C"

@@ -135,9 +135,9 @@ enum PassMode : int { PM_EVAL = 0, PM_MULT = 1, PM_DONE = 2 };
 // Kernel configuration chosen by the host for (d, dtype).
 struct PassConfig {
     int G;        // lanes per ball (power of two, 1..64)
-    int vec;      // elements per lane per load (1 or 2)
+    int vec;      // elements per lane per load (1, 2, or 4 for FP32)
     int nl;       // loads per lane per row
-    int nlmax;    // compile-time bound on nl (4, 8, 16 or 32)
+    int nlmax;    // compile-time bound on nl (2, 4, 8 or 16)
     int waves_per_block;
     int blocks;   // grid size
     int64_t bw;   // balls per wave (multiple of 64 / G)
@@ -193,6 +193,42 @@ struct SyrkArgs {
 
 // Concatenates the per-wave mid-list segments into one list (ascending wave
 // order): offsets by a single-block scan, then a copy.
+// One instance of the multi-instance step: the arguments of its pass,
+// reduction, contraction, assembly and control kernels.  Lives in a device
+// table indexed by slot; a tick names the slots it steps.
+struct BatchItem {
+    PassArgs pa;
+    PassConfig pc;
+    SyrkArgs sa;
+    double* red;          // reduced record, then the slice partials
+    int64_t* list_offs;   // per-wave offsets of the compacted mid list
+    int* flag;            // nullable: the state's mode after each control step
+    int ksplit, ntile;
+    int use_syrk;
+};
+
+// Instances of one launch and the first flat block of each (ascending);
+// passed by value as a kernel argument.
+constexpr int TICK_MAX = 128;
+struct TickList {
+    int n;
+    int slot[TICK_MAX];
+    int off[TICK_MAX + 1];
+};
+
+// One solver step (pass, reduction, mid-list compaction, contraction,
+// assembly, control) for the `n` instances slots[0..n) of the device table
+// `dtab`; `htab` is its host mirror (read for the launch shapes).  The pass
+// takes one launch per template instance among the items; every other kernel
+// one launch per TICK_MAX items.
+// The pass of a group of items that share one template instance.
+hipError_t launch_pass_group(const BatchItem* dtab, const TickList& L, int blocks, int max_d, int dtype,
+                             const PassConfig& cfg, hipStream_t s);
+hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* slots, int n, hipStream_t s);
+int pass_variant(int dtype, const PassConfig& cfg);
+int reduce_nslice(int nrec);
+size_t control_lds_bytes(int n1);
+
 hipError_t launch_mid_compact(const int32_t* mid_cnt, int nwaves, int64_t bw, const int32_t* seg_idx,
                               const double* seg_coef, int64_t* offs, int64_t* total, int32_t* out_idx,
                               double* out_coef, const double* state, hipStream_t s);
@@ -200,11 +236,11 @@ hipError_t launch_mid_compact(const int32_t* mid_cnt, int nwaves, int64_t bw, co
 // ----------------------------------------------------------------------------
 // Launchers (meb_kernels.hip).  All return hipError_t of the launch.
 // ----------------------------------------------------------------------------
-// kind 0: evaluation; 1: evaluation + updated multipliers + KKT terms (both
-// regardless of the state's mode); 3: the solver's pass, which runs the
-// evaluation or the multiplier update (+ KKT + next evaluation) as the
-// state's mode says, and nothing when the run is done.
-hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, int kind, hipStream_t s);
+// The evaluation pass: the solver's evaluation or multiplier update (+ KKT
+// + next evaluation) as the state's mode says, nothing when the run is done;
+// force_mode = PM_EVAL gives a single evaluation (want_kkt adds the updated
+// multipliers and the KKT terms).
+hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, hipStream_t s);
 // Sums (maxima for the KKT maxima) of nrec records of len doubles, `stride`
 // doubles apart; the pass leaves one record per block at stride
 // waves_per_block * len.

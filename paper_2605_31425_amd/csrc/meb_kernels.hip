@@ -1,611 +1,12 @@
-// HIP kernels of libmeb.so for gfx950 (MI355X): the proximal augmented
-// Lagrangian evaluation pass of ripALM for the minimum enclosing ball of
-// balls, its deterministic reductions, the rank-one Hessian contraction, the
-// device-side control step (Armijo decision, relative stopping test,
-// multiplier bookkeeping, FP64 Cholesky solve), the screening and
-// feasibility scans, and the precision-preparation and gather kernels.
-//
-// Layout: centers C (m x d, row-major), radii R (m), multipliers U (m) and
-// V (m x d).  A V row is meaningful only where U != 0: multipliers lie in the
-// second-order cone, so u_i = 0 forces v_i = 0, and the evaluation reads a V
-// row only for u_i != 0.  This keeps the bytes of one pass at
-// m (d + 2) s + nnz(u) d s instead of 2 m (d + 1) s.
-//
-// Work mapping of the evaluation pass: a group of G lanes (G a power of two,
-// 1..64) owns one ball; lane gl of the group owns elements
-// (j G + gl) VEC + q, q < VEC, j < nl of the row, so one wave-wide load
-// instruction reads 64/G consecutive rows and stays coalesced.  Every wave
-// streams its own contiguous range of balls, accumulates per-lane partial
-// sums in FP64, and writes one partial record; records are reduced in a
-// fixed order, so results are bitwise reproducible.
-#include <hip/hip_runtime.h>
-#include <math.h>
-
-#include "meb_internal.h"
+// HIP kernels of libmeb.so for gfx950 (MI355X), apart from the evaluation
+// pass: the deterministic reductions of the pass records, the rank-one
+// Hessian contraction, the device-side control step of ripALM (Armijo
+// decision, relative stopping test, multiplier bookkeeping, FP64 Cholesky
+// solve), the screening and feasibility scans, the precision-preparation
+// and gather kernels, and the multi-instance step of the server.
+#include "meb_device.h"
 
 namespace meb {
-
-constexpr int WAVE = 64;
-constexpr int PASS_THREADS = 256;
-constexpr int WPB = PASS_THREADS / WAVE;
-
-// ---------------------------------------------------------------------------
-// small device helpers
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
-
-template <typename T>
-__device__ __forceinline__ T group_sum(T v, int G) {
-    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-
-// Sum across groups: combines lanes with equal (lane % G).
-__device__ __forceinline__ double cross_group_sum(double v, int G) {
-    for (int o = G; o < WAVE; o <<= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum_t(T v) {
-    for (int o = WAVE >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_max_t(T v) {
-    for (int o = WAVE >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
-    return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T cross_group_sum_t(T v, int G) {
-    for (int o = G; o < WAVE; o <<= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = WAVE >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-    for (int o = WAVE >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
-    return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T tsqrt(T x);
-template <>
-__device__ __forceinline__ double tsqrt<double>(double x) { return sqrt(x); }
-template <>
-__device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
-
-// Distance of (t, s) with ||s|| = n to the second-order cone.
-template <typename T>
-__device__ __forceinline__ T cone_dist(T t, T n) {
-    if (n <= t) return T(0);
-    if (n <= -t) return tsqrt<T>(t * t + n * n);
-    return (n - t) * T(0.70710678118654752440);
-}
-
-template <typename T, int VEC>
-struct RowVec {
-    T v[VEC];
-};
-
-template <typename T, int VEC>
-__device__ __forceinline__ RowVec<T, VEC> load_vec(const T* p) {
-    RowVec<T, VEC> r;
-    if constexpr (VEC == 1) {
-        r.v[0] = *p;
-    } else {
-        if constexpr (sizeof(T) == 8) {
-            double2 x = *reinterpret_cast<const double2*>(p);
-            r.v[0] = x.x;
-            r.v[1] = x.y;
-        } else {
-            float2 x = *reinterpret_cast<const float2*>(p);
-            r.v[0] = x.x;
-            r.v[1] = x.y;
-        }
-    }
-    return r;
-}
-
-template <typename T, int VEC>
-__device__ __forceinline__ void store_vec(T* p, const RowVec<T, VEC>& r) {
-    if constexpr (VEC == 1) {
-        *p = r.v[0];
-    } else {
-        if constexpr (sizeof(T) == 8) {
-            *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
-        } else {
-            *reinterpret_cast<float2*>(p) = make_float2(r.v[0], r.v[1]);
-        }
-    }
-}
-
-// Per-ball projection quantities.
-template <typename T>
-struct BallProj {
-    int cs;   // 0 interior, 1 polar, 2 other
-    T n;      // ||s||
-    T up;     // sigma * Pi(z)_0
-    T gam;    // v+ = gam * s
-    T Z;      // ||Pi(z)||^2
-};
-
-template <typename T>
-__device__ __forceinline__ BallProj<T> project(T t, T nn, T sig) {
-    BallProj<T> b;
-    b.n = tsqrt<T>(nn);
-    if (b.n <= t) {
-        b.cs = 0;
-        b.up = sig * t;
-        b.gam = sig;
-        b.Z = t * t + nn;
-    } else if (b.n <= -t) {
-        b.cs = 1;
-        b.up = T(0);
-        b.gam = T(0);
-        b.Z = T(0);
-    } else {
-        b.cs = 2;
-        T hp = T(0.5) * (t + b.n);
-        b.up = sig * hp;
-        b.gam = sig * hp / b.n;
-        b.Z = T(2) * hp * hp;
-    }
-    return b;
-}
-
-// ---------------------------------------------------------------------------
-// Evaluation pass
-// ---------------------------------------------------------------------------
-
-// Scalar accumulator slots of the evaluation pass (per lane, flushed to the
-// per-wave FP64 record).
-enum : int { A_SU = 0, A_Z1, A_NI, A_NM, A_SG, A_DM, A_RS, A_WW, A_KU, A_BYTES, A_N };
-
-template <typename T>
-struct FlushPeriod {
-    static constexpr int steps = 1 << 30;  // FP64 sums: no intermediate flush
-};
-template <>
-struct FlushPeriod<float> {
-    static constexpr int steps = 32;  // FP32 partial sums cover at most 32 balls per lane
-};
-
-// KIND 0: evaluation (Psi trials, gradient, Hessian parts) -- runs when the
-//         state's mode is PM_EVAL;
-// KIND 1: evaluation plus the updated multipliers and KKT terms at the same
-//         point (the single-evaluation entry point);
-// KIND 2: multiplier update at x_j, KKT terms, and the first evaluation of the
-//         next outer iteration -- runs when the mode is PM_MULT.
-// TRL: Armijo trials per lane (ceil(NT / G) rounded up to 1, 3 or 9).
-template <typename T, int VEC, int NLMAX, int KIND, int TRL>
-__device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& cfg) {
-    extern __shared__ double lds[];
-    const double* st = a.state;
-    const int d = a.d;
-    const int G = cfg.G;
-    const int nl = cfg.nl;
-    const StateLayout sl = a.sl;
-    const RecLayout rl = a.rl;
-
-    const bool have_dir = (KIND != 2) && st[S_HAVE_DIR] != 0.0;
-    constexpr bool is_mult = (KIND == 2);
-    constexpr bool want_kkt = (KIND != 0);
-
-    // the evaluation point y = x_base + dir and the direction, staged in LDS
-    double* l_c = lds;
-    double* l_dc = lds + d;
-    double* l_red = lds + 2 * d;
-    double part = 0.0;
-    for (int k = threadIdx.x; k < d; k += PASS_THREADS) {
-        double dk = have_dir ? st[sl.dir + 1 + k] : 0.0;
-        l_c[k] = st[sl.xb + 1 + k] + dk;
-        l_dc[k] = dk;
-        part += dk * dk;
-    }
-    l_red[threadIdx.x] = part;
-    __syncthreads();
-    for (int o = PASS_THREADS / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) l_red[threadIdx.x] += l_red[threadIdx.x + o];
-        __syncthreads();
-    }
-    const T dc2 = (T)l_red[0];
-    const double dirr_d = have_dir ? st[sl.dir] : 0.0;
-    const T r1 = (T)(st[sl.xb] + dirr_d);
-    const T dirr = (T)dirr_d;
-    const double sig_a_d = st[S_SIGMA];
-    const double sig_b_d = st[S_SIGMA_NEXT];
-    const T sig_a = (T)sig_a_d;
-    const T inv_a = (T)(1.0 / sig_a_d);
-    const T sig_b = (T)sig_b_d;
-    const T inv_b = (T)(1.0 / sig_b_d);
-
-    const T* C = static_cast<const T*>(a.C);
-    const T* R = static_cast<const T*>(a.R);
-    const T* U = static_cast<const T*>(a.U);
-    const T* V = static_cast<const T*>(a.V);
-    T* Uo = static_cast<T*>(a.Uout);
-    T* Vo = static_cast<T*>(a.Vout);
-
-    const int lane = lane_id();
-    const int wid = threadIdx.x / WAVE;
-    const int64_t gw = (int64_t)blockIdx.x * WPB + wid;
-    const int gi = lane / G;
-    const int gl = lane % G;
-    const int bpw = WAVE / G;
-    const bool leader = (gl == 0);
-    const int64_t wbeg = gw * cfg.bw;
-    const int64_t wend = min(a.m, wbeg + cfg.bw);
-    const T es_bytes = (T)sizeof(T);
-
-    // per-lane constants: the owned elements of y and of dir
-    int base[NLMAX];
-    bool own[NLMAX];
-    T cv[NLMAX][VEC], dv[NLMAX][VEC];
-#pragma unroll
-    for (int j = 0; j < NLMAX; ++j) {
-        base[j] = (j * G + gl) * VEC;
-        own[j] = (j < nl) && (base[j] < d);
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) {
-            cv[j][q] = own[j] ? (T)l_c[base[j] + q] : T(0);
-            dv[j][q] = own[j] ? (T)l_dc[base[j] + q] : T(0);
-        }
-    }
-
-    // the wave's record doubles as the FP64 accumulator of the flushes
-    double* rec = a.rec + gw * rl.len;
-    for (int e = lane; e < rl.len; e += WAVE) rec[e] = 0.0;
-
-    T sacc[A_N];
-    T tacc[TRL];
-    T tam[TRL];  // 1 - eta of this lane's trials
-#pragma unroll
-    for (int r = 0; r < TRL; ++r) {
-        const int l = r * G + gl;
-        tam[r] = (l < NT) ? T(1) - (T)a.etas[l] : T(1);
-    }
-    T vsv[NLMAX][VEC], vsw[NLMAX][VEC], vkv[NLMAX][VEC];
-    T mx_p = 0, mx_d = 0, mx_c = 0;
-    auto zero_acc = [&]() {
-#pragma unroll
-        for (int k = 0; k < A_N; ++k) sacc[k] = T(0);
-#pragma unroll
-        for (int k = 0; k < TRL; ++k) tacc[k] = T(0);
-#pragma unroll
-        for (int j = 0; j < NLMAX; ++j)
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) vsv[j][q] = vsw[j][q] = vkv[j][q] = T(0);
-    };
-    auto flush = [&]() {
-        // scalars: wave sums; trials and vectors: sums across groups
-        T sred[A_N];
-#pragma unroll
-        for (int k = 0; k < A_N; ++k) sred[k] = wave_sum_t<T>(sacc[k]);
-        if (lane == 0) {
-            rec[rl.su] += (double)sred[A_SU];
-            rec[rl.z1] += (double)sred[A_Z1];
-            rec[rl.ni] += (double)sred[A_NI];
-            rec[rl.nm] += (double)sred[A_NM];
-            rec[rl.sg] += (double)sred[A_SG];
-            rec[rl.dm] += (double)sred[A_DM];
-            rec[rl.rs] += (double)sred[A_RS];
-            rec[rl.ww] += (double)sred[A_WW];
-            rec[rl.ku] += (double)sred[A_KU];
-            rec[rl.bytes] += (double)sred[A_BYTES];
-        }
-        if (have_dir) {
-#pragma unroll
-            for (int r = 0; r < TRL; ++r) {
-                const T v = cross_group_sum_t<T>(tacc[r], G);
-                const int l = r * G + lane;
-                if (lane < G && l < NT) rec[rl.trial + l] += (double)v;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < NLMAX; ++j) {
-            if (j >= nl) break;
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) {
-                const T a1 = cross_group_sum_t<T>(vsv[j][q], G);
-                const T a2 = cross_group_sum_t<T>(vsw[j][q], G);
-                T a3 = T(0);
-                if constexpr (want_kkt) a3 = cross_group_sum_t<T>(vkv[j][q], G);
-                if (lane < G && own[j]) {
-                    rec[rl.sv + base[j] + q] += (double)a1;
-                    rec[rl.sw + base[j] + q] += (double)a2;
-                    if constexpr (want_kkt) rec[rl.kv + base[j] + q] += (double)a3;
-                }
-            }
-        }
-        zero_acc();
-    };
-    zero_acc();
-
-    int32_t mid_count = 0;
-    int32_t* mid_idx = a.want_mid ? a.mid_idx + gw * cfg.bw : nullptr;
-    double* mid_coef = a.want_mid ? a.mid_coef + gw * cfg.bw : nullptr;
-
-    const int64_t chunk = (int64_t)bpw * FlushPeriod<T>::steps;
-    for (int64_t c0 = wbeg; c0 < wend; c0 += chunk) {
-    const int64_t c1 = min(wend, c0 + chunk);
-    for (int64_t b0 = c0; b0 < c1; b0 += bpw) {
-        const int64_t i = b0 + gi;
-        const bool active = i < wend;
-        const T ri = (R && active) ? R[i] : T(0);
-        const T ui = (U && active) ? U[i] : T(0);
-        const bool hasv = V && (ui != T(0));
-        T s[NLMAX][VEC], vv[NLMAX][VEC], e[NLMAX][VEC];
-        T nn = 0, q = 0, ee = 0, es = 0;
-#pragma unroll
-        for (int j = 0; j < NLMAX; ++j) {
-            const bool ok = active && own[j];
-            RowVec<T, VEC> cr, vr;
-#pragma unroll
-            for (int qq = 0; qq < VEC; ++qq) cr.v[qq] = vr.v[qq] = T(0);
-            if (ok) {
-                cr = load_vec<T, VEC>(C + i * d + base[j]);
-                if (hasv) vr = load_vec<T, VEC>(V + i * d + base[j]);
-            }
-#pragma unroll
-            for (int qq = 0; qq < VEC; ++qq) {
-                const T ek = ok ? cr.v[qq] - cv[j][qq] : T(0);
-                if constexpr (is_mult) e[j][qq] = ek;
-                vv[j][qq] = vr.v[qq];
-                s[j][qq] = ek + vr.v[qq] * inv_a;
-                nn += s[j][qq] * s[j][qq];
-                if constexpr (KIND != 2) {
-                    if (have_dir) q += s[j][qq] * dv[j][qq];
-                }
-                if constexpr (want_kkt) {
-                    ee += ek * ek;
-                    es += ek * s[j][qq];
-                }
-            }
-        }
-        nn = group_sum<T>(nn, G);
-        if (have_dir) q = group_sum<T>(q, G);
-        if constexpr (want_kkt) {
-            ee = group_sum<T>(ee, G);
-            es = group_sum<T>(es, G);
-        }
-        if (leader && active)
-            sacc[A_BYTES] += es_bytes * (T)(d + (R ? 1 : 0) + (U ? 1 : 0) + (hasv ? d : 0));
-        const T t = ri - r1 + ui * inv_a;
-        BallProj<T> pa = project<T>(t, nn, sig_a);
-        if (!active) pa.cs = 1, pa.up = T(0), pa.gam = T(0), pa.Z = T(0);
-
-        T te = t, nne = nn, ue = ui;
-        BallProj<T> pe = pa;
-        T sig_e = sig_a;
-
-        if constexpr (want_kkt) {
-            // updated multipliers w+ = sigma Pi(z) at y and the KKT terms there
-            const T un = pa.up;
-            const bool wrow = Vo && (un != T(0) || a.dense_vout);
-            if (leader && active) {
-                sacc[A_KU] += un;
-                const T tp = r1 - ri;
-                mx_p = fmax(mx_p, cone_dist<T>(tp, tsqrt<T>(ee)));
-                mx_d = fmax(mx_d, cone_dist<T>(un, pa.gam * pa.n));
-                mx_c = fmax(mx_c, fabs(tp * un - pa.gam * es));
-                if (Uo) Uo[i] = un;
-                sacc[A_BYTES] += (Uo ? es_bytes : T(0)) + (wrow ? es_bytes * (T)d : T(0));
-            }
-#pragma unroll
-            for (int j = 0; j < NLMAX; ++j) {
-                RowVec<T, VEC> vn;
-#pragma unroll
-                for (int qq = 0; qq < VEC; ++qq) {
-                    vn.v[qq] = pa.gam * s[j][qq];
-                    vkv[j][qq] += vn.v[qq];
-                }
-                if (active && own[j] && wrow) store_vec<T, VEC>(Vo + i * d + base[j], vn);
-                if constexpr (is_mult) {
-#pragma unroll
-                    for (int qq = 0; qq < VEC; ++qq) vv[j][qq] = vn.v[qq];
-                }
-            }
-            if constexpr (is_mult) {
-                // the first evaluation of the next subproblem: w+ and sigma_{k+1}
-                ue = un;
-                sig_e = sig_b;
-                te = ri - r1 + un * inv_b;
-                T n2 = 0;
-#pragma unroll
-                for (int j = 0; j < NLMAX; ++j)
-#pragma unroll
-                    for (int qq = 0; qq < VEC; ++qq) {
-                        s[j][qq] = e[j][qq] + vv[j][qq] * inv_b;
-                        n2 += s[j][qq] * s[j][qq];
-                    }
-                nne = group_sum<T>(n2, G);
-                pe = project<T>(te, nne, sig_b);
-                if (!active) pe.cs = 1, pe.up = T(0), pe.gam = T(0), pe.Z = T(0);
-            }
-        }
-
-        // ---- evaluation sums at (y, multipliers in use, sigma_e)
-        if (leader && active) {
-            sacc[A_SU] += pe.up;
-            sacc[A_Z1] += pe.Z;
-            const T du = pe.up - ue;
-            sacc[A_DM] += du * du;
-            sacc[A_WW] += ue * ue;
-            if (pe.cs != 1) sacc[A_RS] += fabs(te) + pe.n;
-            if (pe.cs == 0) sacc[A_NI] += T(1);
-            if (pe.cs == 2) {
-                sacc[A_NM] += T(1);
-                sacc[A_SG] += pe.gam;
-            }
-        }
-        // a polar ball with zero multipliers contributes nothing elementwise
-        const bool quiet = (pe.cs == 1) && (ue == T(0));
-        if (!quiet) {
-            const T inv_n = (pe.cs == 2) ? T(1) / pe.n : T(0);
-            T dmb = 0, wwb = 0;
-#pragma unroll
-            for (int j = 0; j < NLMAX; ++j)
-#pragma unroll
-                for (int qq = 0; qq < VEC; ++qq) {
-                    const T vp = pe.gam * s[j][qq];
-                    const T dvk = vp - vv[j][qq];
-                    vsv[j][qq] += vp;
-                    vsw[j][qq] += s[j][qq] * inv_n;
-                    dmb += dvk * dvk;
-                    wwb += vv[j][qq] * vv[j][qq];
-                }
-            sacc[A_DM] += dmb;
-            sacc[A_WW] += wwb;
-        }
-        // Armijo trials along x_base + eta dir: lane gl takes trials gl, gl + G, ...
-        if (have_dir && active) {
-#pragma unroll
-            for (int r = 0; r < TRL; ++r) {
-                const T am = tam[r];
-                const T tl = te + am * dirr;
-                T n2 = nne + T(2) * am * q + am * am * dc2;
-                n2 = n2 > T(0) ? n2 : T(0);
-                if (r * G + gl < NT) tacc[r] += project<T>(tl, n2, sig_e).Z;
-            }
-        }
-        // mid list of the rank-one Hessian part: coef_i = -sigma t_i / (2 n_i^3)
-        if (a.want_mid) {
-            const bool is_mid = active && pe.cs == 2;
-            const unsigned long long bal = __ballot(is_mid && leader);
-            if (is_mid && leader) {
-                const unsigned long long lower = bal & ((1ull << lane) - 1ull);
-                const int pos = mid_count + __popcll(lower);
-                mid_idx[pos] = (int32_t)i;
-                const double nd = (double)pe.n;
-                mid_coef[pos] = -(double)sig_e * (double)te / (2.0 * nd * nd * nd);
-            }
-            mid_count += __popcll(bal);
-        }
-    }
-    flush();
-    }
-    const T mp = wave_max_t<T>(mx_p), md = wave_max_t<T>(mx_d), mc = wave_max_t<T>(mx_c);
-    if (lane == 0) {
-        rec[rl.kmax + 0] = (double)mp;
-        rec[rl.kmax + 1] = (double)md;
-        rec[rl.kmax + 2] = (double)mc;
-        if (a.mid_cnt) a.mid_cnt[gw] = mid_count;
-    }
-    // combine the block's wave records into the first one, in wave order
-    __syncthreads();
-    double* r0 = a.rec + (int64_t)blockIdx.x * WPB * rl.len;
-    for (int e = threadIdx.x; e < rl.len; e += PASS_THREADS) {
-        const bool ismax = e >= rl.kmax && e < rl.kmax + 3;
-        double v = r0[e];
-#pragma unroll
-        for (int w = 1; w < WPB; ++w) {
-            const double x = r0[w * rl.len + e];
-            v = ismax ? fmax(v, x) : v + x;
-        }
-        r0[e] = v;
-    }
-}
-
-// The solver's pass: evaluation or multiplier update, as the device state says.
-template <typename T, int VEC, int NLMAX, int TRL>
-__global__ __launch_bounds__(PASS_THREADS) void pass_kernel(PassArgs a, PassConfig cfg) {
-    const int mode = (int)a.state[S_MODE];
-    if (mode == PM_EVAL)
-        pass_body<T, VEC, NLMAX, 0, TRL>(a, cfg);
-    else if (mode == PM_MULT)
-        pass_body<T, VEC, NLMAX, 2, TRL>(a, cfg);
-}
-
-// A single evaluation (KIND 0) or evaluation with the updated multipliers and
-// KKT terms (KIND 1), independent of the state's mode.
-template <typename T, int VEC, int NLMAX, int KIND, int TRL>
-__global__ __launch_bounds__(PASS_THREADS) void pass_eval_kernel(PassArgs a, PassConfig cfg) {
-    pass_body<T, VEC, NLMAX, KIND, TRL>(a, cfg);
-}
-
-PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
-    PassConfig c;
-    c.vec = (d % 2 == 0) ? 2 : 1;
-    // up to 4 loads (4 VEC elements) per lane when a ball has fewer than 64
-    // lanes: enough work per lane to amortize the cross-lane reduction of
-    // each ball, few enough to keep registers low.  Longer rows use 64 lanes
-    // and 8 or 16 loads.
-    const int per_lane_target = 4;
-    int need = (d + c.vec * per_lane_target - 1) / (c.vec * per_lane_target);
-    int G = 1;
-    while (G < need && G < 64) G <<= 1;
-    c.G = G;
-    c.nl = (d + G * c.vec - 1) / (G * c.vec);
-    c.nlmax = c.nl <= 4 ? 4 : (c.nl <= 8 ? 8 : 16);
-    c.waves_per_block = WPB;
-    const int bpw = WAVE / G;
-    // enough waves to fill the machine, each streaming a contiguous range
-    int64_t max_waves = (int64_t)num_cu * 8;
-    int64_t steps = (m + bpw - 1) / bpw;
-    int64_t waves = steps < max_waves ? steps : max_waves;
-    if (waves < 1) waves = 1;
-    int64_t steps_per_wave = (steps + waves - 1) / waves;
-    c.bw = steps_per_wave * bpw;
-    waves = (m + c.bw - 1) / c.bw;
-    c.blocks = (int)((waves + WPB - 1) / WPB);
-    c.nwaves = c.blocks * WPB;
-    (void)dtype;
-    return c;
-}
-
-// kind 0 / 1: pass_eval_kernel; kind 3: the solver's pass_kernel
-template <typename T, int VEC, int NLMAX, int KIND, int TRL>
-static hipError_t launch_pass_t(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
-    size_t lds = sizeof(double) * (2 * (size_t)a.d + PASS_THREADS);
-    if constexpr (KIND == 3)
-        hipLaunchKernelGGL((pass_kernel<T, VEC, NLMAX, TRL>), dim3(cfg.blocks), dim3(PASS_THREADS), lds, s, a, cfg);
-    else
-        hipLaunchKernelGGL((pass_eval_kernel<T, VEC, NLMAX, KIND, TRL>), dim3(cfg.blocks), dim3(PASS_THREADS), lds, s,
-                           a, cfg);
-    return hipGetLastError();
-}
-
-// kernels that evaluate Armijo trials need one trial slot per G lanes
-template <typename T, int VEC, int KIND>
-static hipError_t launch_pass_small(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
-    if (cfg.G >= 16) return launch_pass_t<T, VEC, 4, KIND, 1>(a, cfg, s);
-    if (cfg.G >= 4) return launch_pass_t<T, VEC, 4, KIND, 3>(a, cfg, s);
-    return launch_pass_t<T, VEC, 4, KIND, 9>(a, cfg, s);
-}
-
-template <typename T, int KIND>
-static hipError_t launch_pass_K(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
-    // nlmax 8 and 16 are used only with G = 64 lanes per ball
-    if (cfg.vec == 2) {
-        if (cfg.nlmax == 4) return launch_pass_small<T, 2, KIND>(a, cfg, s);
-        if (cfg.nlmax == 8) return launch_pass_t<T, 2, 8, KIND, 1>(a, cfg, s);
-        return launch_pass_t<T, 2, 16, KIND, 1>(a, cfg, s);
-    }
-    if (cfg.nlmax == 4) return launch_pass_small<T, 1, KIND>(a, cfg, s);
-    if (cfg.nlmax == 8) return launch_pass_t<T, 1, 8, KIND, 1>(a, cfg, s);
-    return launch_pass_t<T, 1, 16, KIND, 1>(a, cfg, s);
-}
-
-template <typename T>
-static hipError_t launch_pass_T(const PassArgs& a, const PassConfig& cfg, int kind, hipStream_t s) {
-    if (kind == 0) return launch_pass_K<T, 0>(a, cfg, s);
-    if (kind == 1) return launch_pass_K<T, 1>(a, cfg, s);
-    return launch_pass_K<T, 3>(a, cfg, s);
-}
-
-hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, int kind, hipStream_t s) {
-    if (a.dtype == 0) return launch_pass_T<double>(a, cfg, kind, s);
-    return launch_pass_T<float>(a, cfg, kind, s);
-}
-
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of per-wave records: out[e] = sum_w rec[w][e]
 // (maximum for the three KKT maxima).  Two stages: slices of records, then
@@ -617,13 +18,13 @@ constexpr int RED_SLICE = 32;
 // Stage 1: block (x, y) sums entries [64 x, 64 x + 64) over the records of
 // slice y; its four waves take records w = 4 k + wave, then combine in wave
 // order.  Records are `stride` doubles apart.
-__global__ __launch_bounds__(256) void reduce_stage1(const double* rec, int nrec, int len, int64_t stride, int max_lo,
-                                                     int max_hi, double* part) {
+__device__ __forceinline__ void reduce1_body(const double* rec, int nrec, int len, int64_t stride, int max_lo,
+                                             int max_hi, double* part, int bx, int by, int ny) {
     __shared__ double sp[4][64];
-    const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int e = bx * 64 + (threadIdx.x & 63);
     const int sub = threadIdx.x >> 6;
-    const int per = (nrec + gridDim.y - 1) / gridDim.y;
-    const int w0 = blockIdx.y * per, w1 = min(nrec, w0 + per);
+    const int per = (nrec + ny - 1) / ny;
+    const int w0 = by * per, w1 = min(nrec, w0 + per);
     const bool ismax = (e >= max_lo && e < max_hi);
     double acc = 0.0;
     if (e < len) {
@@ -637,13 +38,18 @@ __global__ __launch_bounds__(256) void reduce_stage1(const double* rec, int nrec
     if (threadIdx.x < 64 && e < len) {
         double v = sp[0][threadIdx.x];
         for (int k = 1; k < 4; ++k) v = ismax ? fmax(v, sp[k][threadIdx.x]) : v + sp[k][threadIdx.x];
-        part[(size_t)blockIdx.y * len + e] = v;
+        part[(size_t)by * len + e] = v;
     }
 }
 
-__global__ __launch_bounds__(256) void reduce_stage2(const double* part, int nslice, int len, int max_lo, int max_hi,
-                                                     double* out) {
-    const int e = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void reduce_stage1(const double* rec, int nrec, int len, int64_t stride, int max_lo,
+                                                     int max_hi, double* part) {
+    reduce1_body(rec, nrec, len, stride, max_lo, max_hi, part, blockIdx.x, blockIdx.y, gridDim.y);
+}
+
+__device__ __forceinline__ void reduce2_body(const double* part, int nslice, int len, int max_lo, int max_hi,
+                                             double* out, int bx) {
+    const int e = bx * 256 + threadIdx.x;
     if (e >= len) return;
     const bool ismax = (e >= max_lo && e < max_hi);
     double acc = 0.0;
@@ -654,15 +60,25 @@ __global__ __launch_bounds__(256) void reduce_stage2(const double* part, int nsl
     out[e] = acc;
 }
 
+__global__ __launch_bounds__(256) void reduce_stage2(const double* part, int nslice, int len, int max_lo, int max_hi,
+                                                     double* out) {
+    reduce2_body(part, nslice, len, max_lo, max_hi, out, blockIdx.x);
+}
+
+int reduce_nslice(int nrec) {
+    int nslice = (nrec + 15) / 16;
+    if (nslice > RED_SLICE) nslice = RED_SLICE;
+    if (nslice < 1) nslice = 1;
+    return nslice;
+}
+
 hipError_t launch_reduce_records(const double* rec, int nrec, int len, int64_t stride, double* out, hipStream_t s) {
     // `out` must have room for (RED_SLICE + 1) * len doubles: the slice
     // partials live after the result.  The three maxima sit at a fixed
     // offset ahead of the d-dependent vector parts of the record.
     const RecLayout rl = RecLayout::make(0);
     const int max_lo = rl.kmax, max_hi = rl.kmax + 3;
-    int nslice = (nrec + 15) / 16;
-    if (nslice > RED_SLICE) nslice = RED_SLICE;
-    if (nslice < 1) nslice = 1;
+    const int nslice = reduce_nslice(nrec);
     double* part = out + len;
     dim3 g1((len + 63) / 64, nslice);
     hipLaunchKernelGGL(reduce_stage1, g1, dim3(256), 0, s, rec, nrec, len, stride, max_lo, max_hi, part);
@@ -691,8 +107,8 @@ int syrk_ksplit(int d) {
 
 // Per-wave mid counts -> exclusive offsets and total, then the copy into one
 // list.  Skipped when the run is done.
-__global__ __launch_bounds__(1024) void mid_scan_kernel(const int32_t* cnt, int nw, int64_t* offs, int64_t* total,
-                                                        const double* st) {
+__device__ __forceinline__ void mid_scan_body(const int32_t* cnt, int nw, int64_t* offs, int64_t* total,
+                                              const double* st) {
     __shared__ int64_t sc[1024];
     if ((int)st[S_MODE] == PM_DONE) return;
     const int t = threadIdx.x;
@@ -716,18 +132,29 @@ __global__ __launch_bounds__(1024) void mid_scan_kernel(const int32_t* cnt, int 
     if (t == 1023) *total = sc[1023];
 }
 
-__global__ __launch_bounds__(256) void mid_copy_kernel(const int32_t* cnt, int nw, int64_t bw, const int32_t* si,
-                                                       const double* sc, const int64_t* offs, int32_t* oi,
-                                                       double* oc, const double* st) {
+__global__ __launch_bounds__(1024) void mid_scan_kernel(const int32_t* cnt, int nw, int64_t* offs, int64_t* total,
+                                                        const double* st) {
+    mid_scan_body(cnt, nw, offs, total, st);
+}
+
+__device__ __forceinline__ void mid_copy_body(const int32_t* cnt, int nw, int64_t bw, const int32_t* si,
+                                              const double* sc, const int64_t* offs, int32_t* oi, double* oc,
+                                              const double* st, int bx) {
     if ((int)st[S_MODE] == PM_DONE) return;
     const int lane = lane_id();
-    const int64_t w = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    const int64_t w = (int64_t)bx * 4 + threadIdx.x / WAVE;
     if (w >= nw) return;
     const int64_t n = cnt[w], off = offs[w];
     for (int64_t k = lane; k < n; k += WAVE) {
         oi[off + k] = si[w * bw + k];
         oc[off + k] = sc[w * bw + k];
     }
+}
+
+__global__ __launch_bounds__(256) void mid_copy_kernel(const int32_t* cnt, int nw, int64_t bw, const int32_t* si,
+                                                       const double* sc, const int64_t* offs, int32_t* oi,
+                                                       double* oc, const double* st) {
+    mid_copy_body(cnt, nw, bw, si, sc, offs, oi, oc, st, blockIdx.x);
 }
 
 hipError_t launch_mid_compact(const int32_t* mid_cnt, int nwaves, int64_t bw, const int32_t* seg_idx,
@@ -746,7 +173,7 @@ hipError_t launch_mid_compact(const int32_t* mid_cnt, int nwaves, int64_t bw, co
 // pass with more than skip_k rows the contraction is skipped (block 0 sets
 // S_HSKIP) and the control step re-evaluates if it needs this H.
 template <typename T>
-__global__ __launch_bounds__(256) void syrk_kernel(SyrkArgs a) {
+__device__ __forceinline__ void syrk_body(const SyrkArgs& a, int bx, int by, int npairs) {
     __shared__ double sI[SYRK_KB][SYRK_T + 1];
     __shared__ double sJ[SYRK_KB][SYRK_T + 1];
     __shared__ double cf[SYRK_KB];
@@ -759,18 +186,18 @@ __global__ __launch_bounds__(256) void syrk_kernel(SyrkArgs a) {
     const bool have_dir = (mode == PM_EVAL) && st[S_HAVE_DIR] != 0.0;
     const int64_t K = *a.list_total;
     const bool skip = have_dir && (double)K > a.skip_k;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) st[S_HSKIP] = skip ? 1.0 : 0.0;
+    if (bx == 0 && by == 0 && threadIdx.x == 0) st[S_HSKIP] = skip ? 1.0 : 0.0;
     if (skip) return;
     const double sig = (mode == PM_MULT) ? st[S_SIGMA_NEXT] : st[S_SIGMA];
     const T inv = (T)(1.0 / sig);
-    int p = blockIdx.x, I = 0;
+    int p = bx, I = 0;
     while (p >= a.ntile - I) {
         p -= a.ntile - I;
         ++I;
     }
     const int J = I + p;
     const int64_t per = (K + a.ksplit - 1) / a.ksplit;
-    const int64_t k0 = (int64_t)blockIdx.y * per, k1 = min(K, k0 + per);
+    const int64_t k0 = (int64_t)by * per, k1 = min(K, k0 + per);
     const T* C = static_cast<const T*>(a.C);
     const T* V = static_cast<const T*>(a.V);
     const T* U = static_cast<const T*>(a.U);
@@ -813,12 +240,16 @@ __global__ __launch_bounds__(256) void syrk_kernel(SyrkArgs a) {
             acc[1][1] += a1 * b1;
         }
     }
-    const int npairs = gridDim.x;
-    double* out = a.out + ((size_t)blockIdx.y * npairs + blockIdx.x) * SYRK_T * SYRK_T;
+    double* out = a.out + ((size_t)by * npairs + bx) * SYRK_T * SYRK_T;
     out[ty * SYRK_T + tx] = acc[0][0];
     out[ty * SYRK_T + tx + 16] = acc[0][1];
     out[(ty + 16) * SYRK_T + tx] = acc[1][0];
     out[(ty + 16) * SYRK_T + tx + 16] = acc[1][1];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void syrk_kernel(SyrkArgs a) {
+    syrk_body<T>(a, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 hipError_t launch_syrk(const SyrkArgs& a, hipStream_t s) {
@@ -879,15 +310,15 @@ __device__ void assemble_H(int d, const RecLayout& rl, const double* red, const 
 // Parallel assembly of H into the state (one thread per entry).  Runs after
 // the contraction and before the control step; it is a no-op when the run is
 // done.  The control step reads H only when it takes a Newton step.
-__global__ __launch_bounds__(256) void assemble_kernel(double* st, StateLayout sl, RecLayout rl, const double* red,
-                                                       const double* syrk, int ksplit, int ntile, int have_syrk) {
+__device__ __forceinline__ void assemble_body(double* st, StateLayout sl, RecLayout rl, const double* red,
+                                              const double* syrk, int ksplit, int ntile, int have_syrk, int bx) {
     const int mode = (int)st[S_MODE];
     if (mode == PM_DONE) return;
     if (have_syrk && st[S_HSKIP] != 0.0) return;
     const double sigma = (mode == PM_MULT) ? st[S_SIGMA_NEXT] : st[S_SIGMA];
     const double tau = st[S_TAU];
-    const int d = sl.n1 - 1, n1 = sl.n1;
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int n1 = sl.n1;
+    const int e = bx * 256 + threadIdx.x;
     if (e >= n1 * n1) return;
     const int a = e / n1, b = e % n1;
     const double base = tau / sigma + sigma * red[rl.ni];
@@ -919,6 +350,11 @@ __global__ __launch_bounds__(256) void assemble_kernel(double* st, StateLayout s
     st[sl.H + e] = v;
 }
 
+__global__ __launch_bounds__(256) void assemble_kernel(double* st, StateLayout sl, RecLayout rl, const double* red,
+                                                       const double* syrk, int ksplit, int ntile, int have_syrk) {
+    assemble_body(st, sl, rl, red, syrk, ksplit, ntile, have_syrk, blockIdx.x);
+}
+
 hipError_t launch_assemble(double* state, StateLayout sl, RecLayout rl, const double* red, const double* syrk,
                            int ksplit, int ntile, int have_syrk, hipStream_t s) {
     const int n = sl.n1 * sl.n1;
@@ -933,134 +369,181 @@ hipError_t launch_assemble(double* state, StateLayout sl, RecLayout rl, const do
 // place in global memory.
 // ---------------------------------------------------------------------------
 
-// Cholesky factorization M = L L^T in place (lower triangle, row-major n x n,
-// M in LDS or global memory), blocked right-looking with panels of CB
-// columns: wave 0 factors the CB x CB diagonal block (lanes own rows, no
-// block barrier), all threads then solve the panel below it row by row, and
-// update the trailing lower triangle in a 2-D thread layout.  Three block
-// barriers per panel instead of two per column.  rdiag receives 1 / L_jj.
-// Then the two triangular solves for b by wave 0 alone: lane l owns rows l,
-// l + 64, ...; each step broadcasts the new unknown with a lane shuffle.
-// Returns -1 if a pivot is not positive.
+// Cholesky solve of M y = b for SPD M (row-major, leading dimension ld >= n,
+// in LDS), blocked right-looking with CB-column panels.  The sequential parts
+// -- each CB x CB diagonal block and the triangular sub-solves -- run in the
+// registers of wave 0 (lane r holds row r of the block) and broadcast with
+// readlane instead of round trips through LDS; the panel below a block and
+// the trailing update use every thread, with three block barriers per panel.
+// Pivots use a reciprocal square root refined by two Newton steps instead of
+// an IEEE divide and square root.  rd receives 1 / L_jj.  Returns -1 if a
+// pivot is not positive.
 constexpr int CB = 16;
 
-template <int MAXR>
-__device__ int chol_solve_block(int n, double* M, double* b, double* rdiag) {
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// 1 / sqrt(x) to double precision for x > 0
+__device__ __forceinline__ double rsqrt_f64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
+}
+
+__device__ int chol_solve_lds(int n, int ld, double* M, double* b, double* rd) {
     __shared__ int bad;
     const int tid = threadIdx.x, nth = blockDim.x;
     if (tid == 0) bad = 0;
     __syncthreads();
     for (int j0 = 0; j0 < n; j0 += CB) {
         const int nb = min(CB, n - j0);
-        // (a) diagonal block by wave 0: lane r < nb owns row j0 + r
         if (tid < WAVE) {
             const int r = tid;
-            for (int c = 0; c < nb; ++c) {
-                const int jc = j0 + c;
-                double ajj = M[jc * n + jc];
-                // every lane reads the pivot after the owner's last update:
-                // the wave executes in lockstep, LDS/global order within a wave
-                const bool ok = ajj > 0.0;
-                if (!ok) {
-                    if (r == 0) bad = 1;
-                    break;
+            double a[CB];
+#pragma unroll
+            for (int k = 0; k < CB; ++k) a[k] = (r < nb && k <= r) ? M[(j0 + r) * ld + j0 + k] : 0.0;
+            int fail = 0;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                if (c < nb && !fail) {
+                    const double piv = readlane_f64(a[c], c);
+                    if (!(piv > 0.0)) {
+                        fail = 1;
+                    } else {
+                        const double il = rsqrt_f64(piv);
+                        if (r == c) a[c] = piv * il;
+                        if (r > c) a[c] *= il;
+                        if (r == 0) rd[j0 + c] = il;
+#pragma unroll
+                        for (int k = c + 1; k < CB; ++k) {
+                            const double lkc = readlane_f64(a[c], k);
+                            if (r >= k) a[k] -= a[c] * lkc;
+                        }
+                    }
                 }
-                const double ljj = sqrt(ajj);
-                const double rl = 1.0 / ljj;
-                if (r == c) {
-                    M[jc * n + jc] = ljj;
-                    rdiag[jc] = rl;
-                }
-                if (r > c && r < nb) M[(j0 + r) * n + jc] *= rl;
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                if (r > c && r < nb) {
-                    const double lrc = M[(j0 + r) * n + jc];
-                    for (int k = c + 1; k <= r; ++k) M[(j0 + r) * n + j0 + k] -= lrc * M[(j0 + k) * n + jc];
-                }
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+            if (fail && r == 0) bad = 1;
+            if (r < nb) {
+#pragma unroll
+                for (int k = 0; k < CB; ++k)
+                    if (k <= r) M[(j0 + r) * ld + j0 + k] = a[k];
             }
         }
         __syncthreads();
         if (bad) return -1;
-        // (b) panel below: row i solves L_ib L_bb^T = A_ib (forward in the block)
+        // panel below the block: L_ib = A_ib L_bb^-T, one row per thread
         for (int i = j0 + nb + tid; i < n; i += nth) {
-            for (int c = 0; c < nb; ++c) {
-                double v = M[i * n + j0 + c];
-                for (int k = 0; k < c; ++k) v -= M[i * n + j0 + k] * M[(j0 + c) * n + j0 + k];
-                M[i * n + j0 + c] = v * rdiag[j0 + c];
+            double v[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) v[c] = c < nb ? M[i * ld + j0 + c] : 0.0;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                if (c < nb) {
+                    double sacc = v[c];
+#pragma unroll
+                    for (int k = 0; k < c; ++k) sacc -= v[k] * M[(j0 + c) * ld + j0 + k];
+                    v[c] = sacc * rd[j0 + c];
+                }
             }
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+                if (c < nb) M[i * ld + j0 + c] = v[c];
         }
         __syncthreads();
-        // (c) trailing lower triangle: A_ik -= sum_c L_ic L_kc
+        // trailing lower triangle
         const int rem = n - j0 - nb;
         if (rem > 0) {
-            const int tx = tid & 31, ty = tid >> 5, nty = nth >> 5;
+            const int tx = tid & 15, ty = tid >> 4, nty = nth >> 4;
             for (int ii = ty; ii < rem; ii += nty) {
                 const int i = j0 + nb + ii;
                 double li[CB];
 #pragma unroll
-                for (int c = 0; c < CB; ++c) li[c] = c < nb ? M[i * n + j0 + c] : 0.0;
-                for (int kk = tx; kk <= ii; kk += 32) {
+                for (int c = 0; c < CB; ++c) li[c] = c < nb ? M[i * ld + j0 + c] : 0.0;
+                for (int kk = tx; kk <= ii; kk += 16) {
                     const int k = j0 + nb + kk;
                     double acc = 0.0;
 #pragma unroll
-                    for (int c = 0; c < CB; ++c)
-                        if (c < nb) acc += li[c] * M[k * n + j0 + c];
-                    M[i * n + k] -= acc;
+                    for (int c = 0; c < CB; ++c) acc += li[c] * M[k * ld + j0 + c];
+                    M[i * ld + k] -= acc;
                 }
             }
         }
         __syncthreads();
     }
-    if (tid < WAVE) {
-        const int lane = tid;
-        double bv[MAXR];
+    // forward L y = b: block solves in registers of wave 0, then the update
+    for (int j0 = 0; j0 < n; j0 += CB) {
+        const int nb = min(CB, n - j0);
+        if (tid < WAVE) {
+            const int r = tid;
+            double y = r < nb ? b[j0 + r] : 0.0;
+            double lrow[CB];
 #pragma unroll
-        for (int r = 0; r < MAXR; ++r) {
-            const int row = lane + r * WAVE;
-            bv[r] = row < n ? b[row] : 0.0;
-        }
-        // forward: L y = b
-        for (int j = 0; j < n; ++j) {
-            const int owner = j & (WAVE - 1), slot = j / WAVE;
-            double mine = 0.0;
+            for (int k = 0; k < CB; ++k) lrow[k] = (r < nb && k < r) ? M[(j0 + r) * ld + j0 + k] : 0.0;
 #pragma unroll
-            for (int r = 0; r < MAXR; ++r)
-                if (r == slot) mine = bv[r];
-            const double yj = __shfl(mine * rdiag[j], owner, WAVE);
-#pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-                const int row = lane + r * WAVE;
-                if (row == j) bv[r] = yj;
-                else if (row > j && row < n) bv[r] -= M[row * n + j] * yj;
+            for (int c = 0; c < CB; ++c) {
+                if (c < nb) {
+                    const double yc = readlane_f64(y * rd[j0 + c], c);
+                    if (r == c)
+                        y = yc;
+                    else if (r > c)
+                        y -= lrow[c] * yc;
+                }
             }
+            if (r < nb) b[j0 + r] = y;
         }
-        // backward: L^T x = y
-        for (int i = n - 1; i >= 0; --i) {
-            const int owner = i & (WAVE - 1), slot = i / WAVE;
-            double mine = 0.0;
+        __syncthreads();
+        for (int i = j0 + nb + tid; i < n; i += nth) {
+            double sacc = b[i];
 #pragma unroll
-            for (int r = 0; r < MAXR; ++r)
-                if (r == slot) mine = bv[r];
-            const double xi = __shfl(mine * rdiag[i], owner, WAVE);
-#pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-                const int row = lane + r * WAVE;
-                if (row == i) bv[r] = xi;
-                else if (row < i) bv[r] -= M[i * n + row] * xi;
-            }
+            for (int c = 0; c < CB; ++c)
+                if (c < nb) sacc -= M[i * ld + j0 + c] * b[j0 + c];
+            b[i] = sacc;
         }
-#pragma unroll
-        for (int r = 0; r < MAXR; ++r) {
-            const int row = lane + r * WAVE;
-            if (row < n) b[row] = bv[r];
-        }
+        __syncthreads();
     }
-    __syncthreads();
+    // backward L^T x = y from the last block
+    const int nblk = (n + CB - 1) / CB;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        const int j0 = bi * CB;
+        const int nb = min(CB, n - j0);
+        if (tid < WAVE) {
+            const int r = tid;
+            double x = r < nb ? b[j0 + r] : 0.0;
+            double lcol[CB];
+#pragma unroll
+            for (int k = 0; k < CB; ++k) lcol[k] = (r < nb && k > r && k < nb) ? M[(j0 + k) * ld + j0 + r] : 0.0;
+#pragma unroll
+            for (int c = CB - 1; c >= 0; --c) {
+                if (c < nb) {
+                    const double xc = readlane_f64(x * rd[j0 + c], c);
+                    if (r == c)
+                        x = xc;
+                    else if (r < c)
+                        x -= lcol[c] * xc;
+                }
+            }
+            if (r < nb) b[j0 + r] = x;
+        }
+        __syncthreads();
+        for (int i = tid; i < j0; i += nth) {
+            double sacc = b[i];
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+                if (c < nb) sacc -= M[(j0 + c) * ld + i] * b[j0 + c];
+            b[i] = sacc;
+        }
+        __syncthreads();
+    }
     return 0;
 }
+
+// leading dimension of the LDS copy: odd, so that consecutive rows fall in
+// different LDS banks
+__host__ __device__ inline int chol_ld(int n) { return n | 1; }
 
 // Solve with n above the register budget of the wave-level solves: the
 // triangular solves by the whole block, column oriented.
@@ -1108,42 +591,35 @@ __device__ int chol_solve_block_large(int n, double* M, double* b, double* vec) 
     return 0;
 }
 
-// n <= 192: wave-level triangular solves with 3 rows per lane
-constexpr int CHOL_WAVE_MAX_N = 192;
 
-// vec: scratch of at least n doubles (LDS preferred)
-__device__ int chol_solve_any(int n, double* M, double* b, double* vec) {
-    if (n <= CHOL_WAVE_MAX_N) return chol_solve_block<3>(n, M, b, vec);
-    return chol_solve_block_large(n, M, b, vec);
-}
 
-// Kernels that take more than 64 KiB of dynamic LDS opt in once per size.
-static hipError_t ensure_dynamic_lds(const void* fn, size_t bytes) {
-    if (bytes <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-constexpr int CHOL_LDS_MAX_N = 140;  // 140^2 doubles + vectors < 160 KiB
+constexpr int CHOL_LDS_MAX_N = 140;  // 140 x 141 doubles + vectors < 160 KiB
 constexpr int CTRL_THREADS = 1024;
 // the control kernel also keeps CTRL_THREADS doubles of scratch in LDS
-constexpr int CTRL_CHOL_LDS_MAX_N = 136;
+constexpr int CTRL_CHOL_LDS_MAX_N = 132;  // 1024 + 132 x 133 doubles < 160 KiB
 
 __global__ __launch_bounds__(CTRL_THREADS) void chol_solve_kernel(int n, double* A, double* b, int* info) {
     extern __shared__ double sm[];
     int rc;
     if (n <= CHOL_LDS_MAX_N) {
-        double* M = sm + n;
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] = A[e];
+        // LDS: rd (n), rhs (n), M (n x ld)
+        const int ld = chol_ld(n);
+        double* rd = sm;
+        double* bv = sm + n;
+        double* M = sm + 2 * n;
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[(e / n) * ld + e % n] = A[e];
+        for (int e = threadIdx.x; e < n; e += blockDim.x) bv[e] = b[e];
         __syncthreads();
-        rc = chol_solve_any(n, M, b, sm);
+        rc = chol_solve_lds(n, ld, M, bv, rd);
+        for (int e = threadIdx.x; e < n; e += blockDim.x) b[e] = bv[e];
     } else {
-        rc = chol_solve_any(n, A, b, sm);
+        rc = chol_solve_block_large(n, A, b, sm);
     }
     if (threadIdx.x == 0) *info = rc;
 }
 
 hipError_t launch_chol_solve(int n, double* A, double* b, int* info, hipStream_t s) {
-    size_t lds = sizeof(double) * (size_t)(n <= CHOL_LDS_MAX_N ? n * n + n : n);
+    size_t lds = sizeof(double) * (size_t)(n <= CHOL_LDS_MAX_N ? (size_t)n * chol_ld(n) + 2 * n : n);
     hipError_t ea = ensure_dynamic_lds((const void*)chol_solve_kernel, lds);
     if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(CTRL_THREADS), lds, s, n, A, b, info);
@@ -1170,11 +646,10 @@ __device__ double block_sum(double v, double* scratch) {
     return r;
 }
 
-__global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, StateLayout sl, RecLayout rl,
-                                                               const double* red, int* flag) {
+__device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayout rl, const double* red) {
     extern __shared__ double sm[];
-    double* scratch = sm;                                        // max(CTRL_THREADS, n1)
-    double* lmat = sm + (CTRL_THREADS > sl.n1 ? CTRL_THREADS : sl.n1);  // Cholesky matrix when it fits
+    double* scratch = sm;                                                    // max(CTRL_THREADS, 2 n1)
+    double* lmat = sm + (CTRL_THREADS > 2 * sl.n1 ? CTRL_THREADS : 2 * sl.n1);  // Cholesky matrix when it fits
     __shared__ int s_next;                   // 0 = continue to EVAL_AT_BASE, 1 = return
     __shared__ double s_eta;
     const int mode = (int)st[S_MODE];
@@ -1247,7 +722,6 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
         for (int k = threadIdx.x; k < n1; k += blockDim.x) ab[k] -= sigma * L * L * gb[k];
         __syncthreads();
         if (s_next) {
-            if (threadIdx.x == 0 && flag) *flag = 1;
             return;
         }
         // next outer iteration: sigma, proximal center
@@ -1290,6 +764,9 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
                     break;
                 }
             }
+            if (st[S_VERBOSE] >= 2.0)
+                printf("[meb]   armijo acc=%d gd=%.17g psi0=%.17g dpsi1=%.17g\n", acc, gd, psi0,
+                       dir[0] + 0.5 * sg * (red[rl.trial] - z0) + tau / (2.0 * sg) * (2.0 * dxd + dd));
             if (acc == 0 && st[S_HSKIP] != 0.0) {
                 // full step, but its Hessian contraction was skipped:
                 // move there and evaluate again
@@ -1329,7 +806,6 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
             } else {
                 for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] *= eta;
             }
-            if (threadIdx.x == 0 && flag) *flag = 1;
             return;  // next pass re-evaluates at x_base (mode EVAL)
         }
         __syncthreads();
@@ -1359,6 +835,9 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
         const double rhs = st[S_RHO] * (red[rl.dm] + tN * xx / (L * L));
         const double floor_g = 8.0 * eps * (1.0 + sgm * red[rl.rs]);
         const bool stop = (lhs <= rhs) || (sqrt(gg) <= floor_g) || (st[S_J] >= st[S_MAX_INNER]);
+        if (st[S_VERBOSE] >= 2.0)
+            printf("[meb]   eval x0=%.17g |g|=%.6e lhs=%.6e rhs=%.6e floor=%.3e dm=%.6e stop=%d\n", xb[0], sqrt(gg),
+                   lhs, rhs, floor_g, red[rl.dm], (int)stop);
         if (stop) {
             st[S_MODE] = (double)PM_MULT;
             st[S_HAVE_DIR] = 0.0;
@@ -1368,26 +847,29 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
         }
     }
     __syncthreads();
-    if (s_next) {
-        if (threadIdx.x == 0 && flag) *flag = 1;
-        return;
-    }
+    if (s_next) return;
     // Newton direction: H dir = -g, H assembled by assemble_kernel
-    for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = -gb[k];
     int rc;
     if (n1 <= CTRL_CHOL_LDS_MAX_N) {
-        for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) lmat[e] = H[e];
+        // LDS: scratch = [rd (n1) | rhs (n1)], lmat = H with an odd leading dimension
+        const int ld = chol_ld(n1);
+        double* rd = scratch;
+        double* bv = scratch + n1;
+        for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) lmat[(e / n1) * ld + e % n1] = H[e];
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
         __syncthreads();
-        rc = chol_solve_any(n1, lmat, dir, scratch);
+        rc = chol_solve_lds(n1, ld, lmat, bv, rd);
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
+        __syncthreads();
     } else {
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = -gb[k];
         __syncthreads();
-        rc = chol_solve_any(n1, H, dir, scratch);
+        rc = chol_solve_block_large(n1, H, dir, scratch);
     }
     if (rc != 0) {
         if (threadIdx.x == 0) {
             st[S_STATUS] = -1.0;
             st[S_MODE] = (double)PM_DONE;
-            if (flag) *flag = 1;
         }
         return;
     }
@@ -1399,18 +881,181 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
         st[S_HAVE_DIR] = 1.0;
         st[S_LSH] = 0.0;
         st[S_MODE] = (double)PM_EVAL;
-        if (flag) *flag = 1;
     }
 }
 
+// `flag` (nullable, typically host-mapped) receives the state's mode after
+// the step, so a host can learn that the run has ended without a copy.
+__global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, StateLayout sl, RecLayout rl,
+                                                               const double* red, int* flag) {
+    control_body(st, sl, rl, red);
+    if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
+}
+
+size_t control_lds_bytes(int n1) {
+    size_t lds = sizeof(double) * (size_t)(CTRL_THREADS > 2 * n1 ? CTRL_THREADS : 2 * n1);
+    if (n1 <= CTRL_CHOL_LDS_MAX_N) lds += sizeof(double) * (size_t)n1 * chol_ld(n1);
+    return lds;
+}
+
 hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag, hipStream_t s) {
-    const int n1 = sl.n1;
-    size_t lds = sizeof(double) * (size_t)(CTRL_THREADS > n1 ? CTRL_THREADS : n1);
-    if (n1 <= CTRL_CHOL_LDS_MAX_N) lds += sizeof(double) * (size_t)(n1 * n1 + n1);
+    const size_t lds = control_lds_bytes(sl.n1);
     hipError_t ea = ensure_dynamic_lds((const void*)control_kernel, lds);
     if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL(control_kernel, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, rl, red, flag);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// One solver step for several instances (a tick of the multi-instance
+// server): the same bodies as the single-instance kernels, with each
+// instance's blocks located by the tick list.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int reduce_nslice_dev(int nrec) {
+    int nslice = (nrec + 15) / 16;
+    if (nslice > RED_SLICE) nslice = RED_SLICE;
+    if (nslice < 1) nslice = 1;
+    return nslice;
+}
+
+__global__ __launch_bounds__(256) void reduce1_batch_kernel(const BatchItem* tab, TickList L, int max_lo, int max_hi) {
+    const int k = tick_find(L, blockIdx.x);
+    const BatchItem& it = tab[L.slot[k]];
+    const int b = blockIdx.x - L.off[k];
+    const int len = it.pa.rl.len;
+    const int nx = (len + 63) / 64;
+    reduce1_body(it.pa.rec, it.pc.blocks, len, (int64_t)WPB * len, max_lo, max_hi, it.red + len, b % nx, b / nx,
+                 reduce_nslice_dev(it.pc.blocks));
+}
+
+__global__ __launch_bounds__(256) void reduce2_batch_kernel(const BatchItem* tab, TickList L, int max_lo, int max_hi) {
+    const int k = tick_find(L, blockIdx.x);
+    const BatchItem& it = tab[L.slot[k]];
+    const int len = it.pa.rl.len;
+    reduce2_body(it.red + len, reduce_nslice_dev(it.pc.blocks), len, max_lo, max_hi, it.red, blockIdx.x - L.off[k]);
+}
+
+__global__ __launch_bounds__(1024) void mid_scan_batch_kernel(const BatchItem* tab, TickList L) {
+    const BatchItem& it = tab[L.slot[blockIdx.x]];
+    mid_scan_body(it.pa.mid_cnt, it.pc.nwaves, it.list_offs, const_cast<int64_t*>(it.sa.list_total), it.pa.state);
+}
+
+__global__ __launch_bounds__(256) void mid_copy_batch_kernel(const BatchItem* tab, TickList L) {
+    const int k = tick_find(L, blockIdx.x);
+    const BatchItem& it = tab[L.slot[k]];
+    mid_copy_body(it.pa.mid_cnt, it.pc.nwaves, it.pc.bw, it.pa.mid_idx, it.pa.mid_coef, it.list_offs,
+                  const_cast<int32_t*>(it.sa.list_idx), const_cast<double*>(it.sa.list_coef), it.pa.state,
+                  blockIdx.x - L.off[k]);
+}
+
+__global__ __launch_bounds__(256) void syrk_batch_kernel(const BatchItem* tab, TickList L) {
+    const int k = tick_find(L, blockIdx.x);
+    const BatchItem& it = tab[L.slot[k]];
+    const int b = blockIdx.x - L.off[k];
+    const int npairs = it.ntile * (it.ntile + 1) / 2;
+    if (it.sa.dtype == 0)
+        syrk_body<double>(it.sa, b % npairs, b / npairs, npairs);
+    else
+        syrk_body<float>(it.sa, b % npairs, b / npairs, npairs);
+}
+
+__global__ __launch_bounds__(256) void assemble_batch_kernel(const BatchItem* tab, TickList L) {
+    const int k = tick_find(L, blockIdx.x);
+    const BatchItem& it = tab[L.slot[k]];
+    assemble_body(const_cast<double*>(it.pa.state), it.pa.sl, it.pa.rl, it.red, it.sa.out, it.ksplit, it.ntile, it.use_syrk,
+                  blockIdx.x - L.off[k]);
+}
+
+__global__ __launch_bounds__(CTRL_THREADS) void control_batch_kernel(const BatchItem* tab, TickList L) {
+    const BatchItem& it = tab[L.slot[blockIdx.x]];
+    double* st = const_cast<double*>(it.pa.state);
+    control_body(st, it.pa.sl, it.pa.rl, it.red);
+    if (threadIdx.x == 0 && it.flag) *it.flag = (int)st[S_MODE];
+}
+
+namespace {
+// fills L with the items' slots and block offsets; returns the total blocks
+template <class F>
+int make_list(const BatchItem* htab, const int* slots, int n, TickList& L, F&& blocks_of) {
+    L.n = n;
+    int off = 0;
+    for (int k = 0; k < n; ++k) {
+        L.slot[k] = slots[k];
+        L.off[k] = off;
+        off += blocks_of(htab[slots[k]]);
+    }
+    L.off[n] = off;
+    return off;
+}
+}  // namespace
+
+hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* slots, int n, hipStream_t s) {
+    const RecLayout r0 = RecLayout::make(0);
+    const int max_lo = r0.kmax, max_hi = r0.kmax + 3;
+    for (int c0 = 0; c0 < n; c0 += TICK_MAX) {
+        const int cn = n - c0 < TICK_MAX ? n - c0 : TICK_MAX;
+        const int* sl = slots + c0;
+        TickList L;
+        // evaluation passes, one launch per template instance
+        {
+            int ids[TICK_MAX];
+            bool done[TICK_MAX];
+            for (int k = 0; k < cn; ++k) {
+                ids[k] = pass_variant(htab[sl[k]].pa.dtype, htab[sl[k]].pc);
+                done[k] = false;
+            }
+            for (int k = 0; k < cn; ++k) {
+                if (done[k]) continue;
+                int grp[TICK_MAX];
+                int ng = 0, max_d = 0;
+                for (int q = k; q < cn; ++q)
+                    if (!done[q] && ids[q] == ids[k]) {
+                        grp[ng++] = sl[q];
+                        done[q] = true;
+                        if (htab[sl[q]].pa.d > max_d) max_d = htab[sl[q]].pa.d;
+                    }
+                const int blocks = make_list(htab, grp, ng, L, [](const BatchItem& it) { return it.pc.blocks; });
+                const hipError_t e =
+                    launch_pass_group(dtab, L, blocks, max_d, htab[grp[0]].pa.dtype, htab[grp[0]].pc, s);
+                if (e != hipSuccess) return e;
+            }
+        }
+        int nb = make_list(htab, sl, cn, L, [](const BatchItem& it) {
+            return ((it.pa.rl.len + 63) / 64) * reduce_nslice(it.pc.blocks);
+        });
+        hipLaunchKernelGGL(reduce1_batch_kernel, dim3(nb), dim3(256), 0, s, dtab, L, max_lo, max_hi);
+        nb = make_list(htab, sl, cn, L, [](const BatchItem& it) { return (it.pa.rl.len + 255) / 256; });
+        hipLaunchKernelGGL(reduce2_batch_kernel, dim3(nb), dim3(256), 0, s, dtab, L, max_lo, max_hi);
+        // mid-list compaction and contraction for the instances that use it
+        int ws[TICK_MAX];
+        int nw = 0;
+        for (int k = 0; k < cn; ++k)
+            if (htab[sl[k]].use_syrk && htab[sl[k]].pa.want_mid) ws[nw++] = sl[k];
+        if (nw > 0) {
+            make_list(htab, ws, nw, L, [](const BatchItem&) { return 1; });
+            hipLaunchKernelGGL(mid_scan_batch_kernel, dim3(nw), dim3(1024), 0, s, dtab, L);
+            nb = make_list(htab, ws, nw, L, [](const BatchItem& it) { return (it.pc.nwaves + 3) / 4; });
+            hipLaunchKernelGGL(mid_copy_batch_kernel, dim3(nb), dim3(256), 0, s, dtab, L);
+            nb = make_list(htab, ws, nw, L,
+                           [](const BatchItem& it) { return it.ntile * (it.ntile + 1) / 2 * it.ksplit; });
+            hipLaunchKernelGGL(syrk_batch_kernel, dim3(nb), dim3(256), 0, s, dtab, L);
+        }
+        nb = make_list(htab, sl, cn, L, [](const BatchItem& it) { return (it.pa.sl.n1 * it.pa.sl.n1 + 255) / 256; });
+        hipLaunchKernelGGL(assemble_batch_kernel, dim3(nb), dim3(256), 0, s, dtab, L);
+        size_t lds = 0;
+        for (int k = 0; k < cn; ++k) {
+            const size_t b = control_lds_bytes(htab[sl[k]].pa.sl.n1);
+            if (b > lds) lds = b;
+        }
+        make_list(htab, sl, cn, L, [](const BatchItem&) { return 1; });
+        const hipError_t ea = ensure_dynamic_lds((const void*)control_batch_kernel, lds);
+        if (ea != hipSuccess) return ea;
+        hipLaunchKernelGGL(control_batch_kernel, dim3(cn), dim3(CTRL_THREADS), lds, s, dtab, L);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // g and H of a single evaluation (meb_al_eval).

@@ -80,3 +80,22 @@ def serving_instance(m, d, seed, rmax=0.05):
     """One request: centers N(0, I), radii uniform in [0, rmax]."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((m, d)), rng.uniform(0.0, rmax, m)
+
+
+def poisson_arrivals(n, rate, seed):
+    """Arrival times (s) of a Poisson stream of n requests at `rate` per s."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+def serving_bank_device(n_doubles, n_radii, seed, rmax=0.05, device="cuda"):
+    """Device-resident random numbers for a long request stream: iid N(0, 1)
+    FP64 values (request centers are row-major windows of it) and radii
+    uniform in [0, rmax].  Drawn on the device from torch's seeded generator,
+    so a multi-gigabyte stream needs no host-side generation."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    Z = torch.randn(int(n_doubles), dtype=torch.float64, device=device, generator=g)
+    Rb = torch.rand(int(n_radii), dtype=torch.float64, device=device, generator=g) * rmax
+    return Z, Rb

@@ -25,7 +25,8 @@ WANT_ALL = 63
 
 EXPORTS = ["meb_default_options", "meb_last_error", "meb_workspace_size", "meb_eval_workspace_size", "meb_solve",
            "meb_al_eval", "meb_screen", "meb_check_feasible", "meb_prepare_f32", "meb_chol_workspace_size",
-           "meb_chol_solve"]
+           "meb_chol_solve", "meb_server_create", "meb_server_submit", "meb_server_poll", "meb_server_info",
+           "meb_server_destroy", "meb_sched_simulate"]
 
 
 class Options(ctypes.Structure):
@@ -53,6 +54,20 @@ class Stats(ctypes.Structure):
                     ms_phase=list(self.ms_phase), pass_ms=list(self.pass_ms), pass_bytes=list(self.pass_bytes),
                     pass_launches=list(self.pass_launches), mid_rows=list(self.mid_rows),
                     mid_rows_max=list(self.mid_rows_max))
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("tag", ctypes.c_int64), ("m", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("r", ctypes.c_double), ("t_submit_ms", ctypes.c_double),
+                ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double), ("stats", Stats),
+                ("message", ctypes.c_char * 128)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("queued", ctypes.c_int32), ("active", ctypes.c_int32), ("pool_used", ctypes.c_uint64),
+                ("pool_peak", ctypes.c_uint64), ("pool_capacity", ctypes.c_uint64), ("ticks", ctypes.c_int64),
+                ("mean_tick_items", ctypes.c_double), ("message", ctypes.c_char * 128)]
 
 
 class MebError(RuntimeError):
@@ -87,6 +102,17 @@ def _load():
                                   _vp]
     L.meb_chol_workspace_size.argtypes = [ctypes.c_int32, _szp]
     L.meb_chol_solve.argtypes = [ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.meb_server_create.argtypes = [_vp, ctypes.c_size_t, ctypes.POINTER(Options), ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(_vp)]
+    L.meb_server_submit.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                    _dp, _i64p]
+    L.meb_server_poll.argtypes = [_vp, ctypes.POINTER(ServerResult), ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.POINTER(ctypes.c_int32)]
+    L.meb_server_info.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+    L.meb_server_destroy.argtypes = [_vp]
+    _u64p = ctypes.POINTER(ctypes.c_uint64)
+    L.meb_sched_simulate.argtypes = [ctypes.c_int32, _dp, _dp, _u64p, ctypes.c_uint64, ctypes.c_int32, _dp, _dp,
+                                     _u64p]
     return L
 
 
@@ -235,3 +261,77 @@ def chol_solve(H, b):
     y = torch.empty_like(b)
     _check(lib.meb_chol_solve(n, _ptr(H), _ptr(b), _ptr(y), _ptr(ws), ws.numel(), _stream()))
     return y
+
+
+class Server:
+    """meb_server_* on a device pool of `pool_bytes`.  submit() keeps the
+    request's tensors and its host center buffer alive until its result is
+    polled."""
+
+    def __init__(self, pool_bytes, opts=None, max_active=128, max_d=256, device="cuda", **kw):
+        o = opts if opts is not None else options(**kw)
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
+        if self.pool.data_ptr() % 256:
+            raise MebError("pool allocation is not 256-byte aligned")
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _check(lib.meb_server_create(_ptr(self.pool), self.pool.numel(), ctypes.byref(o), max_active, max_d,
+                                     ctypes.byref(h)))
+        self.h = h
+        self.live = {}
+
+    def submit(self, C, R=None, tag=0):
+        assert C.is_cuda and C.is_contiguous() and C.dim() == 2
+        m, d = C.shape
+        c_out = np.zeros(d)
+        t = ctypes.c_int64()
+        _check(lib.meb_server_submit(self.h, _ptr(C), _ptr(R), m, d, _dtype_code(C), int(tag),
+                                     c_out.ctypes.data_as(_dp), ctypes.byref(t)))
+        self.live[t.value] = (C, R, c_out)
+        return t.value
+
+    def poll(self, wait_ms=0, cap=256):
+        buf = (ServerResult * cap)()
+        n = ctypes.c_int32()
+        _check(lib.meb_server_poll(self.h, buf, cap, int(wait_ms), ctypes.byref(n)))
+        out = []
+        for k in range(n.value):
+            r = buf[k]
+            _, _, c = self.live.pop(r.ticket, (None, None, None))
+            out.append(dict(ticket=r.ticket, tag=r.tag, m=r.m, d=r.d, status=r.status, r=r.r, c=c,
+                            t_submit_ms=r.t_submit_ms, t_admit_ms=r.t_admit_ms, t_done_ms=r.t_done_ms,
+                            stats=r.stats.as_dict(), message=r.message.decode()))
+        return out
+
+    def info(self):
+        st = ServerStats()
+        _check(lib.meb_server_info(self.h, ctypes.byref(st)))
+        return {k: (getattr(st, k).decode() if k == "message" else getattr(st, k)) for k, _ in st._fields_}
+
+    def close(self):
+        if self.h:
+            _check(lib.meb_server_destroy(self.h))
+            self.h = None
+            self.live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sched_simulate(arrival, service, nbytes, pool_bytes, max_active):
+    """meb_sched_simulate: the server's admission policy on a simulated clock.
+    Returns (t_admit, t_done, offset) arrays."""
+    arrival = np.ascontiguousarray(arrival, dtype=np.float64)
+    service = np.ascontiguousarray(service, dtype=np.float64)
+    nbytes = np.ascontiguousarray(nbytes, dtype=np.uint64)
+    n = arrival.shape[0]
+    ta, td = np.empty(n), np.empty(n)
+    off = np.empty(n, dtype=np.uint64)
+    u64 = ctypes.POINTER(ctypes.c_uint64)
+    _check(lib.meb_sched_simulate(n, arrival.ctypes.data_as(_dp), service.ctypes.data_as(_dp),
+                                  nbytes.ctypes.data_as(u64), int(pool_bytes), int(max_active),
+                                  ta.ctypes.data_as(_dp), td.ctypes.data_as(_dp), off.ctypes.data_as(u64)))
+    return ta, td, off
