@@ -13,6 +13,16 @@ kernel): algorithmic bytes it reads and writes (centers, radii, multipliers;
 counted on the device per launch) over its launch durations, both measured
 live with HIP events on the solve's stream during the timed steps.
 `cpu_baseline` runs the CPU oracle on a bounded sample of the same instance.
+
+`serving` is the request-stream leg: requests with m log-uniform in
+[1e3, 1e6], d uniform over {2, 3, 10, 50, 200}, centers N(0, I), radii
+uniform in [0, 0.05], arriving as a Poisson stream, solved in mixed
+precision by the multi-instance server (meb_server_*).  Request data are
+windows of one device-resident bank of random numbers, so the stream needs
+no host-side generation; a request is submitted at its arrival time and its
+latency runs from submission to completion.  The leg first measures the
+saturation throughput (every request queued at once), then replays the
+stream at a fraction of it and reports p50 / p99 latency and solves/s.
 """
 import argparse
 import json
@@ -61,6 +71,94 @@ def cpu_baseline(C, R, m_full, sample_m):
                        f"({el:.2f} s), scaled by {m_full}/{sample_m}")
 
 
+def serving_leg(n_req, load, seed, max_active, pool_gb, check_sample, log):
+    """Saturation run, then a Poisson stream at `load` x saturation rate."""
+    import torch
+
+    from paper_2605_31425_amd import inputs, meb
+
+    reqs = inputs.serving_requests(n_req, seed)
+    need = max(m * d for m, d, _ in reqs)
+    mmax = max(m for m, _, _ in reqs)
+    bank_n = max(need * 5 // 4, 1 << 20)
+    Z, Rb = inputs.serving_bank_device(bank_n, mmax * 2, seed)
+    rng = np.random.default_rng(seed + 1)
+    views = []
+    for m, d, _ in reqs:
+        o = int(rng.integers(0, (bank_n - m * d) // 2 + 1)) * 2  # 16-byte aligned rows
+        ro = int(rng.integers(0, mmax + 1))
+        views.append((Z[o:o + m * d].view(m, d), Rb[ro:ro + m]))
+    torch.cuda.synchronize()
+    opts = meb.options(mode="mixed")
+
+    def run(arrivals):
+        srv = meb.Server(int(pool_gb * (1 << 30)), opts=opts, max_active=max_active, max_d=256)
+        res = {}
+        try:
+            t0 = time.perf_counter()
+            i = 0
+            while len(res) < n_req:
+                now = time.perf_counter() - t0
+                while i < n_req and arrivals[i] <= now:
+                    C, R = views[i]
+                    srv.submit(C, R, tag=i)
+                    i += 1
+                wait = 0 if i < n_req else 50
+                if i < n_req:
+                    wait = max(0, min(2, int((arrivals[i] - (time.perf_counter() - t0)) * 1e3)))
+                for r in srv.poll(wait_ms=wait, cap=1024):
+                    res[r["tag"]] = r
+            info = srv.info()
+        finally:
+            srv.close()
+        bad = [r for r in res.values() if r["status"] < 0]
+        if bad:
+            raise RuntimeError(f"serving: {len(bad)} requests failed: {bad[0]['message']}")
+        lat = np.array([res[k]["t_done_ms"] - res[k]["t_submit_ms"] for k in range(n_req)])
+        t_first = min(r["t_submit_ms"] for r in res.values())
+        t_last = max(r["t_done_ms"] for r in res.values())
+        return res, lat, n_req / ((t_last - t_first) / 1e3), info
+
+    _, lat_sat, thr_sat, info_sat = run(np.zeros(n_req))
+    log(f"serving saturation: {thr_sat:.1f} solves/s, mean tick items {info_sat['mean_tick_items']:.1f}")
+    rate = load * thr_sat
+    arr = inputs.poisson_arrivals(n_req, rate, seed + 2)
+    res, lat, thr, info = run(arr)
+    log(f"serving stream at {rate:.1f}/s: p50 {np.percentile(lat, 50):.2f} ms p99 {np.percentile(lat, 99):.2f} ms")
+    # sample: bitwise equal to meb_solve alone, and feasible in FP64
+    idx = sorted(rng.choice(n_req, size=min(check_sample, n_req), replace=False).tolist())
+    same, viol = True, -np.inf
+    for k in idx:
+        C, R = views[k]
+        r, c, _ = meb.solve(C, R, opts=opts)
+        same = same and (r == res[k]["r"]) and bool(np.array_equal(c, res[k]["c"]))
+        dmax, _, _, _ = meb.check_feasible(C, R, res[k]["r"], res[k]["c"], np.inf, viol_cap=0)
+        viol = max(viol, dmax / (1 + res[k]["r"]))
+    ms = np.array([m for m, _, _ in reqs])
+    return {
+        "requests": n_req,
+        "arrivals": "poisson",
+        "arrival_rate_per_s": rate,
+        "load_vs_saturation": load,
+        "solves_per_s": thr,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "mean_ms": float(lat.mean()),
+        "saturation_solves_per_s": thr_sat,
+        "saturation_p50_ms": float(np.percentile(lat_sat, 50)),
+        "saturation_p99_ms": float(np.percentile(lat_sat, 99)),
+        "mean_requests_per_tick": info["mean_tick_items"],
+        "ticks": info["ticks"],
+        "pool_peak_GB": info["pool_peak"] / 1e9,
+        "max_active": max_active,
+        "m_range": [int(ms.min()), int(ms.max())],
+        "dims": sorted(set(d for _, d, _ in reqs)),
+        "sample_checked": len(idx),
+        "sample_bitwise_equal_to_meb_solve": same,
+        "sample_max_violation_rel": viol,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +169,13 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=100000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-max-active", type=int, default=128)
+    ap.add_argument("--serve-pool-gb", type=float, default=64.0)
+    ap.add_argument("--serve-check", type=int, default=8)
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (3 times), to scale HBM byte counters")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
@@ -79,7 +184,20 @@ def main():
 
     import torch
 
+    if a.copy_calibration > 0:
+        n = int(a.copy_calibration * (1 << 30)) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
+        return
+
     from paper_2605_31425_amd import inputs, meb
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     wl = WORKLOADS[a.workload]
     gen = getattr(inputs, wl["gen"])
@@ -175,6 +293,11 @@ def main():
             "algorithmic_bytes_per_launch": (p_bytes / p_launch) if p_launch else None,
         },
     }
+    del ws, ws64, Cd, Rd
+    torch.cuda.empty_cache()
+    if a.serve_requests > 0:
+        out["serving"] = serving_leg(a.serve_requests, a.serve_load, 5, a.serve_max_active, a.serve_pool_gb,
+                                     a.serve_check, log)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(C, R, m, min(a.cpu_sample, m))
     print(json.dumps(out), flush=True)

@@ -34,9 +34,49 @@ constexpr int WPB = PASS_THREADS / WAVE;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// Cross-lane moves through the DPP modifier of a VALU instruction (no LDS
+// round trip).  Patterns used: quad_perm [1,0,3,2] (lane ^ 1), quad_perm
+// [2,3,0,1] (lane ^ 2), row_half_mirror (lane i <- 7 - i within 8 lanes) and
+// row_mirror (lane i <- 15 - i within 16 lanes); every source lane stays in
+// its row, so all lanes are valid.
+constexpr int DPP_XOR1 = 0xB1;
+constexpr int DPP_XOR2 = 0x4E;
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// lane ^ 16 within each half of the wave (ds_swizzle, bit mode)
+__device__ __forceinline__ float swz_xor16(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+}
+__device__ __forceinline__ double swz_xor16(double v) {
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over each aligned group of G lanes (G a power of two, wave-uniform),
+// returned in every lane of the group.  Each step adds a lane's partner
+// value, so all lanes of a group end with bitwise the same sum.
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int G) {
-    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    if (G >= 2) v += dpp_move<DPP_XOR1>(v);
+    if (G >= 4) v += dpp_move<DPP_XOR2>(v);
+    if (G >= 8) v += dpp_move<DPP_HALF_MIRROR>(v);
+    if (G >= 16) v += dpp_move<DPP_MIRROR>(v);
+    if (G >= 32) v += swz_xor16(v);
+    if (G >= 64) v += __shfl_xor(v, 32, WAVE);
     return v;
 }
 
@@ -186,6 +226,30 @@ struct FlushPeriod<float> {
     static constexpr int steps = 64;  // FP32 partial sums cover at most 64 balls per lane
 };
 
+// LDS of the pass: y and dir in FP64 (2d), a block reduction buffer, y and
+// dir in the working precision (2d + 4), then per wave a flush scratch of
+// WAVE x FLW values.  FLW = NLMAX * VEC when a wave can hold several groups
+// (that needs at most 8 elements per lane), else 0.
+template <int VEC, int NLMAX>
+__host__ __device__ constexpr int pass_flush_width() {
+    return NLMAX * VEC <= 8 ? NLMAX * VEC : 0;
+}
+template <typename T>
+__host__ __device__ inline size_t pass_lds_head(int d) {  // in doubles
+    return 2 * (size_t)d + PASS_THREADS + (sizeof(T) * (2 * (size_t)d + 4) + 7) / 8;
+}
+template <typename T, int VEC, int NLMAX>
+__host__ __device__ inline size_t pass_lds_bytes(int d) {
+    return sizeof(double) * pass_lds_head<T>(d) + sizeof(T) * (size_t)WPB * WAVE * pass_flush_width<VEC, NLMAX>();
+}
+
+// Loads of one ball by one lane: its share of the row, the radius and u.
+template <typename T, int VEC, int NLMAX>
+struct BallLoad {
+    RowVec<T, VEC> c[NLMAX];
+    T r, u;
+};
+
 // The evaluation pass over one wave's contiguous range of balls.
 //
 // KIND 0: evaluation at y = x_base + dir (Psi trials along the segment,
@@ -196,9 +260,12 @@ struct FlushPeriod<float> {
 //         the next outer iteration at sigma_{k+1}.
 // TRL: Armijo trials per lane (ceil(NT / G) rounded up to 1, 3 or 9).
 //
-// Loads are software-pipelined: the rows (and radii, u) of the next group of
-// balls are requested before the current group is processed, so each wave
-// keeps two steps of loads in flight.
+// Every lane of a ball's group computes the ball's scalars redundantly (the
+// group sums leave the same value in all of them); the group leader's copy
+// is the one that reaches the record.  Lanes that own no part of a load read
+// a valid address of the same row and discard it, so the loop has no
+// per-element branches.  Loads are software-pipelined two groups deep: the
+// loop body is unrolled twice over two load buffers.
 template <typename T, int VEC, int NLMAX, int KIND, int TRL>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& cfg, int blk) {
     extern __shared__ double lds[];
@@ -206,12 +273,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     const int d = a.d;
     const int G = cfg.G;
     const int nl = cfg.nl;
-    const StateLayout sl = a.sl;
     const RecLayout rl = a.rl;
+    const StateLayout sl = a.sl;
 
-    const bool have_dir = (KIND != 2) && st[S_HAVE_DIR] != 0.0;
     constexpr bool is_mult = (KIND == 2);
     constexpr bool want_kkt = (KIND != 0);
+    const bool have_dir = (KIND != 2) && st[S_HAVE_DIR] != 0.0;
 
     // the evaluation point y = x_base + dir and the direction, staged in LDS
     double* l_c = lds;
@@ -258,41 +325,48 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     const int64_t wbeg = gw * cfg.bw;
     const int64_t wend = min(a.m, wbeg + cfg.bw);
     const T es_bytes = (T)sizeof(T);
+    const T row_bytes = es_bytes * (T)(d + (R ? 1 : 0) + (U ? 1 : 0));
 
-    // per-lane owned elements; y and dir in the working precision in LDS
-    // (read per use: they would cost 4 registers per owned element)
+    // y and dir in the working precision, read from LDS per use
     T* l_cT = reinterpret_cast<T*>(l_red + PASS_THREADS);
     T* l_dT = l_cT + d;
+    constexpr int FLW = pass_flush_width<VEC, NLMAX>();
+    T* l_fl = reinterpret_cast<T*>(lds + pass_lds_head<T>(d)) + wid * WAVE * FLW;
     for (int k = threadIdx.x; k < d; k += PASS_THREADS) {
         l_cT[k] = (T)l_c[k];
         l_dT[k] = (T)l_dc[k];
     }
     __syncthreads();
-    int base[NLMAX];
+    int col[NLMAX];
     bool own[NLMAX];
 #pragma unroll
     for (int j = 0; j < NLMAX; ++j) {
-        base[j] = (j * G + gl) * VEC;
-        own[j] = (j < nl) && (base[j] < d);
+        const int b = (j * G + gl) * VEC;
+        own[j] = (j < nl) && (b < d);
+        col[j] = own[j] ? b : 0;
     }
 
     // the wave's record doubles as the FP64 accumulator of the flushes
     double* rec = a.rec + gw * rl.len;
     for (int e = lane; e < rl.len; e += WAVE) rec[e] = 0.0;
 
-    T sacc[A_N];
+    T sacc[A_N];  // per-ball scalars, the same in every lane of a group
+    T lacc[2];    // per-lane shares of sum ||w+ - w||^2 and sum ||w||^2
     T tacc[TRL];
     T tam[TRL];  // 1 - eta of this lane's trials
+    bool tok[TRL];
 #pragma unroll
     for (int r = 0; r < TRL; ++r) {
         const int l = r * G + gl;
-        tam[r] = (l < NT) ? T(1) - (T)a.etas[l] : T(1);
+        tok[r] = l < NT;
+        tam[r] = tok[r] ? T(1) - (T)a.etas[l] : T(1);
     }
     T vsv[NLMAX][VEC], vsw[NLMAX][VEC], vkv[NLMAX][VEC];
     T mx_p = 0, mx_d = 0, mx_c = 0;
     auto zero_acc = [&]() {
 #pragma unroll
         for (int k = 0; k < A_N; ++k) sacc[k] = T(0);
+        lacc[0] = lacc[1] = T(0);
 #pragma unroll
         for (int k = 0; k < TRL; ++k) tacc[k] = T(0);
 #pragma unroll
@@ -303,7 +377,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     auto flush = [&]() {
         T sred[A_N];
 #pragma unroll
-        for (int k = 0; k < A_N; ++k) sred[k] = wave_sum_t<T>(sacc[k]);
+        for (int k = 0; k < A_N; ++k) sred[k] = group_sum<T>(leader ? sacc[k] : T(0), WAVE);
+        sred[A_DM] += group_sum<T>(lacc[0], WAVE);
+        sred[A_WW] += group_sum<T>(lacc[1], WAVE);
         if (lane == 0) {
             rec[rl.su] += (double)sred[A_SU];
             rec[rl.z1] += (double)sred[A_Z1];
@@ -324,22 +400,38 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 if (lane < G && l < NT) rec[rl.trial + l] += (double)v;
             }
         }
+        // vector parts: sum over the groups of lanes with equal gl (through
+        // the wave's LDS scratch when a wave holds several groups; program
+        // order within the wave orders the LDS writes before the reads)
+        auto flush_vec = [&](T (&A)[NLMAX][VEC], int off) {
+            if (G < WAVE && FLW > 0) {
 #pragma unroll
-        for (int j = 0; j < NLMAX; ++j) {
-            if (j >= nl) break;
+                for (int j = 0; j < NLMAX; ++j)
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) {
-                const T a1 = cross_group_sum_t<T>(vsv[j][q], G);
-                const T a2 = cross_group_sum_t<T>(vsw[j][q], G);
-                T a3 = T(0);
-                if constexpr (want_kkt) a3 = cross_group_sum_t<T>(vkv[j][q], G);
-                if (lane < G && own[j]) {
-                    rec[rl.sv + base[j] + q] += (double)a1;
-                    rec[rl.sw + base[j] + q] += (double)a2;
-                    if constexpr (want_kkt) rec[rl.kv + base[j] + q] += (double)a3;
+                    for (int q = 0; q < VEC; ++q) l_fl[(j * VEC + q) * WAVE + lane] = A[j][q];
+                if (lane < G) {
+#pragma unroll
+                    for (int j = 0; j < NLMAX; ++j) {
+                        if (!own[j]) continue;
+#pragma unroll
+                        for (int q = 0; q < VEC; ++q) {
+                            T v = T(0);
+                            for (int g = 0; g < bpw; ++g) v += l_fl[(j * VEC + q) * WAVE + g * G + lane];
+                            rec[off + col[j] + q] += (double)v;
+                        }
+                    }
                 }
+            } else {
+#pragma unroll
+                for (int j = 0; j < NLMAX; ++j)
+                    if (own[j])
+#pragma unroll
+                        for (int q = 0; q < VEC; ++q) rec[off + col[j] + q] += (double)A[j][q];
             }
-        }
+        };
+        flush_vec(vsv, rl.sv);
+        flush_vec(vsw, rl.sw);
+        if constexpr (want_kkt) flush_vec(vkv, rl.kv);
         zero_acc();
     };
     zero_acc();
@@ -348,188 +440,189 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     int32_t* mid_idx = a.want_mid ? a.mid_idx + gw * cfg.bw : nullptr;
     double* mid_coef = a.want_mid ? a.mid_coef + gw * cfg.bw : nullptr;
 
-    // loads of one group of balls (one ball per lane group)
-    RowVec<T, VEC> cur[NLMAX], nxt[NLMAX];
-    T r_cur = 0, u_cur = 0, r_nxt = 0, u_nxt = 0;
-    auto load_step = [&](int64_t b0, RowVec<T, VEC> (&buf)[NLMAX], T& rr, T& uu) {
-        const int64_t i = b0 + gi;
-        const bool act = i < wend;
-        rr = (R && act) ? R[i] : T(0);
-        uu = (U && act) ? U[i] : T(0);
+    // rows of the group's ball; past the wave's end, its last ball again
+    auto load = [&](int64_t b0, BallLoad<T, VEC, NLMAX>& L) {
+        int64_t i = b0 + gi;
+        i = i < wend ? i : wend - 1;
+        L.r = R ? R[i] : T(0);
+        L.u = U ? U[i] : T(0);
 #pragma unroll
-        for (int j = 0; j < NLMAX; ++j) {
-            if (act && own[j]) {
-                buf[j] = load_vec<T, VEC>(C + i * d + base[j]);
-            } else {
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) buf[j].v[q] = T(0);
-            }
-        }
+        for (int j = 0; j < NLMAX; ++j) L.c[j] = load_vec<T, VEC>(C + i * d + col[j]);
     };
 
-    const int64_t chunk = (int64_t)bpw * FlushPeriod<T>::steps;
-    for (int64_t c0 = wbeg; c0 < wend; c0 += chunk) {
-        const int64_t c1 = min(wend, c0 + chunk);
-        load_step(c0, cur, r_cur, u_cur);
-        for (int64_t b0 = c0; b0 < c1; b0 += bpw) {
-            if (b0 + bpw < c1) load_step(b0 + bpw, nxt, r_nxt, u_nxt);
-            const int64_t i = b0 + gi;
-            const bool active = i < wend;
-            const T ri = r_cur;
-            const T ui = u_cur;
-            const bool hasv = V && (ui != T(0));
-            T s[NLMAX][VEC], vv[NLMAX][VEC];
-            T nn = 0, q = 0, ee = 0, es = 0;
+    auto process = [&](int64_t b0, BallLoad<T, VEC, NLMAX>& L) {
+        const int64_t i = b0 + gi;
+        const bool active = i < wend;
+        const T ri = L.r;
+        const T ui = active ? L.u : T(0);
+        const bool hasv = V && (ui != T(0));
+        // e = c_i - y (owned elements), vv = v_i where u_i != 0
+        RowVec<T, VEC> vv[NLMAX];
+        T nn = 0, q = 0, ee = 0, es = 0;
+#pragma unroll
+        for (int j = 0; j < NLMAX; ++j) {
+            const RowVec<T, VEC> cy = load_vec<T, VEC>(l_cT + col[j]);
+#pragma unroll
+            for (int qq = 0; qq < VEC; ++qq) {
+                L.c[j].v[qq] = own[j] ? L.c[j].v[qq] - cy.v[qq] : T(0);
+                vv[j].v[qq] = T(0);
+            }
+        }
+        if (hasv) {
+#pragma unroll
+            for (int j = 0; j < NLMAX; ++j)
+                if (own[j]) vv[j] = load_vec<T, VEC>(V + i * d + col[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < NLMAX; ++j) {
+            RowVec<T, VEC> dy;
+            if (KIND != 2 && have_dir) dy = load_vec<T, VEC>(l_dT + col[j]);
+#pragma unroll
+            for (int qq = 0; qq < VEC; ++qq) {
+                const T ek = L.c[j].v[qq];
+                const T sk = ek + vv[j].v[qq] * inv_a;
+                nn += sk * sk;
+                if constexpr (KIND != 2) {
+                    if (have_dir) q += sk * dy.v[qq];
+                }
+                if constexpr (want_kkt) {
+                    ee += ek * ek;
+                    es += ek * sk;
+                }
+            }
+        }
+        nn = group_sum<T>(nn, G);
+        if (KIND != 2 && have_dir) q = group_sum<T>(q, G);
+        if constexpr (want_kkt) {
+            ee = group_sum<T>(ee, G);
+            es = group_sum<T>(es, G);
+        }
+        sacc[A_BYTES] += active ? row_bytes + (hasv ? es_bytes * (T)d : T(0)) : T(0);
+        const T t = ri - r1 + ui * inv_a;
+        BallProj<T> pa = project<T>(t, nn, sig_a);
+        if (!active) pa.cs = 1, pa.up = T(0), pa.gam = T(0), pa.Z = T(0);
+
+        T te = t, nne = nn, ue = ui;
+        BallProj<T> pe = pa;
+        T sig_e = sig_a;
+        T inv_e = inv_a;
+
+        if constexpr (want_kkt) {
+            // updated multipliers w+ = sigma Pi(z) at y and the KKT terms there
+            const T un = pa.up;
+            const bool wrow = Vo && (un != T(0) || a.dense_vout);
+            if (active) {
+                sacc[A_KU] += un;
+                const T tp = r1 - ri;
+                mx_p = fmax(mx_p, cone_dist<T>(tp, tsqrt<T>(ee)));
+                mx_d = fmax(mx_d, cone_dist<T>(un, pa.gam * pa.n));
+                mx_c = fmax(mx_c, fabs(tp * un - pa.gam * es));
+                if (Uo && leader) Uo[i] = un;
+                sacc[A_BYTES] += (Uo ? es_bytes : T(0)) + (wrow ? es_bytes * (T)d : T(0));
+            }
 #pragma unroll
             for (int j = 0; j < NLMAX; ++j) {
-                const bool ok = active && own[j];
-                RowVec<T, VEC> vr, cy, dy;
-#pragma unroll
-                for (int qq = 0; qq < VEC; ++qq) vr.v[qq] = cy.v[qq] = dy.v[qq] = T(0);
-                if (ok && hasv) vr = load_vec<T, VEC>(V + i * d + base[j]);
-                if (own[j]) {
-                    cy = load_vec<T, VEC>(l_cT + base[j]);
-                    if (have_dir) dy = load_vec<T, VEC>(l_dT + base[j]);
-                }
+                RowVec<T, VEC> vn;
 #pragma unroll
                 for (int qq = 0; qq < VEC; ++qq) {
-                    const T ek = ok ? cur[j].v[qq] - cy.v[qq] : T(0);
-                    if constexpr (is_mult) cur[j].v[qq] = ek;  // keep c_i - y for the next subproblem
-                    vv[j][qq] = vr.v[qq];
-                    s[j][qq] = ek + vr.v[qq] * inv_a;
-                    nn += s[j][qq] * s[j][qq];
-                    if constexpr (KIND != 2) {
-                        if (have_dir) q += s[j][qq] * dy.v[qq];
-                    }
-                    if constexpr (want_kkt) {
-                        ee += ek * ek;
-                        es += ek * s[j][qq];
-                    }
+                    vn.v[qq] = pa.gam * (L.c[j].v[qq] + vv[j].v[qq] * inv_a);
+                    vkv[j][qq] += vn.v[qq];
                 }
+                if (active && own[j] && wrow) store_vec<T, VEC>(Vo + i * d + col[j], vn);
+                if constexpr (is_mult) vv[j] = vn;
             }
-            nn = group_sum<T>(nn, G);
-            if (have_dir) q = group_sum<T>(q, G);
-            if constexpr (want_kkt) {
-                ee = group_sum<T>(ee, G);
-                es = group_sum<T>(es, G);
-            }
-            if (leader && active)
-                sacc[A_BYTES] += es_bytes * (T)(d + (R ? 1 : 0) + (U ? 1 : 0) + (hasv ? d : 0));
-            const T t = ri - r1 + ui * inv_a;
-            BallProj<T> pa = project<T>(t, nn, sig_a);
-            if (!active) pa.cs = 1, pa.up = T(0), pa.gam = T(0), pa.Z = T(0);
-
-            T te = t, nne = nn, ue = ui;
-            BallProj<T> pe = pa;
-            T sig_e = sig_a;
-
-            if constexpr (want_kkt) {
-                // updated multipliers w+ = sigma Pi(z) at y and the KKT terms there
-                const T un = pa.up;
-                const bool wrow = Vo && (un != T(0) || a.dense_vout);
-                if (leader && active) {
-                    sacc[A_KU] += un;
-                    const T tp = r1 - ri;
-                    mx_p = fmax(mx_p, cone_dist<T>(tp, tsqrt<T>(ee)));
-                    mx_d = fmax(mx_d, cone_dist<T>(un, pa.gam * pa.n));
-                    mx_c = fmax(mx_c, fabs(tp * un - pa.gam * es));
-                    if (Uo) Uo[i] = un;
-                    sacc[A_BYTES] += (Uo ? es_bytes : T(0)) + (wrow ? es_bytes * (T)d : T(0));
-                }
-#pragma unroll
-                for (int j = 0; j < NLMAX; ++j) {
-                    RowVec<T, VEC> vn;
-#pragma unroll
-                    for (int qq = 0; qq < VEC; ++qq) {
-                        vn.v[qq] = pa.gam * s[j][qq];
-                        vkv[j][qq] += vn.v[qq];
-                    }
-                    if (active && own[j] && wrow) store_vec<T, VEC>(Vo + i * d + base[j], vn);
-                    if constexpr (is_mult) {
-#pragma unroll
-                        for (int qq = 0; qq < VEC; ++qq) vv[j][qq] = vn.v[qq];
-                    }
-                }
-                if constexpr (is_mult) {
-                    // the first evaluation of the next subproblem: w+ and sigma_{k+1}
-                    ue = un;
-                    sig_e = sig_b;
-                    te = ri - r1 + un * inv_b;
-                    T n2 = 0;
-#pragma unroll
-                    for (int j = 0; j < NLMAX; ++j)
-#pragma unroll
-                        for (int qq = 0; qq < VEC; ++qq) {
-                            s[j][qq] = cur[j].v[qq] + vv[j][qq] * inv_b;
-                            n2 += s[j][qq] * s[j][qq];
-                        }
-                    nne = group_sum<T>(n2, G);
-                    pe = project<T>(te, nne, sig_b);
-                    if (!active) pe.cs = 1, pe.up = T(0), pe.gam = T(0), pe.Z = T(0);
-                }
-            }
-
-            // ---- evaluation sums at (y, multipliers in use, sigma_e)
-            if (leader && active) {
-                sacc[A_SU] += pe.up;
-                sacc[A_Z1] += pe.Z;
-                const T du = pe.up - ue;
-                sacc[A_DM] += du * du;
-                sacc[A_WW] += ue * ue;
-                if (pe.cs != 1) sacc[A_RS] += fabs(te) + pe.n;
-                if (pe.cs == 0) sacc[A_NI] += T(1);
-                if (pe.cs == 2) {
-                    sacc[A_NM] += T(1);
-                    sacc[A_SG] += pe.gam;
-                }
-            }
-            // a polar ball with zero multipliers contributes nothing elementwise
-            const bool quiet = (pe.cs == 1) && (ue == T(0));
-            if (!quiet) {
-                const T inv_n = (pe.cs == 2) ? T(1) / pe.n : T(0);
-                T dmb = 0, wwb = 0;
+            if constexpr (is_mult) {
+                // the first evaluation of the next subproblem: w+ and sigma_{k+1}
+                ue = un;
+                sig_e = sig_b;
+                inv_e = inv_b;
+                te = ri - r1 + un * inv_b;
+                T n2 = 0;
 #pragma unroll
                 for (int j = 0; j < NLMAX; ++j)
 #pragma unroll
                     for (int qq = 0; qq < VEC; ++qq) {
-                        const T vp = pe.gam * s[j][qq];
-                        const T dvk = vp - vv[j][qq];
-                        vsv[j][qq] += vp;
-                        vsw[j][qq] += s[j][qq] * inv_n;
-                        dmb += dvk * dvk;
-                        wwb += vv[j][qq] * vv[j][qq];
+                        const T sk = L.c[j].v[qq] + vv[j].v[qq] * inv_b;
+                        n2 += sk * sk;
                     }
-                sacc[A_DM] += dmb;
-                sacc[A_WW] += wwb;
+                nne = group_sum<T>(n2, G);
+                pe = project<T>(te, nne, sig_b);
+                if (!active) pe.cs = 1, pe.up = T(0), pe.gam = T(0), pe.Z = T(0);
             }
-            // Armijo trials along x_base + eta dir: lane gl takes trials gl, gl + G, ...
-            if (have_dir && active) {
+        }
+
+        // ---- evaluation sums at (y, multipliers in use, sigma_e)
+        {
+            sacc[A_SU] += pe.up;
+            sacc[A_Z1] += pe.Z;
+            const T du = pe.up - ue;
+            sacc[A_DM] += du * du;
+            sacc[A_WW] += ue * ue;
+            sacc[A_RS] += (pe.cs != 1) ? fabs(te) + pe.n : T(0);
+            sacc[A_NI] += (pe.cs == 0) ? T(1) : T(0);
+            sacc[A_NM] += (pe.cs == 2) ? T(1) : T(0);
+            sacc[A_SG] += (pe.cs == 2) ? pe.gam : T(0);
+        }
+        // a polar ball with zero multipliers contributes nothing elementwise
+        const bool quiet = (pe.cs == 1) && (ue == T(0));
+        if (!quiet) {
+            const T inv_n = (pe.cs == 2) ? T(1) / pe.n : T(0);
+            T dmb = 0, wwb = 0;
 #pragma unroll
-                for (int r = 0; r < TRL; ++r) {
-                    const T am = tam[r];
-                    const T tl = te + am * dirr;
-                    T n2 = nne + T(2) * am * q + am * am * dc2;
-                    n2 = n2 > T(0) ? n2 : T(0);
-                    if (r * G + gl < NT) tacc[r] += project<T>(tl, n2, sig_e).Z;
-                }
-            }
-            // mid list of the rank-one Hessian part: coef_i = -sigma t_i / (2 n_i^3)
-            if (a.want_mid) {
-                const bool is_mid = active && pe.cs == 2;
-                const unsigned long long bal = __ballot(is_mid && leader);
-                if (is_mid && leader) {
-                    const unsigned long long lower = bal & ((1ull << lane) - 1ull);
-                    const int pos = mid_count + __popcll(lower);
-                    mid_idx[pos] = (int32_t)i;
-                    const double nd = (double)pe.n;
-                    mid_coef[pos] = -(double)sig_e * (double)te / (2.0 * nd * nd * nd);
-                }
-                mid_count += __popcll(bal);
-            }
+            for (int j = 0; j < NLMAX; ++j)
 #pragma unroll
-            for (int j = 0; j < NLMAX; ++j) cur[j] = nxt[j];
-            r_cur = r_nxt;
-            u_cur = u_nxt;
+                for (int qq = 0; qq < VEC; ++qq) {
+                    const T sk = L.c[j].v[qq] + vv[j].v[qq] * inv_e;
+                    const T vp = pe.gam * sk;
+                    const T dvk = vp - vv[j].v[qq];
+                    vsv[j][qq] += vp;
+                    vsw[j][qq] += sk * inv_n;
+                    dmb += dvk * dvk;
+                    wwb += vv[j].v[qq] * vv[j].v[qq];
+                }
+            // per-lane shares of the elementwise parts (summed over all lanes)
+            lacc[0] += dmb;
+            lacc[1] += wwb;
+        }
+        // Armijo trials along x_base + eta dir: lane gl takes trials gl, gl + G, ...
+        if (KIND != 2 && have_dir) {
+#pragma unroll
+            for (int r = 0; r < TRL; ++r) {
+                const T am = tam[r];
+                const T tl = te + am * dirr;
+                T n2 = nne + T(2) * am * q + am * am * dc2;
+                n2 = n2 > T(0) ? n2 : T(0);
+                const T z = project<T>(tl, n2, sig_e).Z;
+                tacc[r] += (active && tok[r]) ? z : T(0);
+            }
+        }
+        // mid list of the rank-one Hessian part: coef_i = -sigma t_i / (2 n_i^3)
+        if (a.want_mid) {
+            const bool is_mid = active && pe.cs == 2;
+            const unsigned long long bal = __ballot(is_mid && leader);
+            if (is_mid && leader) {
+                const unsigned long long lower = bal & ((1ull << lane) - 1ull);
+                const int pos = mid_count + __popcll(lower);
+                mid_idx[pos] = (int32_t)i;
+                const double nd = (double)pe.n;
+                mid_coef[pos] = -(double)sig_e * (double)te / (2.0 * nd * nd * nd);
+            }
+            mid_count += __popcll(bal);
+        }
+    };
+
+    BallLoad<T, VEC, NLMAX> LA, LB;
+    const int64_t chunk = (int64_t)bpw * FlushPeriod<T>::steps;
+    for (int64_t c0 = wbeg; c0 < wend; c0 += chunk) {
+        const int64_t c1 = min(wend, c0 + chunk);
+        load(c0, LA);
+        for (int64_t b0 = c0; b0 < c1; b0 += 2 * bpw) {
+            const bool more = b0 + bpw < c1;
+            if (more) load(b0 + bpw, LB);
+            process(b0, LA);
+            if (!more) break;
+            if (b0 + 2 * bpw < c1) load(b0 + 2 * bpw, LA);
+            process(b0 + bpw, LB);
         }
         flush();
     }
@@ -561,20 +654,26 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
 // when want_kkt is set).
 template <typename T, int VEC, int NLMAX, int TRL>
 __device__ __forceinline__ void pass_dispatch(const PassArgs& a, const PassConfig& cfg, int blk) {
-    const int mode = a.force_mode >= 0 ? a.force_mode : (int)a.state[S_MODE];
-    if (mode == PM_EVAL) {
-        if (a.want_kkt)
-            pass_body<T, VEC, NLMAX, 1, TRL>(a, cfg, blk);
-        else
-            pass_body<T, VEC, NLMAX, 0, TRL>(a, cfg, blk);
-    } else if (mode == PM_MULT) {
+    const int mode = (int)a.state[S_MODE];
+    if (mode == PM_EVAL)
+        pass_body<T, VEC, NLMAX, 0, TRL>(a, cfg, blk);
+    else if (mode == PM_MULT)
         pass_body<T, VEC, NLMAX, 2, TRL>(a, cfg, blk);
-    }
 }
 
 template <typename T, int VEC, int NLMAX, int TRL>
 __global__ __launch_bounds__(PASS_THREADS) void pass_kernel(PassArgs a, PassConfig cfg) {
     pass_dispatch<T, VEC, NLMAX, TRL>(a, cfg, blockIdx.x);
+}
+
+// A single evaluation (meb_al_eval), independent of the state's mode; with
+// want_kkt also the updated multipliers and the KKT terms.
+template <typename T, int VEC, int NLMAX, int TRL>
+__global__ __launch_bounds__(PASS_THREADS) void pass_eval_kernel(PassArgs a, PassConfig cfg) {
+    if (a.want_kkt)
+        pass_body<T, VEC, NLMAX, 1, TRL>(a, cfg, blockIdx.x);
+    else
+        pass_body<T, VEC, NLMAX, 0, TRL>(a, cfg, blockIdx.x);
 }
 
 // Several instances in one launch (a tick of the multi-instance server): the
@@ -606,10 +705,6 @@ static hipError_t ensure_dynamic_lds(const void* fn, size_t bytes) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename T>
-static size_t pass_lds_bytes(int d) {
-    return sizeof(double) * (2 * (size_t)d + PASS_THREADS) + sizeof(T) * (2 * (size_t)d + 4);
-}
 
 // The template instance of the pass for (dtype, config): visits
 // f.go<T, VEC, NLMAX, TRL>().  Valid (vec, nlmax) pairs: G < 64 implies

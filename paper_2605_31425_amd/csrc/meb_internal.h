@@ -241,6 +241,8 @@ hipError_t launch_mid_compact(const int32_t* mid_cnt, int nwaves, int64_t bw, co
 // force_mode = PM_EVAL gives a single evaluation (want_kkt adds the updated
 // multipliers and the KKT terms).
 hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, hipStream_t s);
+// the single evaluation (force_mode >= 0), called by launch_pass
+hipError_t launch_pass_eval(const PassArgs& a, const PassConfig& cfg, hipStream_t s);
 // Sums (maxima for the KKT maxima) of nrec records of len doubles, `stride`
 // doubles apart; the pass leaves one record per block at stride
 // waves_per_block * len.

@@ -394,7 +394,7 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
     return y;
 }
 
-__device__ int chol_solve_lds(int n, int ld, double* M, double* b, double* rd) {
+__device__ __forceinline__ int chol_solve_lds(int n, int ld, double* M, double* b, double* rd) {
     __shared__ int bad;
     const int tid = threadIdx.x, nth = blockDim.x;
     if (tid == 0) bad = 0;
@@ -547,7 +547,7 @@ __host__ __device__ inline int chol_ld(int n) { return n | 1; }
 
 // Solve with n above the register budget of the wave-level solves: the
 // triangular solves by the whole block, column oriented.
-__device__ int chol_solve_block_large(int n, double* M, double* b, double* vec) {
+__device__ __forceinline__ int chol_solve_block_large(int n, double* M, double* b, double* vec) {
     __shared__ int bad;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int tx = tid & 31, ty = tid >> 5, nty = nth >> 5;
@@ -633,7 +633,7 @@ hipError_t launch_chol_solve(int n, double* A, double* b, int* info, hipStream_t
 // solver).  Writes S_MODE = PM_DONE when the run ends.
 // ---------------------------------------------------------------------------
 
-__device__ double block_sum(double v, double* scratch) {
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
     __syncthreads();
     scratch[threadIdx.x] = v;
     __syncthreads();

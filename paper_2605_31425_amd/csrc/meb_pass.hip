@@ -41,7 +41,7 @@ struct SingleLaunch {
     hipStream_t s;
     template <typename T, int VEC, int NLMAX, int TRL>
     hipError_t go() {
-        const size_t lds = pass_lds_bytes<T>(a.d);
+        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(a.d);
         const hipError_t ea = ensure_dynamic_lds((const void*)pass_kernel<T, VEC, NLMAX, TRL>, lds);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL((pass_kernel<T, VEC, NLMAX, TRL>), dim3(cfg.blocks), dim3(PASS_THREADS), lds, s, a, cfg);
@@ -60,6 +60,7 @@ struct VariantId {
 };
 
 hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
+    if (a.force_mode >= 0) return launch_pass_eval(a, cfg, s);
     SingleLaunch f{a, cfg, s};
     return visit_pass(a.dtype, cfg, f);
 }

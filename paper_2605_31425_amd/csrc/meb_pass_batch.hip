@@ -12,7 +12,7 @@ struct BatchPassLaunch {
     hipStream_t s;
     template <typename T, int VEC, int NLMAX, int TRL>
     hipError_t go() {
-        const size_t lds = pass_lds_bytes<T>(max_d);
+        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(max_d);
         const hipError_t ea = ensure_dynamic_lds((const void*)pass_batch_kernel<T, VEC, NLMAX, TRL>, lds);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL((pass_batch_kernel<T, VEC, NLMAX, TRL>), dim3(blocks), dim3(PASS_THREADS), lds, s, tab, L);
