@@ -89,10 +89,13 @@ PassArgs Engine::args(const void* C, const void* R, void* U, void* V) const {
     a.mid_idx = mid_idx;
     a.mid_coef = mid_coef;
     a.mid_cnt = mid_cnt;
+    a.act_idx = act_idx;
+    a.act_coef = act_coef;
+    a.red = red;
+    a.sync = sync;
     a.force_mode = -1;
     a.want_kkt = 0;
     a.want_mid = 1;
-    a.dense_vout = 0;
     for (int l = 0; l < NT; ++l) a.etas[l] = solver_eta(l);
     return a;
 }
@@ -109,11 +112,14 @@ SyrkArgs Engine::syrk_args(const void* C, const void* U, const void* V) const {
     s.sl = sl;
     s.red = red;
     s.rl = rl;
-    s.list_idx = list_idx;
-    s.list_coef = list_coef;
-    s.list_total = list_total;
+    s.mid_cnt = mid_cnt;
+    s.mid_idx = mid_idx;
+    s.mid_coef = mid_coef;
+    s.nwaves = pc.nwaves;
+    s.bw = pc.bw;
     s.skip_k = skip_k;
     s.out = syrk;
+    s.sync = sync;
     s.ksplit = ksplit;
     s.tile = syrk_tile();
     s.ntile = ntile;
@@ -126,12 +132,7 @@ BatchItem Engine::item(const PassArgs& a, int* flag) const {
     it.pa = a;
     it.pc = pc;
     it.sa = syrk_args(a.C, a.Uout ? a.Uout : a.U, a.Vout ? a.Vout : a.V);
-    it.red = red;
-    it.list_offs = list_offs;
     it.flag = flag;
-    it.ksplit = ksplit;
-    it.ntile = ntile;
-    it.use_syrk = use_syrk ? 1 : 0;
     return it;
 }
 
@@ -139,14 +140,13 @@ int Engine::step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0,
     if (ev0) HIPCHK(hipEventRecord(ev0, s));
     HIPCHK(launch_pass(a, pc, s));
     if (ev1) HIPCHK(hipEventRecord(ev1, s));
-    HIPCHK(launch_reduce_records(rec, pc.blocks, rl.len, (int64_t)pc.waves_per_block * rl.len, red, s));
-    if (use_syrk && a.want_mid) {
-        HIPCHK(launch_mid_compact(mid_cnt, pc.nwaves, pc.bw, mid_idx, mid_coef, list_offs, list_total, list_idx,
-                                  list_coef, state, s));
-        HIPCHK(launch_syrk(syrk_args(a.C, a.Uout ? a.Uout : a.U, a.Vout ? a.Vout : a.V), s));
-    }
-    if (control) HIPCHK(launch_assemble(state, sl, rl, red, syrk, ksplit, ntile, use_syrk ? 1 : 0, s));
+    if (a.want_mid) HIPCHK(launch_syrk(syrk_args(a.C, a.Uout ? a.Uout : a.U, a.Vout ? a.Vout : a.V), s));
     if (control) HIPCHK(launch_control(state, sl, rl, red, nullptr, s));
+    return MEB_OK;
+}
+
+int Engine::reset_sync(hipStream_t s) {
+    HIPCHK(launch_fill_bytes_zero(sync, sizeof(int) * SYNC_LEN, s));
     return MEB_OK;
 }
 
@@ -381,6 +381,7 @@ int Job::begin_run(int id, Engine& eng, const void* Cr, const void* Rr, void* U,
     }
     // H is assembled before any Newton step reads it
     HIPCHK(hipMemcpyAsync(eng.state, h, sizeof(double) * sl.H, hipMemcpyHostToDevice, s));
+    CHK(eng.reset_sync(s));
     pa = eng.args(Cr, Rr, U, V);
     e = &eng;
     run_id = id;
@@ -805,26 +806,22 @@ int meb_al_eval(const void* C, const void* R, const void* U, const void* V, int6
     a.want_kkt = (want & (MEB_WANT_KKT | MEB_WANT_MULT)) ? 1 : 0;
     a.Uout = (want & MEB_WANT_MULT) ? U_new : nullptr;
     a.Vout = (want & MEB_WANT_MULT) ? V_new : nullptr;
-    a.dense_vout = 1;
     a.want_mid = (want & MEB_WANT_HESS) ? 1 : 0;
     for (int l = 0; l < NT; ++l) a.etas[l] = (l < n_eta) ? etas[l] : 0.0;
+    // the pass writes the V rows of non-zero updated multipliers only
+    if (want & MEB_WANT_MULT) HIPCHK(launch_fill_bytes_zero(V_new, dtype_size(dtype) * (size_t)m * d, s));
+    CHK(e.reset_sync(s));
     HIPCHK(launch_pass(a, e.pc, s));
-    HIPCHK(launch_reduce_records(e.rec, e.pc.blocks, e.rl.len, (int64_t)e.pc.waves_per_block * e.rl.len, e.red, s));
     if (want & MEB_WANT_HESS) {
-        HIPCHK(launch_mid_compact(e.mid_cnt, e.pc.nwaves, e.pc.bw, e.mid_idx, e.mid_coef, e.list_offs, e.list_total,
-                                  e.list_idx, e.list_coef, e.state, s));
+        // the contraction assembles H into the state
         SyrkArgs sa = e.syrk_args(C, U, V);
         sa.skip_k = INFINITY;
         HIPCHK(launch_syrk(sa, s));
     }
-    // g and H into the tail of the state buffer (free in this call)
     double* gdev = e.state + e.sl.gb;
     double* Hdev = e.state + e.sl.H;
-    if (want & (MEB_WANT_GRAD | MEB_WANT_HESS))
-        HIPCHK(launch_eval_assemble(e.state, e.sl, e.rl, e.red, e.syrk, e.ksplit, syrk_tile(), e.ntile,
-                                    (want & MEB_WANT_HESS) ? 1 : 0, sigma, tau, ybuf, ybuf + n1,
-                                    (want & MEB_WANT_GRAD) ? gdev : nullptr, (want & MEB_WANT_HESS) ? Hdev : nullptr,
-                                    s));
+    if (want & MEB_WANT_GRAD)
+        HIPCHK(launch_eval_outputs(e.state, e.sl, e.rl, e.red, sigma, tau, ybuf, ybuf + n1, gdev, nullptr, s));
     std::vector<double> rh(e.rl.len);
     HIPCHK(hipMemcpyAsync(rh.data(), e.red, sizeof(double) * e.rl.len, hipMemcpyDeviceToHost, s));
     if ((want & MEB_WANT_GRAD) && g) HIPCHK(hipMemcpyAsync(g, gdev, sizeof(double) * n1, hipMemcpyDeviceToHost, s));

@@ -243,6 +243,74 @@ __host__ __device__ inline size_t pass_lds_bytes(int d) {
     return sizeof(double) * pass_lds_head<T>(d) + sizeof(T) * (size_t)WPB * WAVE * pass_flush_width<VEC, NLMAX>();
 }
 
+// Loads and stores of data that other blocks (possibly on other XCDs, with
+// their own L2) read within the same kernel: agent-scope relaxed atomics,
+// i.e. write-through stores and coherent loads, so no cache flush or
+// invalidation is needed.  A block publishes its data before it counts its
+// arrival: the barrier waits for its stores to complete.
+__device__ __forceinline__ void st_shared_dev(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_shared_dev(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int arrive(int* counter) {
+    return __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum (maximum for the three KKT maxima) of n consecutive records of len
+// doubles, `stride` apart, in index order, into out (written with coherent
+// stores when `shared_out`).  Loads are issued in batches of eight before
+// they are combined.
+__device__ __forceinline__ void sum_records(const double* src, int n, int len, int64_t stride, int kmax,
+                                            double* out, bool shared_out) {
+    for (int e = threadIdx.x; e < len; e += blockDim.x) {
+        const bool ismax = e >= kmax && e < kmax + 3;
+        double v = ld_shared_dev(src + e);
+        for (int k0 = 1; k0 < n; k0 += 8) {
+            double x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = (k0 + q < n) ? ld_shared_dev(src + (int64_t)(k0 + q) * stride + e) : 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (k0 + q < n) v = ismax ? fmax(v, x[q]) : v + x[q];
+        }
+        if (shared_out)
+            st_shared_dev(out + e, v);
+        else
+            out[e] = v;
+    }
+}
+
+// In-kernel reduction of the nrec block records (each published with
+// coherent stores): the last block of each group of RED_GROUP blocks to
+// arrive sums its group, then the last group sums the groups, always in
+// index order, so the result does not depend on which block arrives last.
+// Arrival counters are reset by the block that consumes them.
+__device__ __forceinline__ void reduce_block_records(const double* rec, int nrec, const RecLayout& rl,
+                                                     int64_t stride, double* red, int* sync, int blk) {
+    __shared__ int s_last;
+    const int len = rl.len;
+    const int ng = (nrec + RED_GROUP - 1) / RED_GROUP;
+    const int g = blk / RED_GROUP;
+    const int gb = g * RED_GROUP, gn = min(RED_GROUP, nrec - gb);
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = arrive(&sync[g]) == gn - 1;
+    __syncthreads();
+    if (!s_last) return;
+    double* gp = (ng == 1) ? red : red + (size_t)(1 + g) * len;
+    sum_records(rec + (int64_t)gb * stride, gn, len, stride, rl.kmax, gp, ng > 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sync[g] = 0;
+        s_last = (ng > 1) ? (arrive(&sync[SYNC_TOP]) == ng - 1) : 0;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    sum_records(red + len, ng, len, len, rl.kmax, red, false);
+    if (threadIdx.x == 0) sync[SYNC_TOP] = 0;
+}
+
 // Loads of one ball by one lane: its share of the row, the radius and u.
 template <typename T, int VEC, int NLMAX>
 struct BallLoad {
@@ -260,12 +328,23 @@ struct BallLoad {
 //         the next outer iteration at sigma_{k+1}.
 // TRL: Armijo trials per lane (ceil(NT / G) rounded up to 1, 3 or 9).
 //
+// Phase 1 streams the wave's balls.  With e = c_i - y and v = v_i (zero
+// unless u_i != 0), everything a ball contributes to the scalar sums follows
+// from five dot products, ||e||^2, <e, v>, ||v||^2, <e, dir>, <v, dir>
+// (s = e + v / sigma, so ||s||^2 and <s, dir> are their combinations), so
+// phase 1 keeps no per-element state beyond the row being read.  Balls whose
+// vector parts are non-zero -- not polar at the evaluation point, or with an
+// updated multiplier -- are appended to the wave's active list with the
+// coefficients (a, b) of each part a e + b v.  Phase 2 reads those rows again
+// (few, except in the first passes of a run) and accumulates the vector sums
+// and writes the updated V rows.
+//
 // Every lane of a ball's group computes the ball's scalars redundantly (the
 // group sums leave the same value in all of them); the group leader's copy
 // is the one that reaches the record.  Lanes that own no part of a load read
-// a valid address of the same row and discard it, so the loop has no
-// per-element branches.  Loads are software-pipelined two groups deep: the
-// loop body is unrolled twice over two load buffers.
+// a valid address of the same row and discard it.  Phase-1 loads are
+// software-pipelined two groups deep (the loop body is unrolled over two
+// load buffers).
 template <typename T, int VEC, int NLMAX, int KIND, int TRL>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& cfg, int blk) {
     extern __shared__ double lds[];
@@ -316,7 +395,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     T* Vo = static_cast<T*>(a.Vout);
 
     const int lane = lane_id();
-    const int wid = threadIdx.x / WAVE;
+    // wave-uniform: keeps the wave's offsets and pointers in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int64_t gw = (int64_t)blk * WPB + wid;
     const int gi = lane / G;
     const int gl = lane % G;
@@ -350,8 +430,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     double* rec = a.rec + gw * rl.len;
     for (int e = lane; e < rl.len; e += WAVE) rec[e] = 0.0;
 
+    // ------------------------------------------------------------------
+    // phase 1
+    // ------------------------------------------------------------------
     T sacc[A_N];  // per-ball scalars, the same in every lane of a group
-    T lacc[2];    // per-lane shares of sum ||w+ - w||^2 and sum ||w||^2
     T tacc[TRL];
     T tam[TRL];  // 1 - eta of this lane's trials
     bool tok[TRL];
@@ -361,25 +443,17 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
         tok[r] = l < NT;
         tam[r] = tok[r] ? T(1) - (T)a.etas[l] : T(1);
     }
-    T vsv[NLMAX][VEC], vsw[NLMAX][VEC], vkv[NLMAX][VEC];
     T mx_p = 0, mx_d = 0, mx_c = 0;
-    auto zero_acc = [&]() {
+    auto zero_scalars = [&]() {
 #pragma unroll
         for (int k = 0; k < A_N; ++k) sacc[k] = T(0);
-        lacc[0] = lacc[1] = T(0);
 #pragma unroll
         for (int k = 0; k < TRL; ++k) tacc[k] = T(0);
-#pragma unroll
-        for (int j = 0; j < NLMAX; ++j)
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) vsv[j][q] = vsw[j][q] = vkv[j][q] = T(0);
     };
-    auto flush = [&]() {
+    auto flush_scalars = [&]() {
         T sred[A_N];
 #pragma unroll
         for (int k = 0; k < A_N; ++k) sred[k] = group_sum<T>(leader ? sacc[k] : T(0), WAVE);
-        sred[A_DM] += group_sum<T>(lacc[0], WAVE);
-        sred[A_WW] += group_sum<T>(lacc[1], WAVE);
         if (lane == 0) {
             rec[rl.su] += (double)sred[A_SU];
             rec[rl.z1] += (double)sred[A_Z1];
@@ -400,9 +474,218 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 if (lane < G && l < NT) rec[rl.trial + l] += (double)v;
             }
         }
-        // vector parts: sum over the groups of lanes with equal gl (through
-        // the wave's LDS scratch when a wave holds several groups; program
-        // order within the wave orders the LDS writes before the reads)
+        zero_scalars();
+    };
+    zero_scalars();
+
+    int32_t mid_count = 0, act_count = 0;
+    int32_t* mid_idx = a.want_mid ? a.mid_idx + gw * cfg.bw : nullptr;
+    double* mid_coef = a.want_mid ? a.mid_coef + gw * cfg.bw : nullptr;
+    int32_t* act_idx = a.act_idx + gw * cfg.bw;
+    T* act_coef = static_cast<T*>(a.act_coef) + gw * cfg.bw * ACT_NC;
+
+    // rows of the group's ball; past the wave's end, its last ball again
+    auto load = [&](int64_t b0, BallLoad<T, VEC, NLMAX>& L) {
+        int64_t i = b0 + gi;
+        i = i < wend ? i : wend - 1;
+        L.r = R ? R[i] : T(0);
+        L.u = U ? U[i] : T(0);
+#pragma unroll
+        for (int j = 0; j < NLMAX; ++j) L.c[j] = load_vec<T, VEC>(C + i * d + col[j]);
+    };
+
+    auto process = [&](int64_t b0, BallLoad<T, VEC, NLMAX>& L) {
+        const int64_t i = b0 + gi;
+        const bool active = i < wend;
+        const T ri = L.r;
+        const T ui = active ? L.u : T(0);
+        const bool hasv = V && (ui != T(0));
+        // dot products of e = c_i - y and v with each other and with dir
+        T ee = 0, ed = 0, ev = 0, vv = 0, vd = 0;
+#pragma unroll
+        for (int j = 0; j < NLMAX; ++j) {
+            const RowVec<T, VEC> cy = load_vec<T, VEC>(l_cT + col[j]);
+            RowVec<T, VEC> dy{};
+            if (KIND != 2 && have_dir) dy = load_vec<T, VEC>(l_dT + col[j]);
+#pragma unroll
+            for (int qq = 0; qq < VEC; ++qq) {
+                const T ek = own[j] ? L.c[j].v[qq] - cy.v[qq] : T(0);
+                ee += ek * ek;
+                if (KIND != 2 && have_dir) ed += ek * dy.v[qq];
+                L.c[j].v[qq] = ek;
+            }
+        }
+        if (hasv) {
+#pragma unroll
+            for (int j = 0; j < NLMAX; ++j) {
+                const RowVec<T, VEC> vr = load_vec<T, VEC>(V + i * d + col[j]);
+                RowVec<T, VEC> dy{};
+                if (KIND != 2 && have_dir) dy = load_vec<T, VEC>(l_dT + col[j]);
+#pragma unroll
+                for (int qq = 0; qq < VEC; ++qq) {
+                    const T vk = own[j] ? vr.v[qq] : T(0);
+                    ev += L.c[j].v[qq] * vk;
+                    vv += vk * vk;
+                    if (KIND != 2 && have_dir) vd += vk * dy.v[qq];
+                }
+            }
+        }
+        ee = group_sum<T>(ee, G);
+        if (KIND != 2 && have_dir) ed = group_sum<T>(ed, G);
+        if (__any(hasv)) {
+            ev = group_sum<T>(ev, G);
+            vv = group_sum<T>(vv, G);
+            if (KIND != 2 && have_dir) vd = group_sum<T>(vd, G);
+        }
+        sacc[A_BYTES] += active ? row_bytes + (hasv ? es_bytes * (T)d : T(0)) : T(0);
+
+        // the ball at (y, w, sigma_a): s = e + v / sigma_a
+        const T t = ri - r1 + ui * inv_a;
+        const T nn = ee + inv_a * (T(2) * ev + inv_a * vv);
+        BallProj<T> pa = project<T>(t, nn, sig_a);
+        if (!active) pa.cs = 1, pa.up = T(0), pa.gam = T(0), pa.Z = T(0);
+
+        // evaluation point of the sums: s_e = ca e + cb v, multipliers in use
+        // (ue, wa e + wb v)
+        T te = t, nne = nn, ue = ui, sig_e = sig_a;
+        T ca = T(1), cb = inv_a, wa = T(0), wb = T(1), wwv = vv;
+        BallProj<T> pe = pa;
+        T un = T(0), ga = T(0);
+        if constexpr (want_kkt) {
+            // updated multipliers w+ = sigma Pi(z) = (up, gam s) and the KKT terms
+            un = pa.up;
+            ga = pa.gam;
+            if (active) {
+                sacc[A_KU] += un;
+                const T tp = r1 - ri;
+                const T es = ee + inv_a * ev;
+                mx_p = fmax(mx_p, cone_dist<T>(tp, tsqrt<T>(ee)));
+                mx_d = fmax(mx_d, cone_dist<T>(un, pa.gam * pa.n));
+                mx_c = fmax(mx_c, fabs(tp * un - pa.gam * es));
+                if (Uo && leader) Uo[i] = un;
+                sacc[A_BYTES] += (Uo ? es_bytes : T(0)) + ((Vo && un != T(0)) ? es_bytes * (T)d : T(0));
+            }
+            if constexpr (is_mult) {
+                // the first evaluation of the next subproblem: w+ and sigma_{k+1};
+                // s' = e + gam s / sigma_b = (1 + gam / sigma_b) e + gam / (sigma_a sigma_b) v
+                ca = T(1) + ga * inv_b;
+                cb = ga * inv_a * inv_b;
+                wa = ga;
+                wb = ga * inv_a;
+                wwv = ga * ga * nn;
+                ue = un;
+                sig_e = sig_b;
+                te = ri - r1 + un * inv_b;
+                nne = ca * ca * ee + cb * (T(2) * ca * ev + cb * vv);
+                pe = project<T>(te, nne, sig_b);
+                if (!active) pe.cs = 1, pe.up = T(0), pe.gam = T(0), pe.Z = T(0);
+            }
+        }
+
+        // ---- evaluation sums at (y, multipliers in use, sigma_e)
+        {
+            sacc[A_SU] += pe.up;
+            sacc[A_Z1] += pe.Z;
+            const T du = pe.up - ue;
+            // ||gam_e s_e - w_v||^2 with gam_e s_e - w_v = A e + B v
+            const T Ac = pe.gam * ca - wa, Bc = pe.gam * cb - wb;
+            const T dv2 = Ac * Ac * ee + Bc * (T(2) * Ac * ev + Bc * vv);
+            sacc[A_DM] += du * du + (active ? dv2 : T(0));
+            sacc[A_WW] += ue * ue + (active ? wwv : T(0));
+            sacc[A_RS] += (pe.cs != 1) ? fabs(te) + pe.n : T(0);
+            sacc[A_NI] += (pe.cs == 0) ? T(1) : T(0);
+            sacc[A_NM] += (pe.cs == 2) ? T(1) : T(0);
+            sacc[A_SG] += (pe.cs == 2) ? pe.gam : T(0);
+        }
+        // Armijo trials along x_base + eta dir: lane gl takes trials gl, gl + G, ...
+        if (KIND != 2 && have_dir) {
+            const T q = ed + inv_a * vd;  // <s, dir>
+#pragma unroll
+            for (int r = 0; r < TRL; ++r) {
+                const T am = tam[r];
+                const T tl = te + am * dirr;
+                T n2 = nne + T(2) * am * q + am * am * dc2;
+                n2 = n2 > T(0) ? n2 : T(0);
+                const T z = project<T>(tl, n2, sig_e).Z;
+                tacc[r] += (active && tok[r]) ? z : T(0);
+            }
+        }
+        // mid list of the rank-one Hessian part: coef_i = -sigma t_i / (2 n_i^3)
+        if (a.want_mid) {
+            const bool is_mid = active && pe.cs == 2;
+            const unsigned long long bal = __ballot(is_mid && leader);
+            if (is_mid && leader) {
+                const unsigned long long lower = bal & ((1ull << lane) - 1ull);
+                const int pos = mid_count + __popcll(lower);
+                mid_idx[pos] = (int32_t)i;
+                const double nd = (double)pe.n;
+                mid_coef[pos] = -(double)sig_e * (double)te / (2.0 * nd * nd * nd);
+            }
+            mid_count += __popcll(bal);
+        }
+        // active list: balls with non-zero vector parts
+        {
+            const bool wrt = want_kkt && Vo && un != T(0);
+            const bool is_act = active && (pe.cs != 1 || (want_kkt && un != T(0)));
+            const unsigned long long bal = __ballot(is_act && leader);
+            if (is_act && leader) {
+                const unsigned long long lower = bal & ((1ull << lane) - 1ull);
+                const int pos = act_count + __popcll(lower);
+                act_idx[pos] = (int32_t)i;
+                T* cf = act_coef + (size_t)pos * ACT_NC;
+                const T inv_n = (pe.cs == 2) ? T(1) / pe.n : T(0);
+                cf[0] = pe.gam * ca;
+                cf[1] = pe.gam * cb;
+                cf[2] = inv_n * ca;
+                cf[3] = inv_n * cb;
+                cf[4] = ga;
+                cf[5] = ga * inv_a;
+                cf[6] = (T)((hasv ? 1 : 0) | (wrt ? 2 : 0));
+            }
+            act_count += __popcll(bal);
+        }
+    };
+
+    BallLoad<T, VEC, NLMAX> LA, LB;
+    const int64_t chunk = (int64_t)bpw * FlushPeriod<T>::steps;
+    for (int64_t c0 = wbeg; c0 < wend; c0 += chunk) {
+        const int64_t c1 = min(wend, c0 + chunk);
+        load(c0, LA);
+        for (int64_t b0 = c0; b0 < c1; b0 += 2 * bpw) {
+            const bool more = b0 + bpw < c1;
+            if (more) load(b0 + bpw, LB);
+            process(b0, LA);
+            if (!more) break;
+            if (b0 + 2 * bpw < c1) load(b0 + 2 * bpw, LA);
+            process(b0 + bpw, LB);
+        }
+        flush_scalars();
+    }
+    {
+        const T mp = wave_max_t<T>(mx_p), md = wave_max_t<T>(mx_d), mc = wave_max_t<T>(mx_c);
+        if (lane == 0) {
+            rec[rl.kmax + 0] = (double)mp;
+            rec[rl.kmax + 1] = (double)md;
+            rec[rl.kmax + 2] = (double)mc;
+            if (a.mid_cnt) a.mid_cnt[gw] = mid_count;
+        }
+    }
+
+    // ------------------------------------------------------------------
+    // phase 2: vector parts of the active list (written above by this wave)
+    // ------------------------------------------------------------------
+    if (act_count > 0) {
+        __threadfence_block();
+        T vsv[NLMAX][VEC], vsw[NLMAX][VEC], vkv[NLMAX][VEC];
+        auto zero_vec = [&]() {
+#pragma unroll
+            for (int j = 0; j < NLMAX; ++j)
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) vsv[j][q] = vsw[j][q] = vkv[j][q] = T(0);
+        };
+        // sum over the groups of lanes with equal gl (through the wave's LDS
+        // scratch when a wave holds several groups; program order within the
+        // wave orders the LDS writes before the reads)
         auto flush_vec = [&](T (&A)[NLMAX][VEC], int off) {
             if (G < WAVE && FLW > 0) {
 #pragma unroll
@@ -429,210 +712,61 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                         for (int q = 0; q < VEC; ++q) rec[off + col[j] + q] += (double)A[j][q];
             }
         };
-        flush_vec(vsv, rl.sv);
-        flush_vec(vsw, rl.sw);
-        if constexpr (want_kkt) flush_vec(vkv, rl.kv);
-        zero_acc();
-    };
-    zero_acc();
-
-    int32_t mid_count = 0;
-    int32_t* mid_idx = a.want_mid ? a.mid_idx + gw * cfg.bw : nullptr;
-    double* mid_coef = a.want_mid ? a.mid_coef + gw * cfg.bw : nullptr;
-
-    // rows of the group's ball; past the wave's end, its last ball again
-    auto load = [&](int64_t b0, BallLoad<T, VEC, NLMAX>& L) {
-        int64_t i = b0 + gi;
-        i = i < wend ? i : wend - 1;
-        L.r = R ? R[i] : T(0);
-        L.u = U ? U[i] : T(0);
-#pragma unroll
-        for (int j = 0; j < NLMAX; ++j) L.c[j] = load_vec<T, VEC>(C + i * d + col[j]);
-    };
-
-    auto process = [&](int64_t b0, BallLoad<T, VEC, NLMAX>& L) {
-        const int64_t i = b0 + gi;
-        const bool active = i < wend;
-        const T ri = L.r;
-        const T ui = active ? L.u : T(0);
-        const bool hasv = V && (ui != T(0));
-        // e = c_i - y (owned elements), vv = v_i where u_i != 0
-        RowVec<T, VEC> vv[NLMAX];
-        T nn = 0, q = 0, ee = 0, es = 0;
-#pragma unroll
-        for (int j = 0; j < NLMAX; ++j) {
-            const RowVec<T, VEC> cy = load_vec<T, VEC>(l_cT + col[j]);
-#pragma unroll
-            for (int qq = 0; qq < VEC; ++qq) {
-                L.c[j].v[qq] = own[j] ? L.c[j].v[qq] - cy.v[qq] : T(0);
-                vv[j].v[qq] = T(0);
-            }
-        }
-        if (hasv) {
-#pragma unroll
-            for (int j = 0; j < NLMAX; ++j)
-                if (own[j]) vv[j] = load_vec<T, VEC>(V + i * d + col[j]);
-        }
-#pragma unroll
-        for (int j = 0; j < NLMAX; ++j) {
-            RowVec<T, VEC> dy;
-            if (KIND != 2 && have_dir) dy = load_vec<T, VEC>(l_dT + col[j]);
-#pragma unroll
-            for (int qq = 0; qq < VEC; ++qq) {
-                const T ek = L.c[j].v[qq];
-                const T sk = ek + vv[j].v[qq] * inv_a;
-                nn += sk * sk;
-                if constexpr (KIND != 2) {
-                    if (have_dir) q += sk * dy.v[qq];
-                }
-                if constexpr (want_kkt) {
-                    ee += ek * ek;
-                    es += ek * sk;
-                }
-            }
-        }
-        nn = group_sum<T>(nn, G);
-        if (KIND != 2 && have_dir) q = group_sum<T>(q, G);
-        if constexpr (want_kkt) {
-            ee = group_sum<T>(ee, G);
-            es = group_sum<T>(es, G);
-        }
-        sacc[A_BYTES] += active ? row_bytes + (hasv ? es_bytes * (T)d : T(0)) : T(0);
-        const T t = ri - r1 + ui * inv_a;
-        BallProj<T> pa = project<T>(t, nn, sig_a);
-        if (!active) pa.cs = 1, pa.up = T(0), pa.gam = T(0), pa.Z = T(0);
-
-        T te = t, nne = nn, ue = ui;
-        BallProj<T> pe = pa;
-        T sig_e = sig_a;
-        T inv_e = inv_a;
-
-        if constexpr (want_kkt) {
-            // updated multipliers w+ = sigma Pi(z) at y and the KKT terms there
-            const T un = pa.up;
-            const bool wrow = Vo && (un != T(0) || a.dense_vout);
-            if (active) {
-                sacc[A_KU] += un;
-                const T tp = r1 - ri;
-                mx_p = fmax(mx_p, cone_dist<T>(tp, tsqrt<T>(ee)));
-                mx_d = fmax(mx_d, cone_dist<T>(un, pa.gam * pa.n));
-                mx_c = fmax(mx_c, fabs(tp * un - pa.gam * es));
-                if (Uo && leader) Uo[i] = un;
-                sacc[A_BYTES] += (Uo ? es_bytes : T(0)) + (wrow ? es_bytes * (T)d : T(0));
-            }
+        zero_vec();
+        constexpr int FS = FlushPeriod<T>::steps;
+        for (int k0 = 0; k0 < act_count; k0 += bpw) {
+            const int k = k0 + gi;
+            const bool ok = k < act_count;
+            const int kk = ok ? k : act_count - 1;
+            const int64_t i = act_idx[kk];
+            const T* cf = act_coef + (size_t)kk * ACT_NC;
+            const T a1 = cf[0], b1 = cf[1], a2 = cf[2], b2 = cf[3];
+            const int flags = ok ? (int)cf[6] : 0;
+            RowVec<T, VEC> er[NLMAX], vr[NLMAX];
 #pragma unroll
             for (int j = 0; j < NLMAX; ++j) {
-                RowVec<T, VEC> vn;
+                er[j] = load_vec<T, VEC>(C + i * d + col[j]);
+                const RowVec<T, VEC> cy = load_vec<T, VEC>(l_cT + col[j]);
 #pragma unroll
-                for (int qq = 0; qq < VEC; ++qq) {
-                    vn.v[qq] = pa.gam * (L.c[j].v[qq] + vv[j].v[qq] * inv_a);
-                    vkv[j][qq] += vn.v[qq];
+                for (int q = 0; q < VEC; ++q) {
+                    er[j].v[q] = (ok && own[j]) ? er[j].v[q] - cy.v[q] : T(0);
+                    vr[j].v[q] = T(0);
                 }
-                if (active && own[j] && wrow) store_vec<T, VEC>(Vo + i * d + col[j], vn);
-                if constexpr (is_mult) vv[j] = vn;
             }
-            if constexpr (is_mult) {
-                // the first evaluation of the next subproblem: w+ and sigma_{k+1}
-                ue = un;
-                sig_e = sig_b;
-                inv_e = inv_b;
-                te = ri - r1 + un * inv_b;
-                T n2 = 0;
+            if (flags & 1) {
 #pragma unroll
                 for (int j = 0; j < NLMAX; ++j)
-#pragma unroll
-                    for (int qq = 0; qq < VEC; ++qq) {
-                        const T sk = L.c[j].v[qq] + vv[j].v[qq] * inv_b;
-                        n2 += sk * sk;
-                    }
-                nne = group_sum<T>(n2, G);
-                pe = project<T>(te, nne, sig_b);
-                if (!active) pe.cs = 1, pe.up = T(0), pe.gam = T(0), pe.Z = T(0);
+                    if (own[j]) vr[j] = load_vec<T, VEC>(V + i * d + col[j]);
             }
-        }
-
-        // ---- evaluation sums at (y, multipliers in use, sigma_e)
-        {
-            sacc[A_SU] += pe.up;
-            sacc[A_Z1] += pe.Z;
-            const T du = pe.up - ue;
-            sacc[A_DM] += du * du;
-            sacc[A_WW] += ue * ue;
-            sacc[A_RS] += (pe.cs != 1) ? fabs(te) + pe.n : T(0);
-            sacc[A_NI] += (pe.cs == 0) ? T(1) : T(0);
-            sacc[A_NM] += (pe.cs == 2) ? T(1) : T(0);
-            sacc[A_SG] += (pe.cs == 2) ? pe.gam : T(0);
-        }
-        // a polar ball with zero multipliers contributes nothing elementwise
-        const bool quiet = (pe.cs == 1) && (ue == T(0));
-        if (!quiet) {
-            const T inv_n = (pe.cs == 2) ? T(1) / pe.n : T(0);
-            T dmb = 0, wwb = 0;
 #pragma unroll
             for (int j = 0; j < NLMAX; ++j)
 #pragma unroll
-                for (int qq = 0; qq < VEC; ++qq) {
-                    const T sk = L.c[j].v[qq] + vv[j].v[qq] * inv_e;
-                    const T vp = pe.gam * sk;
-                    const T dvk = vp - vv[j].v[qq];
-                    vsv[j][qq] += vp;
-                    vsw[j][qq] += sk * inv_n;
-                    dmb += dvk * dvk;
-                    wwb += vv[j].v[qq] * vv[j].v[qq];
+                for (int q = 0; q < VEC; ++q) {
+                    vsv[j][q] += a1 * er[j].v[q] + b1 * vr[j].v[q];
+                    vsw[j][q] += a2 * er[j].v[q] + b2 * vr[j].v[q];
                 }
-            // per-lane shares of the elementwise parts (summed over all lanes)
-            lacc[0] += dmb;
-            lacc[1] += wwb;
-        }
-        // Armijo trials along x_base + eta dir: lane gl takes trials gl, gl + G, ...
-        if (KIND != 2 && have_dir) {
+            if constexpr (want_kkt) {
+                const T a3 = cf[4], b3 = cf[5];
 #pragma unroll
-            for (int r = 0; r < TRL; ++r) {
-                const T am = tam[r];
-                const T tl = te + am * dirr;
-                T n2 = nne + T(2) * am * q + am * am * dc2;
-                n2 = n2 > T(0) ? n2 : T(0);
-                const T z = project<T>(tl, n2, sig_e).Z;
-                tacc[r] += (active && tok[r]) ? z : T(0);
+                for (int j = 0; j < NLMAX; ++j) {
+                    RowVec<T, VEC> vn;
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) {
+                        vn.v[q] = a3 * er[j].v[q] + b3 * vr[j].v[q];
+                        vkv[j][q] += vn.v[q];
+                    }
+                    if ((flags & 2) && own[j]) store_vec<T, VEC>(Vo + i * d + col[j], vn);
+                }
+            }
+            if ((k0 / bpw + 1) % FS == 0 || k0 + bpw >= act_count) {
+                flush_vec(vsv, rl.sv);
+                flush_vec(vsw, rl.sw);
+                if constexpr (want_kkt) flush_vec(vkv, rl.kv);
+                zero_vec();
             }
         }
-        // mid list of the rank-one Hessian part: coef_i = -sigma t_i / (2 n_i^3)
-        if (a.want_mid) {
-            const bool is_mid = active && pe.cs == 2;
-            const unsigned long long bal = __ballot(is_mid && leader);
-            if (is_mid && leader) {
-                const unsigned long long lower = bal & ((1ull << lane) - 1ull);
-                const int pos = mid_count + __popcll(lower);
-                mid_idx[pos] = (int32_t)i;
-                const double nd = (double)pe.n;
-                mid_coef[pos] = -(double)sig_e * (double)te / (2.0 * nd * nd * nd);
-            }
-            mid_count += __popcll(bal);
-        }
-    };
+    }
 
-    BallLoad<T, VEC, NLMAX> LA, LB;
-    const int64_t chunk = (int64_t)bpw * FlushPeriod<T>::steps;
-    for (int64_t c0 = wbeg; c0 < wend; c0 += chunk) {
-        const int64_t c1 = min(wend, c0 + chunk);
-        load(c0, LA);
-        for (int64_t b0 = c0; b0 < c1; b0 += 2 * bpw) {
-            const bool more = b0 + bpw < c1;
-            if (more) load(b0 + bpw, LB);
-            process(b0, LA);
-            if (!more) break;
-            if (b0 + 2 * bpw < c1) load(b0 + 2 * bpw, LA);
-            process(b0 + bpw, LB);
-        }
-        flush();
-    }
-    const T mp = wave_max_t<T>(mx_p), md = wave_max_t<T>(mx_d), mc = wave_max_t<T>(mx_c);
-    if (lane == 0) {
-        rec[rl.kmax + 0] = (double)mp;
-        rec[rl.kmax + 1] = (double)md;
-        rec[rl.kmax + 2] = (double)mc;
-        if (a.mid_cnt) a.mid_cnt[gw] = mid_count;
-    }
     // combine the block's wave records into the first one, in wave order
     __syncthreads();
     double* r0 = a.rec + (int64_t)blk * WPB * rl.len;
@@ -644,8 +778,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
             const double x = r0[w * rl.len + e];
             v = ismax ? fmax(v, x) : v + x;
         }
-        r0[e] = v;
+        st_shared_dev(r0 + e, v);
     }
+    reduce_block_records(a.rec, cfg.blocks, rl, (int64_t)WPB * rl.len, a.red, a.sync, blk);
 }
 
 // The pass kernel: the solver's evaluation or multiplier update, as the device

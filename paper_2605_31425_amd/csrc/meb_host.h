@@ -86,18 +86,16 @@ struct Engine {
     StateLayout sl{};
     RecLayout rl{};
     int ntile = 0, ksplit = 0;
-    bool use_syrk = true;
     double* state = nullptr;
     double* rec = nullptr;
     double* red = nullptr;
     int32_t* mid_idx = nullptr;
     double* mid_coef = nullptr;
     int32_t* mid_cnt = nullptr;
+    int32_t* act_idx = nullptr;
+    double* act_coef = nullptr;  // ACT_NC per entry, in the working precision
     double* syrk = nullptr;
-    int32_t* list_idx = nullptr;
-    double* list_coef = nullptr;
-    int64_t* list_offs = nullptr;
-    int64_t* list_total = nullptr;
+    int* sync = nullptr;         // SYNC_LEN arrival counters, zero between kernels
     double skip_k = INFINITY;
 
     void setup(int64_t m_, int d_, int dtype_);
@@ -105,25 +103,27 @@ struct Engine {
     void carve(A& a) {
         state = a.template take<double>(sl.len);
         rec = a.template take<double>((size_t)pc.nwaves * rl.len);
-        red = a.template take<double>((size_t)(32 + 1) * rl.len);
+        red = a.template take<double>((size_t)(SYNC_GROUPS + 1) * rl.len);
         const size_t cap = (size_t)pc.nwaves * (size_t)pc.bw;
         mid_idx = a.template take<int32_t>(cap);
         mid_coef = a.template take<double>(cap);
         mid_cnt = a.template take<int32_t>(pc.nwaves);
+        act_idx = a.template take<int32_t>(cap);
+        act_coef = a.template take<double>(cap * ACT_NC);
         const size_t pairs = (size_t)ntile * (ntile + 1) / 2;
         syrk = a.template take<double>((size_t)ksplit * pairs * syrk_tile() * syrk_tile());
-        list_idx = a.template take<int32_t>(cap);
-        list_coef = a.template take<double>(cap);
-        list_offs = a.template take<int64_t>(pc.nwaves);
-        list_total = a.template take<int64_t>(4);
+        sync = a.template take<int>(SYNC_LEN);
     }
     PassArgs args(const void* C, const void* R, void* U, void* V) const;
     SyrkArgs syrk_args(const void* C, const void* U, const void* V) const;
     // the multi-instance table entry of a run over (C, R, U, V)
     BatchItem item(const PassArgs& a, int* flag) const;
-    // pass + reduce + contraction (+ assembly and control when `control`);
-    // with `ev0` non-null, the pass launch is bracketed by the two events
+    // pass (with its reduction) + contraction (with the H assembly)
+    // (+ control when `control`); with `ev0` non-null, the pass launch is
+    // bracketed by the two events
     int step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+    // clears the arrival counters (before the first kernel of a run)
+    int reset_sync(hipStream_t s);
 };
 
 size_t engine_bytes(int64_t m, int d, int dtype);

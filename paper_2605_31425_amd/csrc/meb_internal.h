@@ -129,6 +129,13 @@ struct RecLayout {
     }
 };
 
+// Coefficients of one active-list entry (working precision): the ball's
+// vector parts are a e + b v with e = c_i - y and v = v_i, for the sums
+// sum gamma s (sv), sum_mid s / ||s|| (sw) and the updated multiplier (kv,
+// also the V row written), then a flag word (bit 0: v_i is read, bit 1: the
+// V row is written).
+constexpr int ACT_NC = 7;
+
 // Pass modes.
 enum PassMode : int { PM_EVAL = 0, PM_MULT = 1, PM_DONE = 2 };
 
@@ -164,12 +171,24 @@ struct PassArgs {
     int32_t* mid_idx;    // nwaves segments of bw entries
     double* mid_coef;
     int32_t* mid_cnt;    // nwaves
+    int32_t* act_idx;    // nwaves segments of bw entries: balls with vector parts
+    void* act_coef;      // ACT_NC working-precision coefficients per entry
+    double* red;         // reduced record (len), then the group partials
+    int* sync;           // arrival counters of the in-kernel reductions (zero between passes)
     int force_mode;      // -1: read S_MODE from state; else PM_EVAL / PM_MULT
     int want_kkt;        // evaluate KKT terms in PM_EVAL (meb_al_eval)
     int want_mid;        // write the mid list (Hessian contraction needed)
-    int dense_vout;      // write every V row of the update (else only u != 0 rows)
     double etas[NT];     // Armijo trial step sizes
 };
+
+// Arrival counters (ints) of the in-kernel reductions: SYNC_GROUPS group
+// counters and one top counter for the pass, then one counter per tile pair
+// of the contraction.  Each counter returns to zero after use.
+constexpr int RED_GROUP = 32;      // block records summed per group
+constexpr int SYNC_GROUPS = 64;    // at most RED_GROUP * SYNC_GROUPS pass blocks
+constexpr int SYNC_TOP = SYNC_GROUPS;
+constexpr int SYNC_SYRK = 128;     // first tile-pair counter
+constexpr int SYNC_LEN = 4096;
 
 struct SyrkArgs {
     const void* C;
@@ -177,34 +196,31 @@ struct SyrkArgs {
     const void* U;
     int d;
     int dtype;
-    double* state;       // block 0 writes S_HSKIP
+    double* state;       // block 0 writes S_HSKIP; the tile finishers write H
     StateLayout sl;
-    const double* red;   // reduced record (its mid count)
+    const double* red;   // reduced record of the pass
     RecLayout rl;
-    const int32_t* list_idx;   // compacted mid list (K entries)
-    const double* list_coef;
-    const int64_t* list_total; // K
+    const int32_t* mid_cnt;    // per-wave mid counts of the pass
+    const int32_t* mid_idx;    // per-wave segments of bw entries
+    const double* mid_coef;
+    int nwaves;
+    int64_t bw;
     double* out;         // ksplit x pairs x T x T partial blocks
+    int* sync;           // tile-pair counters (at SYNC_SYRK)
     int ksplit;
     int tile;
     int ntile;           // tiles per dimension
     double skip_k;       // in a line-search pass, skip when K exceeds this
 };
 
-// Concatenates the per-wave mid-list segments into one list (ascending wave
-// order): offsets by a single-block scan, then a copy.
 // One instance of the multi-instance step: the arguments of its pass,
-// reduction, contraction, assembly and control kernels.  Lives in a device
-// table indexed by slot; a tick names the slots it steps.
+// contraction and control kernels.  Lives in a device table indexed by slot;
+// a tick names the slots it steps.
 struct BatchItem {
     PassArgs pa;
     PassConfig pc;
     SyrkArgs sa;
-    double* red;          // reduced record, then the slice partials
-    int64_t* list_offs;   // per-wave offsets of the compacted mid list
     int* flag;            // nullable: the state's mode after each control step
-    int ksplit, ntile;
-    int use_syrk;
 };
 
 // Instances of one launch and the first flat block of each (ascending);
@@ -216,22 +232,17 @@ struct TickList {
     int off[TICK_MAX + 1];
 };
 
-// One solver step (pass, reduction, mid-list compaction, contraction,
+// One solver step (pass with its reduction, contraction with the Hessian
 // assembly, control) for the `n` instances slots[0..n) of the device table
 // `dtab`; `htab` is its host mirror (read for the launch shapes).  The pass
-// takes one launch per template instance among the items; every other kernel
-// one launch per TICK_MAX items.
+// takes one launch per template instance among the items; the other two
+// kernels one launch per TICK_MAX items.
 // The pass of a group of items that share one template instance.
 hipError_t launch_pass_group(const BatchItem* dtab, const TickList& L, int blocks, int max_d, int dtype,
                              const PassConfig& cfg, hipStream_t s);
 hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* slots, int n, hipStream_t s);
 int pass_variant(int dtype, const PassConfig& cfg);
-int reduce_nslice(int nrec);
 size_t control_lds_bytes(int n1);
-
-hipError_t launch_mid_compact(const int32_t* mid_cnt, int nwaves, int64_t bw, const int32_t* seg_idx,
-                              const double* seg_coef, int64_t* offs, int64_t* total, int32_t* out_idx,
-                              double* out_coef, const double* state, hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // Launchers (meb_kernels.hip).  All return hipError_t of the launch.
@@ -239,28 +250,28 @@ hipError_t launch_mid_compact(const int32_t* mid_cnt, int nwaves, int64_t bw, co
 // The evaluation pass: the solver's evaluation or multiplier update (+ KKT
 // + next evaluation) as the state's mode says, nothing when the run is done;
 // force_mode = PM_EVAL gives a single evaluation (want_kkt adds the updated
-// multipliers and the KKT terms).
+// multipliers and the KKT terms).  The last block to finish sums the block
+// records into a.red (fixed order), so the record is complete when the
+// launch is.
 hipError_t launch_pass(const PassArgs& a, const PassConfig& cfg, hipStream_t s);
 // the single evaluation (force_mode >= 0), called by launch_pass
 hipError_t launch_pass_eval(const PassArgs& a, const PassConfig& cfg, hipStream_t s);
-// Sums (maxima for the KKT maxima) of nrec records of len doubles, `stride`
-// doubles apart; the pass leaves one record per block at stride
-// waves_per_block * len.
-hipError_t launch_reduce_records(const double* rec, int nrec, int len, int64_t stride, double* out, hipStream_t s);
+// The rank-one Hessian part over the pass's mid list, tiled; the last block
+// of each tile pair sums the k-split partials and writes its part of H
+// (with the diagonal and the r row and column from the record) into the
+// state, unless the contraction is skipped.
 hipError_t launch_syrk(const SyrkArgs& a, hipStream_t s);
 int syrk_ksplit(int d);
 int syrk_tile();
 hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag_host_mapped,
                           hipStream_t s);
-hipError_t launch_assemble(double* state, StateLayout sl, RecLayout rl, const double* red, const double* syrk,
-                           int ksplit, int ntile, int have_syrk, hipStream_t s);
-hipError_t launch_eval_assemble(const double* state, StateLayout sl, RecLayout rl, const double* red,
-                                const double* syrk_out, int ksplit, int tile, int ntile, int have_syrk, double sigma,
-                                double tau, const double* x1, const double* xbar, double* out_g, double* out_H,
-                                hipStream_t s);
+// g of a single evaluation, and a copy of the H assembled in the state
+hipError_t launch_eval_outputs(const double* state, StateLayout sl, RecLayout rl, const double* red, double sigma,
+                               double tau, const double* y, const double* xbar, double* out_g, double* out_H,
+                               hipStream_t s);
+// Partition of a scan over rows (the lanes per row are chosen per launch).
 struct ScanCfg {
-    int G, vec, nl;
-    int64_t bw;  // rows per wave
+    int64_t bw;  // rows per wave, a multiple of 64
     int nwaves, blocks;
 };
 ScanCfg scan_config(int64_t m, int d, int num_cu);

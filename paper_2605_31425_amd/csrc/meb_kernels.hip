@@ -7,96 +7,25 @@
 #include "meb_device.h"
 
 namespace meb {
-// ---------------------------------------------------------------------------
-// Fixed-order reduction of per-wave records: out[e] = sum_w rec[w][e]
-// (maximum for the three KKT maxima).  Two stages: slices of records, then
-// the slices; both in ascending order.
-// ---------------------------------------------------------------------------
-
-constexpr int RED_SLICE = 32;
-
-// Stage 1: block (x, y) sums entries [64 x, 64 x + 64) over the records of
-// slice y; its four waves take records w = 4 k + wave, then combine in wave
-// order.  Records are `stride` doubles apart.
-__device__ __forceinline__ void reduce1_body(const double* rec, int nrec, int len, int64_t stride, int max_lo,
-                                             int max_hi, double* part, int bx, int by, int ny) {
-    __shared__ double sp[4][64];
-    const int e = bx * 64 + (threadIdx.x & 63);
-    const int sub = threadIdx.x >> 6;
-    const int per = (nrec + ny - 1) / ny;
-    const int w0 = by * per, w1 = min(nrec, w0 + per);
-    const bool ismax = (e >= max_lo && e < max_hi);
-    double acc = 0.0;
-    if (e < len) {
-        for (int w = w0 + sub; w < w1; w += 4) {
-            const double v = rec[(int64_t)w * stride + e];
-            acc = ismax ? fmax(acc, v) : acc + v;
-        }
-    }
-    sp[sub][threadIdx.x & 63] = acc;
-    __syncthreads();
-    if (threadIdx.x < 64 && e < len) {
-        double v = sp[0][threadIdx.x];
-        for (int k = 1; k < 4; ++k) v = ismax ? fmax(v, sp[k][threadIdx.x]) : v + sp[k][threadIdx.x];
-        part[(size_t)by * len + e] = v;
-    }
-}
-
-__global__ __launch_bounds__(256) void reduce_stage1(const double* rec, int nrec, int len, int64_t stride, int max_lo,
-                                                     int max_hi, double* part) {
-    reduce1_body(rec, nrec, len, stride, max_lo, max_hi, part, blockIdx.x, blockIdx.y, gridDim.y);
-}
-
-__device__ __forceinline__ void reduce2_body(const double* part, int nslice, int len, int max_lo, int max_hi,
-                                             double* out, int bx) {
-    const int e = bx * 256 + threadIdx.x;
-    if (e >= len) return;
-    const bool ismax = (e >= max_lo && e < max_hi);
-    double acc = 0.0;
-    for (int w = 0; w < nslice; ++w) {
-        const double v = part[(size_t)w * len + e];
-        acc = ismax ? fmax(acc, v) : acc + v;
-    }
-    out[e] = acc;
-}
-
-__global__ __launch_bounds__(256) void reduce_stage2(const double* part, int nslice, int len, int max_lo, int max_hi,
-                                                     double* out) {
-    reduce2_body(part, nslice, len, max_lo, max_hi, out, blockIdx.x);
-}
-
-int reduce_nslice(int nrec) {
-    int nslice = (nrec + 15) / 16;
-    if (nslice > RED_SLICE) nslice = RED_SLICE;
-    if (nslice < 1) nslice = 1;
-    return nslice;
-}
-
-hipError_t launch_reduce_records(const double* rec, int nrec, int len, int64_t stride, double* out, hipStream_t s) {
-    // `out` must have room for (RED_SLICE + 1) * len doubles: the slice
-    // partials live after the result.  The three maxima sit at a fixed
-    // offset ahead of the d-dependent vector parts of the record.
-    const RecLayout rl = RecLayout::make(0);
-    const int max_lo = rl.kmax, max_hi = rl.kmax + 3;
-    const int nslice = reduce_nslice(nrec);
-    double* part = out + len;
-    dim3 g1((len + 63) / 64, nslice);
-    hipLaunchKernelGGL(reduce_stage1, g1, dim3(256), 0, s, rec, nrec, len, stride, max_lo, max_hi, part);
-    hipLaunchKernelGGL(reduce_stage2, dim3((len + 255) / 256), dim3(256), 0, s, part, nslice, len, max_lo, max_hi,
-                       out);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // Rank-one Hessian contraction  sum_{i in mid} coef_i s_i s_i^T  (FP64
-// accumulation), tiled T x T over the upper triangle of d x d, split over
-// the wave segments of the mid list.  s_i is recomputed from C and V
-// exactly as the pass computed it.
+// accumulation), tiled T x T over the upper triangle of d x d and split
+// over the pass's wave segments of the mid list (no compaction: block y of
+// a tile pair walks the mid entries of waves [y W / S, (y + 1) W / S)).
+// s_i is recomputed from C and V exactly as the pass computed it.  The last
+// of the S blocks of a tile pair to finish sums their partial tiles in
+// order and writes the tile of H (Section 4):
+//   H_rr = tau/sigma + sigma N_I + sigma/2 N_mid
+//   H_rc = sigma/2 sum_mid s_i / ||s_i||
+//   H_cc = (tau/sigma + sigma N_I + sum_mid gamma_i) I + sum_mid coef_i s_i s_i^T
+// (tile pair 0 also writes the r row and column).
 // ---------------------------------------------------------------------------
 
 constexpr int SYRK_T = 32;
 constexpr int SYRK_KB = 32;     // mid balls staged per step
 constexpr int SYRK_KSPLIT = 8;  // blocks along the mid list per tile pair
+constexpr int SYRK_SEGS = 1024; // most wave segments one block walks
 
 int syrk_tile() { return SYRK_T; }
 
@@ -105,87 +34,24 @@ int syrk_ksplit(int d) {
     return SYRK_KSPLIT;
 }
 
-// Per-wave mid counts -> exclusive offsets and total, then the copy into one
-// list.  Skipped when the run is done.
-__device__ __forceinline__ void mid_scan_body(const int32_t* cnt, int nw, int64_t* offs, int64_t* total,
-                                              const double* st) {
-    __shared__ int64_t sc[1024];
-    if ((int)st[S_MODE] == PM_DONE) return;
-    const int t = threadIdx.x;
-    const int per = (nw + 1023) / 1024;
-    const int w0 = t * per, w1 = min(nw, w0 + per);
-    int64_t c = 0;
-    for (int w = w0; w < w1; ++w) c += cnt[w];
-    sc[t] = c;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int64_t v = t >= o ? sc[t - o] : 0;
-        __syncthreads();
-        sc[t] += v;
-        __syncthreads();
-    }
-    int64_t run = t > 0 ? sc[t - 1] : 0;
-    for (int w = w0; w < w1; ++w) {
-        offs[w] = run;
-        run += cnt[w];
-    }
-    if (t == 1023) *total = sc[1023];
-}
-
-__global__ __launch_bounds__(1024) void mid_scan_kernel(const int32_t* cnt, int nw, int64_t* offs, int64_t* total,
-                                                        const double* st) {
-    mid_scan_body(cnt, nw, offs, total, st);
-}
-
-__device__ __forceinline__ void mid_copy_body(const int32_t* cnt, int nw, int64_t bw, const int32_t* si,
-                                              const double* sc, const int64_t* offs, int32_t* oi, double* oc,
-                                              const double* st, int bx) {
-    if ((int)st[S_MODE] == PM_DONE) return;
-    const int lane = lane_id();
-    const int64_t w = (int64_t)bx * 4 + threadIdx.x / WAVE;
-    if (w >= nw) return;
-    const int64_t n = cnt[w], off = offs[w];
-    for (int64_t k = lane; k < n; k += WAVE) {
-        oi[off + k] = si[w * bw + k];
-        oc[off + k] = sc[w * bw + k];
-    }
-}
-
-__global__ __launch_bounds__(256) void mid_copy_kernel(const int32_t* cnt, int nw, int64_t bw, const int32_t* si,
-                                                       const double* sc, const int64_t* offs, int32_t* oi,
-                                                       double* oc, const double* st) {
-    mid_copy_body(cnt, nw, bw, si, sc, offs, oi, oc, st, blockIdx.x);
-}
-
-hipError_t launch_mid_compact(const int32_t* mid_cnt, int nwaves, int64_t bw, const int32_t* seg_idx,
-                              const double* seg_coef, int64_t* offs, int64_t* total, int32_t* out_idx,
-                              double* out_coef, const double* state, hipStream_t s) {
-    hipLaunchKernelGGL(mid_scan_kernel, dim3(1), dim3(1024), 0, s, mid_cnt, nwaves, offs, total, state);
-    hipLaunchKernelGGL(mid_copy_kernel, dim3((nwaves + 3) / 4), dim3(256), 0, s, mid_cnt, nwaves, bw, seg_idx,
-                       seg_coef, offs, out_idx, out_coef, state);
-    return hipGetLastError();
-}
-
-// Rank-one Hessian part  sum_{i in mid} coef_i s_i s_i^T  with FP64
-// accumulation over the compacted mid list, tiled T x T over the upper
-// triangle of the d x d block; blockIdx.y splits the list evenly.  s_i is
-// recomputed from C and V exactly as the pass computed it.  In a line-search
-// pass with more than skip_k rows the contraction is skipped (block 0 sets
-// S_HSKIP) and the control step re-evaluates if it needs this H.
 template <typename T>
 __device__ __forceinline__ void syrk_body(const SyrkArgs& a, int bx, int by, int npairs) {
     __shared__ double sI[SYRK_KB][SYRK_T + 1];
     __shared__ double sJ[SYRK_KB][SYRK_T + 1];
     __shared__ double cf[SYRK_KB];
     __shared__ int32_t ix[SYRK_KB];
+    __shared__ int32_t pref[SYRK_SEGS + 1];
+    __shared__ int s_last;
     double* st = a.state;
     const int mode = (int)st[S_MODE];
     if (mode == PM_DONE) return;
     const int d = a.d;
     const StateLayout sl = a.sl;
+    const RecLayout rl = a.rl;
+    const double* red = a.red;
     const bool have_dir = (mode == PM_EVAL) && st[S_HAVE_DIR] != 0.0;
-    const int64_t K = *a.list_total;
-    const bool skip = have_dir && (double)K > a.skip_k;
+    const double K = red[rl.nm];
+    const bool skip = have_dir && K > a.skip_k;
     if (bx == 0 && by == 0 && threadIdx.x == 0) st[S_HSKIP] = skip ? 1.0 : 0.0;
     if (skip) return;
     const double sig = (mode == PM_MULT) ? st[S_SIGMA_NEXT] : st[S_SIGMA];
@@ -196,19 +62,66 @@ __device__ __forceinline__ void syrk_body(const SyrkArgs& a, int bx, int by, int
         ++I;
     }
     const int J = I + p;
-    const int64_t per = (K + a.ksplit - 1) / a.ksplit;
-    const int64_t k0 = (int64_t)by * per, k1 = min(K, k0 + per);
+    // this block's wave segments and their exclusive prefix (LDS)
+    const int per = (a.nwaves + a.ksplit - 1) / a.ksplit;
+    const int w0 = by * per, w1 = min(a.nwaves, w0 + per);
+    const int nseg = max(0, w1 - w0);
+    // exclusive prefix of the segment counts: each thread sums a run of
+    // four, the runs are scanned in LDS, then each run is written out
+    {
+        __shared__ int runs[256];
+        const int q0 = threadIdx.x * 4;
+        int c[4], t = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = (q0 + u < nseg) ? a.mid_cnt[w0 + q0 + u] : 0;
+            t += c[u];
+        }
+        runs[threadIdx.x] = t;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const int v = threadIdx.x >= o ? runs[threadIdx.x - o] : 0;
+            __syncthreads();
+            runs[threadIdx.x] += v;
+            __syncthreads();
+        }
+        int run = runs[threadIdx.x] - t;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (q0 + u <= nseg) pref[q0 + u] = run;
+            run += c[u];
+        }
+        __syncthreads();
+    }
+    const int total = pref[nseg];
     const T* C = static_cast<const T*>(a.C);
     const T* V = static_cast<const T*>(a.V);
     const T* U = static_cast<const T*>(a.U);
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     double acc[2][2] = {{0, 0}, {0, 0}};
-    for (int64_t kb = k0; kb < k1; kb += SYRK_KB) {
-        const int nk = (int)min((int64_t)SYRK_KB, k1 - kb);
+    for (int kb = 0; kb < total; kb += SYRK_KB) {
+        const int nk = min(SYRK_KB, total - kb);
         __syncthreads();
         if (threadIdx.x < SYRK_KB) {
-            ix[threadIdx.x] = threadIdx.x < nk ? a.list_idx[kb + threadIdx.x] : 0;
-            cf[threadIdx.x] = threadIdx.x < nk ? a.list_coef[kb + threadIdx.x] : 0.0;
+            const int e = kb + threadIdx.x;
+            int32_t id = 0;
+            double c = 0.0;
+            if (threadIdx.x < nk) {
+                // segment holding entry e: the last q with pref[q] <= e
+                int lo = 0, hi = nseg - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pref[mid] <= e)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                const int64_t pos = (int64_t)(w0 + lo) * a.bw + (e - pref[lo]);
+                id = a.mid_idx[pos];
+                c = a.mid_coef[pos];
+            }
+            ix[threadIdx.x] = id;
+            cf[threadIdx.x] = c;
         }
         __syncthreads();
         for (int e = threadIdx.x; e < SYRK_KB * SYRK_T * 2; e += 256) {
@@ -241,10 +154,42 @@ __device__ __forceinline__ void syrk_body(const SyrkArgs& a, int bx, int by, int
         }
     }
     double* out = a.out + ((size_t)by * npairs + bx) * SYRK_T * SYRK_T;
-    out[ty * SYRK_T + tx] = acc[0][0];
-    out[ty * SYRK_T + tx + 16] = acc[0][1];
-    out[(ty + 16) * SYRK_T + tx] = acc[1][0];
-    out[(ty + 16) * SYRK_T + tx + 16] = acc[1][1];
+    st_shared_dev(out + ty * SYRK_T + tx, acc[0][0]);
+    st_shared_dev(out + ty * SYRK_T + tx + 16, acc[0][1]);
+    st_shared_dev(out + (ty + 16) * SYRK_T + tx, acc[1][0]);
+    st_shared_dev(out + (ty + 16) * SYRK_T + tx + 16, acc[1][1]);
+
+    // the last block of the tile pair assembles its part of H
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = arrive(&a.sync[SYNC_SYRK + bx]) == a.ksplit - 1;
+    __syncthreads();
+    if (!s_last) return;
+    const double tau = st[S_TAU];
+    const double base = tau / sig + sig * red[rl.ni];
+    const int n1 = d + 1;
+    double* H = st + sl.H;
+    for (int e = threadIdx.x; e < SYRK_T * SYRK_T; e += blockDim.x) {
+        const int r = e / SYRK_T, c = e % SYRK_T;
+        const int k = I * SYRK_T + r, l = J * SYRK_T + c;
+        if (k >= d || l >= d) continue;
+        double v = 0.0;
+        for (int ks = 0; ks < a.ksplit; ++ks) v += ld_shared_dev(a.out + ((size_t)ks * npairs + bx) * SYRK_T * SYRK_T + e);
+        if (k == l) v += base + red[rl.sg];
+        H[(1 + k) * n1 + 1 + l] = v;
+        if (I != J) H[(1 + l) * n1 + 1 + k] = v;
+    }
+    if (bx == 0) {
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+            if (k == 0) {
+                H[0] = base + 0.5 * sig * red[rl.nm];
+            } else {
+                const double v = 0.5 * sig * red[rl.sw + k - 1];
+                H[k] = v;
+                H[k * n1] = v;
+            }
+        }
+    }
+    if (threadIdx.x == 0) a.sync[SYNC_SYRK + bx] = 0;
 }
 
 template <typename T>
@@ -254,6 +199,7 @@ __global__ __launch_bounds__(256) void syrk_kernel(SyrkArgs a) {
 
 hipError_t launch_syrk(const SyrkArgs& a, hipStream_t s) {
     const int pairs = a.ntile * (a.ntile + 1) / 2;
+    if ((a.nwaves + a.ksplit - 1) / a.ksplit > SYRK_SEGS || pairs > SYNC_LEN - SYNC_SYRK) return hipErrorInvalidValue;
     dim3 grid(pairs, a.ksplit);
     if (a.dtype == 0)
         hipLaunchKernelGGL(syrk_kernel<double>, grid, dim3(256), 0, s, a);
@@ -262,104 +208,29 @@ hipError_t launch_syrk(const SyrkArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Hessian assembly from the reduced record and the contraction blocks:
-//   H_rr = tau/sigma + sigma N_I + sigma/2 N_mid
-//   H_rc = sigma/2 sum_mid w_i
-//   H_cc = (tau/sigma + sigma N_I + sum_mid gamma_i) I + sum_mid coef_i s_i s_i^T
-// (the per-case generalized Jacobian of the cone projection, Section 4).
-// ---------------------------------------------------------------------------
-
-__device__ void assemble_H(int d, const RecLayout& rl, const double* red, const double* syrk, int ksplit, int ntile,
-                           int have_syrk, double sigma, double tau, double* H) {
+// g of a single evaluation (meb_al_eval), and a copy of the H the
+// contraction assembled in the state.
+__global__ __launch_bounds__(256) void eval_outputs_kernel(const double* st, StateLayout sl, RecLayout rl,
+                                                           const double* red, double sigma, double tau, int d,
+                                                           const double* y, const double* xbar, double* out_g,
+                                                           double* out_H) {
     const int n1 = d + 1;
-    const double base = tau / sigma + sigma * red[rl.ni];
-    const int npairs = ntile * (ntile + 1) / 2;
-    for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) {
-        const int a = e / n1, b = e % n1;
-        double v;
-        if (a == 0 && b == 0) {
-            v = base + 0.5 * sigma * red[rl.nm];
-        } else if (a == 0 || b == 0) {
-            const int k = (a == 0 ? b : a) - 1;
-            v = 0.5 * sigma * red[rl.sw + k];
-        } else {
-            const int k = a - 1, l = b - 1;
-            v = (k == l) ? base + red[rl.sg] : 0.0;
-            if (have_syrk) {
-                int kk = k, ll = l;
-                if (kk / SYRK_T > ll / SYRK_T) {
-                    const int t = kk;
-                    kk = ll;
-                    ll = t;
-                }
-                const int I = kk / SYRK_T, J = ll / SYRK_T;
-                // pair index of (I, J) in the row-major upper triangle
-                const int pidx = I * ntile - I * (I - 1) / 2 + (J - I);
-                const int ia = kk % SYRK_T, ib = ll % SYRK_T;
-                double sacc = 0.0;
-                for (int ks = 0; ks < ksplit; ++ks)
-                    sacc += syrk[((size_t)ks * npairs + pidx) * SYRK_T * SYRK_T + ia * SYRK_T + ib];
-                v += sacc;
-            }
+    for (int k = threadIdx.x + blockIdx.x * blockDim.x; k < n1 * n1; k += blockDim.x * gridDim.x) {
+        if (out_H) out_H[k] = st[sl.H + k];
+        if (out_g && k < n1) {
+            const double sv = (k == 0) ? red[rl.su] : red[rl.sv + k - 1];
+            out_g[k] = (k == 0 ? 1.0 : 0.0) - sv + (tau / sigma) * (y[k] - xbar[k]);
         }
-        H[e] = v;
     }
 }
 
-// Parallel assembly of H into the state (one thread per entry).  Runs after
-// the contraction and before the control step; it is a no-op when the run is
-// done.  The control step reads H only when it takes a Newton step.
-__device__ __forceinline__ void assemble_body(double* st, StateLayout sl, RecLayout rl, const double* red,
-                                              const double* syrk, int ksplit, int ntile, int have_syrk, int bx) {
-    const int mode = (int)st[S_MODE];
-    if (mode == PM_DONE) return;
-    if (have_syrk && st[S_HSKIP] != 0.0) return;
-    const double sigma = (mode == PM_MULT) ? st[S_SIGMA_NEXT] : st[S_SIGMA];
-    const double tau = st[S_TAU];
+hipError_t launch_eval_outputs(const double* state, StateLayout sl, RecLayout rl, const double* red, double sigma,
+                               double tau, const double* y, const double* xbar, double* out_g, double* out_H,
+                               hipStream_t s) {
     const int n1 = sl.n1;
-    const int e = bx * 256 + threadIdx.x;
-    if (e >= n1 * n1) return;
-    const int a = e / n1, b = e % n1;
-    const double base = tau / sigma + sigma * red[rl.ni];
-    double v;
-    if (a == 0 && b == 0) {
-        v = base + 0.5 * sigma * red[rl.nm];
-    } else if (a == 0 || b == 0) {
-        v = 0.5 * sigma * red[rl.sw + (a == 0 ? b : a) - 1];
-    } else {
-        const int k = a - 1, l = b - 1;
-        v = (k == l) ? base + red[rl.sg] : 0.0;
-        if (have_syrk) {
-            int kk = k, ll = l;
-            if (kk / SYRK_T > ll / SYRK_T) {
-                const int t = kk;
-                kk = ll;
-                ll = t;
-            }
-            const int I = kk / SYRK_T, J = ll / SYRK_T;
-            const int npairs = ntile * (ntile + 1) / 2;
-            const int pidx = I * ntile - I * (I - 1) / 2 + (J - I);
-            const int ia = kk % SYRK_T, ib = ll % SYRK_T;
-            double sacc = 0.0;
-            for (int ks = 0; ks < ksplit; ++ks)
-                sacc += syrk[((size_t)ks * npairs + pidx) * SYRK_T * SYRK_T + ia * SYRK_T + ib];
-            v += sacc;
-        }
-    }
-    st[sl.H + e] = v;
-}
-
-__global__ __launch_bounds__(256) void assemble_kernel(double* st, StateLayout sl, RecLayout rl, const double* red,
-                                                       const double* syrk, int ksplit, int ntile, int have_syrk) {
-    assemble_body(st, sl, rl, red, syrk, ksplit, ntile, have_syrk, blockIdx.x);
-}
-
-hipError_t launch_assemble(double* state, StateLayout sl, RecLayout rl, const double* red, const double* syrk,
-                           int ksplit, int ntile, int have_syrk, hipStream_t s) {
-    const int n = sl.n1 * sl.n1;
-    hipLaunchKernelGGL(assemble_kernel, dim3((n + 255) / 256), dim3(256), 0, s, state, sl, rl, red, syrk, ksplit,
-                       ntile, have_syrk);
+    const int blocks = (n1 * n1 + 255) / 256;
+    hipLaunchKernelGGL(eval_outputs_kernel, dim3(blocks), dim3(256), 0, s, state, sl, rl, red, sigma, tau, n1 - 1, y,
+                       xbar, out_g, out_H);
     return hipGetLastError();
 }
 
@@ -848,7 +719,7 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
     }
     __syncthreads();
     if (s_next) return;
-    // Newton direction: H dir = -g, H assembled by assemble_kernel
+    // Newton direction: H dir = -g, H assembled by the contraction
     int rc;
     if (n1 <= CTRL_CHOL_LDS_MAX_N) {
         // LDS: scratch = [rd (n1) | rhs (n1)], lmat = H with an odd leading dimension
@@ -912,65 +783,21 @@ hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const dou
 // instance's blocks located by the tick list.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int reduce_nslice_dev(int nrec) {
-    int nslice = (nrec + 15) / 16;
-    if (nslice > RED_SLICE) nslice = RED_SLICE;
-    if (nslice < 1) nslice = 1;
-    return nslice;
-}
-
-__global__ __launch_bounds__(256) void reduce1_batch_kernel(const BatchItem* tab, TickList L, int max_lo, int max_hi) {
-    const int k = tick_find(L, blockIdx.x);
-    const BatchItem& it = tab[L.slot[k]];
-    const int b = blockIdx.x - L.off[k];
-    const int len = it.pa.rl.len;
-    const int nx = (len + 63) / 64;
-    reduce1_body(it.pa.rec, it.pc.blocks, len, (int64_t)WPB * len, max_lo, max_hi, it.red + len, b % nx, b / nx,
-                 reduce_nslice_dev(it.pc.blocks));
-}
-
-__global__ __launch_bounds__(256) void reduce2_batch_kernel(const BatchItem* tab, TickList L, int max_lo, int max_hi) {
-    const int k = tick_find(L, blockIdx.x);
-    const BatchItem& it = tab[L.slot[k]];
-    const int len = it.pa.rl.len;
-    reduce2_body(it.red + len, reduce_nslice_dev(it.pc.blocks), len, max_lo, max_hi, it.red, blockIdx.x - L.off[k]);
-}
-
-__global__ __launch_bounds__(1024) void mid_scan_batch_kernel(const BatchItem* tab, TickList L) {
-    const BatchItem& it = tab[L.slot[blockIdx.x]];
-    mid_scan_body(it.pa.mid_cnt, it.pc.nwaves, it.list_offs, const_cast<int64_t*>(it.sa.list_total), it.pa.state);
-}
-
-__global__ __launch_bounds__(256) void mid_copy_batch_kernel(const BatchItem* tab, TickList L) {
-    const int k = tick_find(L, blockIdx.x);
-    const BatchItem& it = tab[L.slot[k]];
-    mid_copy_body(it.pa.mid_cnt, it.pc.nwaves, it.pc.bw, it.pa.mid_idx, it.pa.mid_coef, it.list_offs,
-                  const_cast<int32_t*>(it.sa.list_idx), const_cast<double*>(it.sa.list_coef), it.pa.state,
-                  blockIdx.x - L.off[k]);
-}
-
 __global__ __launch_bounds__(256) void syrk_batch_kernel(const BatchItem* tab, TickList L) {
     const int k = tick_find(L, blockIdx.x);
     const BatchItem& it = tab[L.slot[k]];
     const int b = blockIdx.x - L.off[k];
-    const int npairs = it.ntile * (it.ntile + 1) / 2;
+    const int npairs = it.sa.ntile * (it.sa.ntile + 1) / 2;
     if (it.sa.dtype == 0)
         syrk_body<double>(it.sa, b % npairs, b / npairs, npairs);
     else
         syrk_body<float>(it.sa, b % npairs, b / npairs, npairs);
 }
 
-__global__ __launch_bounds__(256) void assemble_batch_kernel(const BatchItem* tab, TickList L) {
-    const int k = tick_find(L, blockIdx.x);
-    const BatchItem& it = tab[L.slot[k]];
-    assemble_body(const_cast<double*>(it.pa.state), it.pa.sl, it.pa.rl, it.red, it.sa.out, it.ksplit, it.ntile, it.use_syrk,
-                  blockIdx.x - L.off[k]);
-}
-
 __global__ __launch_bounds__(CTRL_THREADS) void control_batch_kernel(const BatchItem* tab, TickList L) {
     const BatchItem& it = tab[L.slot[blockIdx.x]];
     double* st = const_cast<double*>(it.pa.state);
-    control_body(st, it.pa.sl, it.pa.rl, it.red);
+    control_body(st, it.pa.sl, it.pa.rl, it.pa.red);
     if (threadIdx.x == 0 && it.flag) *it.flag = (int)st[S_MODE];
 }
 
@@ -991,13 +818,11 @@ int make_list(const BatchItem* htab, const int* slots, int n, TickList& L, F&& b
 }  // namespace
 
 hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* slots, int n, hipStream_t s) {
-    const RecLayout r0 = RecLayout::make(0);
-    const int max_lo = r0.kmax, max_hi = r0.kmax + 3;
     for (int c0 = 0; c0 < n; c0 += TICK_MAX) {
         const int cn = n - c0 < TICK_MAX ? n - c0 : TICK_MAX;
         const int* sl = slots + c0;
         TickList L;
-        // evaluation passes, one launch per template instance
+        // evaluation passes (with their reductions), one launch per template instance
         {
             int ids[TICK_MAX];
             bool done[TICK_MAX];
@@ -1021,28 +846,17 @@ hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* 
                 if (e != hipSuccess) return e;
             }
         }
-        int nb = make_list(htab, sl, cn, L, [](const BatchItem& it) {
-            return ((it.pa.rl.len + 63) / 64) * reduce_nslice(it.pc.blocks);
-        });
-        hipLaunchKernelGGL(reduce1_batch_kernel, dim3(nb), dim3(256), 0, s, dtab, L, max_lo, max_hi);
-        nb = make_list(htab, sl, cn, L, [](const BatchItem& it) { return (it.pa.rl.len + 255) / 256; });
-        hipLaunchKernelGGL(reduce2_batch_kernel, dim3(nb), dim3(256), 0, s, dtab, L, max_lo, max_hi);
-        // mid-list compaction and contraction for the instances that use it
+        // contraction with the Hessian assembly
         int ws[TICK_MAX];
         int nw = 0;
         for (int k = 0; k < cn; ++k)
-            if (htab[sl[k]].use_syrk && htab[sl[k]].pa.want_mid) ws[nw++] = sl[k];
+            if (htab[sl[k]].pa.want_mid) ws[nw++] = sl[k];
         if (nw > 0) {
-            make_list(htab, ws, nw, L, [](const BatchItem&) { return 1; });
-            hipLaunchKernelGGL(mid_scan_batch_kernel, dim3(nw), dim3(1024), 0, s, dtab, L);
-            nb = make_list(htab, ws, nw, L, [](const BatchItem& it) { return (it.pc.nwaves + 3) / 4; });
-            hipLaunchKernelGGL(mid_copy_batch_kernel, dim3(nb), dim3(256), 0, s, dtab, L);
-            nb = make_list(htab, ws, nw, L,
-                           [](const BatchItem& it) { return it.ntile * (it.ntile + 1) / 2 * it.ksplit; });
+            const int nb = make_list(htab, ws, nw, L, [](const BatchItem& it) {
+                return it.sa.ntile * (it.sa.ntile + 1) / 2 * it.sa.ksplit;
+            });
             hipLaunchKernelGGL(syrk_batch_kernel, dim3(nb), dim3(256), 0, s, dtab, L);
         }
-        nb = make_list(htab, sl, cn, L, [](const BatchItem& it) { return (it.pa.sl.n1 * it.pa.sl.n1 + 255) / 256; });
-        hipLaunchKernelGGL(assemble_batch_kernel, dim3(nb), dim3(256), 0, s, dtab, L);
         size_t lds = 0;
         for (int k = 0; k < cn; ++k) {
             const size_t b = control_lds_bytes(htab[sl[k]].pa.sl.n1);
@@ -1058,33 +872,6 @@ hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* 
     return hipSuccess;
 }
 
-// g and H of a single evaluation (meb_al_eval).
-__global__ __launch_bounds__(CTRL_THREADS) void eval_assemble_kernel(RecLayout rl, const double* red,
-                                                                     const double* syrk, int ksplit, int ntile,
-                                                                     int have_syrk, double sigma, double tau, int d,
-                                                                     const double* y, const double* xbar,
-                                                                     double* out_g, double* out_H) {
-    const int n1 = d + 1;
-    if (out_g) {
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) {
-            const double sv = (k == 0) ? red[rl.su] : red[rl.sv + k - 1];
-            out_g[k] = (k == 0 ? 1.0 : 0.0) - sv + (tau / sigma) * (y[k] - xbar[k]);
-        }
-    }
-    if (out_H) assemble_H(d, rl, red, syrk, ksplit, ntile, have_syrk, sigma, tau, out_H);
-}
-
-hipError_t launch_eval_assemble(const double* state, StateLayout sl, RecLayout rl, const double* red,
-                                const double* syrk_out, int ksplit, int tile, int ntile, int have_syrk, double sigma,
-                                double tau, const double* y, const double* xbar, double* out_g, double* out_H,
-                                hipStream_t s) {
-    (void)state;
-    (void)sl;
-    (void)tile;
-    hipLaunchKernelGGL(eval_assemble_kernel, dim3(1), dim3(CTRL_THREADS), 0, s, rl, red, syrk_out, ksplit, ntile,
-                       have_syrk, sigma, tau, rl.d, y, xbar, out_g, out_H);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // Streaming scans over all balls in FP64 arithmetic: the feasibility check
@@ -1099,30 +886,51 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_WPB = SCAN_THREADS / WAVE;
 
 ScanCfg scan_config(int64_t m, int d, int num_cu) {
+    (void)d;
     ScanCfg c;
-    c.vec = (d % 2 == 0) ? 2 : 1;
-    int need = (d + c.vec * 4 - 1) / (c.vec * 4);
-    int G = 1;
-    while (G < need && G < 64) G <<= 1;
-    c.G = G;
-    c.nl = (d + G * c.vec - 1) / (G * c.vec);
-    const int bpw = WAVE / G;
-    int64_t steps = (m + bpw - 1) / bpw;
-    int64_t maxw = (int64_t)num_cu * 8;
-    int64_t w = steps < maxw ? steps : maxw;
+    // many waves with few rows each: the scan keeps little state, so a CU
+    // holds enough waves to keep HBM busy; bw is a multiple of 64 so that
+    // every lane-group width divides it
+    const int64_t maxw = (int64_t)num_cu * 32;
+    int64_t w = (m + 63) / 64;
+    if (w > maxw) w = maxw;
     if (w < 1) w = 1;
-    c.bw = ((steps + w - 1) / w) * bpw;
-    int64_t waves = (m + c.bw - 1) / c.bw;
+    c.bw = (((m + w - 1) / w) + 63) / 64 * 64;
+    const int64_t waves = (m + c.bw - 1) / c.bw;
     c.blocks = (int)((waves + SCAN_WPB - 1) / SCAN_WPB);
     c.nwaves = c.blocks * SCAN_WPB;
     return c;
 }
 
+// Lanes per row for a scan of precision dtype: 16-byte loads where the row
+// allows, about 16 bytes x 4 loads per lane.
+struct ScanLanes {
+    int G, vec, nl, nlmax;
+};
+static ScanLanes scan_lanes(int d, int dtype) {
+    ScanLanes l;
+    if (dtype != 0 && d % 4 == 0)
+        l.vec = 4;
+    else
+        l.vec = (d % 2 == 0) ? 2 : 1;
+    const int per_lane = (dtype == 0) ? 8 : 16;
+    const int need = (d + per_lane - 1) / per_lane;
+    int G = 1;
+    while (G < need && G < 64) G <<= 1;
+    l.G = G;
+    l.nl = (d + G * l.vec - 1) / (G * l.vec);
+    l.nlmax = l.nl <= 2 ? 2 : (l.nl <= 4 ? 4 : (l.nl <= 8 ? 8 : (l.nl <= 16 ? 16 : 32)));
+    return l;
+}
+
 // MODE 0: feasibility (hit: reach - r > thr; keeps max reach - r and argmax)
 // MODE 1: screening (value r - r_i - ||c - c_i||; hit: value <= thr)
 // MODE 2: FP32 preparation (writes float(c_i - x) and float(r_i); keeps max)
-template <typename T, int VEC, int MODE>
-__global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T* R, int64_t m, int d,
+// Distances are accumulated in FP64 (FP32 rows are widened exactly).  Each
+// wave streams its own rows with the next group's loads issued before the
+// current group is used.
+template <typename T, int VEC, int NLMAX, int MODE>
+__global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T* R, int64_t m, int d, int G, int nl,
                                                             const double* xdev, double r, double thr,
                                                             double* slack, float* C32, float* R32, ScanCfg cfg,
                                                             double* wmax, int64_t* warg, int64_t* wcnt,
@@ -1130,32 +938,50 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T*
     extern __shared__ double lx[];
     for (int k = threadIdx.x; k < d; k += SCAN_THREADS) lx[k] = xdev ? xdev[k] : 0.0;
     __syncthreads();
-    const int G = cfg.G, nl = cfg.nl;
-    const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    const int lane = lane_id();
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int64_t gw = (int64_t)blockIdx.x * SCAN_WPB + wid;
     const int gi = lane / G, gl = lane % G, bpw = WAVE / G;
     const int64_t wbeg = gw * cfg.bw, wend = min(m, wbeg + cfg.bw);
+    int col[NLMAX];
+    bool own[NLMAX];
+#pragma unroll
+    for (int j = 0; j < NLMAX; ++j) {
+        const int b = (j * G + gl) * VEC;
+        own[j] = (j < nl) && (b < d);
+        col[j] = own[j] ? b : 0;
+    }
     double best = -INFINITY;
     int64_t barg = INT64_MAX;
     int64_t count = 0;
-    for (int64_t b0 = wbeg; b0 < wend; b0 += bpw) {
+    struct Rows {
+        RowVec<T, VEC> c[NLMAX];
+        T r;
+    };
+    auto load = [&](int64_t b0, Rows& L) {
+        int64_t i = b0 + gi;
+        i = i < wend ? i : wend - 1;
+        L.r = R ? R[i] : T(0);
+#pragma unroll
+        for (int j = 0; j < NLMAX; ++j) L.c[j] = load_vec<T, VEC>(C + i * d + col[j]);
+    };
+    auto process = [&](int64_t b0, const Rows& L) {
         const int64_t i = b0 + gi;
         const bool act = i < wend;
         double acc = 0.0;
-        for (int j = 0; j < nl; ++j) {
-            const int base = (j * G + gl) * VEC;
-            if (act && base < d) {
-                const RowVec<T, VEC> cr = load_vec<T, VEC>(C + i * d + base);
 #pragma unroll
-                for (int q = 0; q < VEC; ++q) {
-                    const double e = (double)cr.v[q] - lx[base + q];
-                    acc += e * e;
-                    if (MODE == 2) C32[i * d + base + q] = (float)e;
-                }
+        for (int j = 0; j < NLMAX; ++j) {
+            RowVec<float, VEC> o;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                const double e = own[j] ? (double)L.c[j].v[q] - lx[col[j] + q] : 0.0;
+                acc += e * e;
+                o.v[q] = (float)e;
             }
+            if (MODE == 2 && act && own[j]) store_vec<float, VEC>(C32 + i * d + col[j], o);
         }
         const double dist = sqrt(group_sum<double>(acc, G));
-        const double ri = (R && act) ? (double)R[i] : 0.0;
+        const double ri = act ? (double)L.r : 0.0;
         double val;
         bool hit;
         if (MODE == 1) {
@@ -1176,6 +1002,16 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T*
             if (hit && gl == 0) seg[wbeg + count + __popcll(bal & ((1ull << lane) - 1ull))] = i;
             count += __popcll(bal);
         }
+    };
+    Rows A, B;
+    if (wbeg < wend) load(wbeg, A);
+    for (int64_t b0 = wbeg; b0 < wend; b0 += 2 * bpw) {
+        const bool more = b0 + bpw < wend;
+        if (more) load(b0 + bpw, B);
+        process(b0, A);
+        if (!more) break;
+        if (b0 + 2 * bpw < wend) load(b0 + 2 * bpw, A);
+        process(b0 + bpw, B);
     }
     if (MODE != 1) {
         for (int o = WAVE / 2; o > 0; o >>= 1) {
@@ -1260,31 +1096,42 @@ __global__ __launch_bounds__(256) void scan_copy(const int64_t* seg, const int64
     }
 }
 
+template <typename T, int MODE, int VEC, int NLMAX>
+static hipError_t launch_scan_v(const void* C, const void* R, int64_t m, int d, const ScanLanes& l, const double* x,
+                                double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c,
+                                double* wmax, int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s) {
+    hipLaunchKernelGGL((scan_kernel<T, VEC, NLMAX, MODE>), dim3(c.blocks), dim3(SCAN_THREADS), sizeof(double) * d, s,
+                       (const T*)C, (const T*)R, m, d, l.G, l.nl, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt,
+                       seg);
+    return hipGetLastError();
+}
+
+template <typename T, int MODE, int VEC>
+static hipError_t launch_scan_n(const void* C, const void* R, int64_t m, int d, const ScanLanes& l, const double* x,
+                                double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c,
+                                double* wmax, int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s) {
+#define MEB_SCAN_ARGS C, R, m, d, l, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, s
+    if (l.nlmax == 2) return launch_scan_v<T, MODE, VEC, 2>(MEB_SCAN_ARGS);
+    if (l.nlmax == 4) return launch_scan_v<T, MODE, VEC, 4>(MEB_SCAN_ARGS);
+    if (l.nlmax == 8) return launch_scan_v<T, MODE, VEC, 8>(MEB_SCAN_ARGS);
+    if (l.nlmax == 16) return launch_scan_v<T, MODE, VEC, 16>(MEB_SCAN_ARGS);
+    return launch_scan_v<T, MODE, VEC, 32>(MEB_SCAN_ARGS);
+}
+
 template <int MODE>
 static hipError_t launch_scan_t(const void* C, const void* R, int64_t m, int d, int dtype, const double* x,
                                 double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c,
                                 double* wmax, int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s) {
-    const size_t lds = sizeof(double) * d;
+    const ScanLanes l = scan_lanes(d, dtype);
     if (dtype == 0) {
-        if (c.vec == 2)
-            hipLaunchKernelGGL((scan_kernel<double, 2, MODE>), dim3(c.blocks), dim3(SCAN_THREADS), lds, s,
-                               (const double*)C, (const double*)R, m, d, x, r, thr, slack, C32, R32, c, wmax, warg,
-                               wcnt, seg);
-        else
-            hipLaunchKernelGGL((scan_kernel<double, 1, MODE>), dim3(c.blocks), dim3(SCAN_THREADS), lds, s,
-                               (const double*)C, (const double*)R, m, d, x, r, thr, slack, C32, R32, c, wmax, warg,
-                               wcnt, seg);
-    } else {
-        if (c.vec == 2)
-            hipLaunchKernelGGL((scan_kernel<float, 2, MODE>), dim3(c.blocks), dim3(SCAN_THREADS), lds, s,
-                               (const float*)C, (const float*)R, m, d, x, r, thr, slack, C32, R32, c, wmax, warg,
-                               wcnt, seg);
-        else
-            hipLaunchKernelGGL((scan_kernel<float, 1, MODE>), dim3(c.blocks), dim3(SCAN_THREADS), lds, s,
-                               (const float*)C, (const float*)R, m, d, x, r, thr, slack, C32, R32, c, wmax, warg,
-                               wcnt, seg);
+        if (l.vec == 2) return launch_scan_n<double, MODE, 2>(MEB_SCAN_ARGS);
+        return launch_scan_n<double, MODE, 1>(MEB_SCAN_ARGS);
     }
-    return hipGetLastError();
+    if constexpr (MODE == 2) return hipErrorInvalidValue;  // the preparation reads FP64
+    if (l.vec == 4) return launch_scan_n<float, MODE, 4>(MEB_SCAN_ARGS);
+    if (l.vec == 2) return launch_scan_n<float, MODE, 2>(MEB_SCAN_ARGS);
+    return launch_scan_n<float, MODE, 1>(MEB_SCAN_ARGS);
+#undef MEB_SCAN_ARGS
 }
 
 hipError_t launch_scan(int mode, const void* C, const void* R, int64_t m, int d, int dtype, const double* x,

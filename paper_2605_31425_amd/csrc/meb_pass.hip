@@ -23,7 +23,7 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     c.waves_per_block = WPB;
     const int bpw = WAVE / G;
     // enough waves to fill the machine, each streaming a contiguous range
-    int64_t max_waves = (int64_t)num_cu * 8;
+    int64_t max_waves = (int64_t)num_cu * 16;
     int64_t steps = (m + bpw - 1) / bpw;
     int64_t waves = steps < max_waves ? steps : max_waves;
     if (waves < 1) waves = 1;
