@@ -49,6 +49,29 @@ WORKLOADS = {
 }
 
 
+PROFILE_HBM = os.path.join(ROOT, "profiles", "pass_kernel_f32_balls_1e6_d100_hbm.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 evaluation pass from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        txt = open(PROFILE_HBM).read()
+    except OSError:
+        return None
+    m_t = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
+    m_h = re.search(r"source_sha256\(meb_device.h\): ([0-9a-f]+)", txt)
+    if not m_t or not m_h:
+        return None
+    src = os.path.join(ROOT, "paper_2605_31425_amd", "csrc", "meb_device.h")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_h.group(1):
+        return None
+    return float(m_t.group(1))
+
+
 def golden(name):
     p = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
     if os.path.exists(p):
@@ -287,7 +310,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "launches": p_launch,
             "avg_launch_us": (p_ms * 1e3 / p_launch) if p_launch else None,
             "algorithmic_bytes_per_launch": (p_bytes / p_launch) if p_launch else None,

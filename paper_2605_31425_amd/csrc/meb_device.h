@@ -260,19 +260,20 @@ __device__ __forceinline__ int arrive(int* counter) {
 
 // Sum (maximum for the three KKT maxima) of n consecutive records of len
 // doubles, `stride` apart, in index order, into out (written with coherent
-// stores when `shared_out`).  Loads are issued in batches of eight before
+// stores when `shared_out`).  Loads are issued in batches of sixteen before
 // they are combined.
 __device__ __forceinline__ void sum_records(const double* src, int n, int len, int64_t stride, int kmax,
                                             double* out, bool shared_out) {
     for (int e = threadIdx.x; e < len; e += blockDim.x) {
         const bool ismax = e >= kmax && e < kmax + 3;
         double v = ld_shared_dev(src + e);
-        for (int k0 = 1; k0 < n; k0 += 8) {
-            double x[8];
+        for (int k0 = 1; k0 < n; k0 += 16) {
+            double x[16];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) x[q] = (k0 + q < n) ? ld_shared_dev(src + (int64_t)(k0 + q) * stride + e) : 0.0;
+            for (int q = 0; q < 16; ++q)
+                x[q] = (k0 + q < n) ? ld_shared_dev(src + (int64_t)(k0 + q) * stride + e) : 0.0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
+            for (int q = 0; q < 16; ++q)
                 if (k0 + q < n) v = ismax ? fmax(v, x[q]) : v + x[q];
         }
         if (shared_out)

@@ -172,8 +172,13 @@ __device__ __forceinline__ void syrk_body(const SyrkArgs& a, int bx, int by, int
         const int r = e / SYRK_T, c = e % SYRK_T;
         const int k = I * SYRK_T + r, l = J * SYRK_T + c;
         if (k >= d || l >= d) continue;
+        double part[SYRK_KSPLIT];
+#pragma unroll
+        for (int ks = 0; ks < SYRK_KSPLIT; ++ks)
+            part[ks] = ks < a.ksplit ? ld_shared_dev(a.out + ((size_t)ks * npairs + bx) * SYRK_T * SYRK_T + e) : 0.0;
         double v = 0.0;
-        for (int ks = 0; ks < a.ksplit; ++ks) v += ld_shared_dev(a.out + ((size_t)ks * npairs + bx) * SYRK_T * SYRK_T + e);
+#pragma unroll
+        for (int ks = 0; ks < SYRK_KSPLIT; ++ks) v += part[ks];
         if (k == l) v += base + red[rl.sg];
         H[(1 + k) * n1 + 1 + l] = v;
         if (I != J) H[(1 + l) * n1 + 1 + k] = v;
