@@ -262,12 +262,13 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
-// 1 / sqrt(x) to double precision for x > 0
+// 1 / sqrt(x) to double precision for x > 0: the hardware estimate
+// (relative error about 2^-24) refined by one third-order step,
+// y (1 + e / 2 + 3 e^2 / 8) with e = 1 - x y^2.
 __device__ __forceinline__ double rsqrt_f64(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    y = y * (1.5 - 0.5 * x * y * y);
-    y = y * (1.5 - 0.5 * x * y * y);
-    return y;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
 __device__ __forceinline__ int chol_solve_lds(int n, int ld, double* M, double* b, double* rd) {
@@ -417,6 +418,290 @@ __device__ __forceinline__ int chol_solve_lds(int n, int ld, double* M, double* 
     return 0;
 }
 
+// Solve of H x = b (H symmetric positive definite) by an LDL^T
+// factorization with the matrix in registers, for n + 1 <= 128 (two rows per
+// lane) and 16 waves.  Right-looking, in panels of RCH_B columns; wave p
+// owns panel p.  A panel's owner factors it in its own registers -- pivots
+// and the multipliers of the panel's later columns are broadcast with
+// readlane, no LDS round trip and no block barrier -- and writes the unit
+// lower columns of L and the pivots D to LDS (L row-major, ldr columns).
+// After one block barrier every later panel takes the rank-RCH_B update
+// A(:, c) -= L(:, k) D_k L(c, k) from that copy: per-lane loads of L's rows
+// and uniform-address loads of the multipliers L(c, k).  A panel thus costs
+// one barrier, and the critical path is the next owner's update and
+// factorization; that wave runs at raised priority meanwhile.
+//
+// The right-hand side rides along as row n: factoring [H b; b^T *] leaves
+// l = D^-1 L^-1 b in row n of L, and x solves the unit triangular system
+// L^T x = l, which wave 0 does four rows at a time.  The last panel is
+// padded to RCH_B columns; entries of L above the diagonal are stored as 0,
+// and no result reads the padding.  A pivot that is not positive sets a
+// flag: the factorization still runs its fixed sequence of barriers and
+// the solve returns -1.
+constexpr int RCH_B = 8;        // panel width
+constexpr int RCH_WAVES = 16;   // waves of the calling block
+constexpr int RCH_MAX_N = 127;  // n + 1 rows in two halves of 64 lanes
+
+__host__ __device__ inline int rch_ldr(int n) { return (n + RCH_B - 1) / RCH_B * RCH_B + 2; }
+// doubles of LDS: L with the right-hand-side row, then D (padded)
+__host__ __device__ inline size_t rch_lds_doubles(int n) {
+    return (size_t)(n + 1) * rch_ldr(n) + (n + RCH_B - 1) / RCH_B * RCH_B;
+}
+__host__ __device__ inline bool rch_fits(int n, int threads) {
+    return n >= 1 && n <= RCH_MAX_N && threads == RCH_WAVES * WAVE;
+}
+
+// 1 / x to double precision for x > 0: the hardware estimate refined by one
+// third-order step, y (1 + e + e^2) with e = 1 - x y.
+__device__ __forceinline__ double rcp_f64(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, y, 1.0);
+    return fma(y, fma(e, e, e), y);
+}
+
+// Factor one panel held as a[j][h] = A(64 h + lane, c0 + j).  LOW: the
+// panel's columns lie below 64, so pivots sit in half 0 and both halves
+// carry rows below the diagonal; otherwise only half 1 does.  Columns at or
+// past n are padding.  Leaves the unit lower columns of L in a, lane j of
+// the wave receives the pivot D of the panel's column j, and the pivot
+// failure flag is returned.
+//
+// Latency: a readlane round trip costs several dependent FP64 operations,
+// so each column broadcasts all its entries in the panel's rows at once,
+// unscaled, and the later columns are updated with the unscaled column
+// times r / D; the column is scaled afterwards, off the path to the next
+// pivot.
+template <bool LOW>
+__device__ __forceinline__ bool rch_factor(double (&a)[RCH_B][2], int c0, int n, double* d_lane) {
+    const int lane = lane_id();
+    bool bad = false;
+    double dv = 0.0;
+#pragma unroll
+    for (int j = 0; j < RCH_B; ++j) {
+        const int c = c0 + j;
+        double r[RCH_B];
+#pragma unroll
+        for (int j2 = j; j2 < RCH_B; ++j2)
+            r[j2] = LOW ? readlane_f64(a[j][0], c0 + j2) : readlane_f64(a[j][1], c0 + j2 - 64);
+        bad |= (c < n) && !(r[j] > 0.0);
+        const double piv = c < n ? r[j] : 1.0;
+        const double id = rcp_f64(piv);
+#pragma unroll
+        for (int j2 = j + 1; j2 < RCH_B; ++j2) {
+            const double m = r[j2] * id;
+            if (LOW) a[j2][0] -= a[j][0] * m;
+            a[j2][1] -= a[j][1] * m;
+        }
+        if (LOW) a[j][0] *= id;
+        a[j][1] *= id;
+        dv = lane == j ? piv : dv;
+    }
+    *d_lane = dv;
+    return bad;
+}
+
+// Write a factored panel to L (rows 0..n; entries above the diagonal as 0).
+template <bool LOW>
+__device__ __forceinline__ void rch_store(const double (&a)[RCH_B][2], int c0, int n, double* Lr, int ldr) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int h = LOW ? 0 : 1; h < 2; ++h) {
+        const int row = 64 * h + lane;
+        if (row <= n) {
+#pragma unroll
+            for (int j = 0; j < RCH_B; j += 2) {
+                const double v0 = row >= c0 + j ? a[j][h] : 0.0;
+                const double v1 = row >= c0 + j + 1 ? a[j + 1][h] : 0.0;
+                *reinterpret_cast<double2*>(Lr + (size_t)row * ldr + c0 + j) = make_double2(v0, v1);
+            }
+        }
+    }
+}
+
+// Rank-RCH_B update of the panel at c0q by the factored panel at c0p.  Rows
+// past n read row n and columns past n are padding: both only produce values
+// that are never read.
+template <bool LOWQ>
+__device__ __forceinline__ void rch_update(double (&a)[RCH_B][2], int c0q, int c0p, int n, const double* Lr,
+                                           int ldr, const double* D) {
+    const int lane = lane_id();
+    double dp[RCH_B];
+#pragma unroll
+    for (int j = 0; j < RCH_B; j += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(D + c0p + j);
+        dp[j] = v.x;
+        dp[j + 1] = v.y;
+    }
+    double lp[2][RCH_B];  // L(row, k) D_k
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int row = 64 * h + lane;
+        const int rr = row <= n ? row : n;
+#pragma unroll
+        for (int j = 0; j < RCH_B; j += 2) {
+            double2 v = make_double2(0.0, 0.0);
+            if (LOWQ || h == 1) v = *reinterpret_cast<const double2*>(Lr + (size_t)rr * ldr + c0p + j);
+            lp[h][j] = v.x * dp[j];
+            lp[h][j + 1] = v.y * dp[j + 1];
+        }
+    }
+#pragma unroll
+    for (int jq = 0; jq < RCH_B; ++jq) {
+        const int rq = c0q + jq <= n ? c0q + jq : n;  // the column's own row
+        const double* lrow = Lr + (size_t)rq * ldr + c0p;
+        double l[RCH_B];
+#pragma unroll
+        for (int j = 0; j < RCH_B; j += 2) {
+            const double2 v = *reinterpret_cast<const double2*>(lrow + j);
+            l[j] = v.x;
+            l[j + 1] = v.y;
+        }
+#pragma unroll
+        for (int j = 0; j < RCH_B; ++j) {
+            if (LOWQ) a[jq][0] -= lp[0][j] * l[j];
+            a[jq][1] -= lp[1][j] * l[j];
+        }
+    }
+}
+
+// H: n x n symmetric, row-major, full (global or LDS); b: n entries, read
+// before x (n entries) is written, so they may alias.  Lr: LDS of
+// rch_lds_doubles(n), 16-byte aligned.  Requires rch_fits(n, blockDim.x).
+__device__ __forceinline__ int chol_solve_regs(int n, const double* H, const double* b, double* x, double* Lr) {
+    __shared__ int s_bad;
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int np = (n + RCH_B - 1) / RCH_B;
+    const int ldr = rch_ldr(n);
+    double* D = Lr + (size_t)(n + 1) * ldr;
+    const int c0 = w * RCH_B;
+    double a[RCH_B][2];
+#pragma unroll
+    for (int j = 0; j < RCH_B; ++j) {
+        // masks multiply the loaded values, so that no load is sunk into a
+        // branch of its own
+        const int c = c0 + j;
+        const int cc = c < n ? c : 0;
+        const double bc = b[cc];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = 64 * h + lane;
+            const double hv = H[(size_t)cc * n + (row < n ? row : 0)];
+            const double mh = (c < n && row < n) ? 1.0 : 0.0;
+            const double mb = (c < n && row == n) ? 1.0 : 0.0;
+            a[j][h] = hv * mh + bc * mb;
+        }
+    }
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    for (int p = 0; p < np; ++p) {
+        if (w == p) {
+            double dl;
+            bool bad;
+            if (c0 < 64) {
+                bad = rch_factor<true>(a, c0, n, &dl);
+                rch_store<true>(a, c0, n, Lr, ldr);
+            } else {
+                bad = rch_factor<false>(a, c0, n, &dl);
+                rch_store<false>(a, c0, n, Lr, ldr);
+            }
+            if (lane < RCH_B) D[c0 + lane] = dl;
+            if (bad && lane == 0) s_bad = 1;
+            __builtin_amdgcn_s_setprio(0);
+        }
+        __syncthreads();
+        if (w > p && w < np) {
+            if (w == p + 1) __builtin_amdgcn_s_setprio(2);
+            if (c0 < 64)
+                rch_update<true>(a, c0, p * RCH_B, n, Lr, ldr, D);
+            else
+                rch_update<false>(a, c0, p * RCH_B, n, Lr, ldr, D);
+        }
+    }
+    if (s_bad) return -1;
+    // L^T x = l (l in row n, L unit lower): x_k = w_k, then w_j -= L_kj x_k
+    // for j < k.  Four steps at a time: their w are broadcast together, the
+    // 4 x 4 triangle among them is solved in uniform registers, and the other
+    // lanes take one rank-4 update.  The loads of a group do not depend on
+    // the solve, so the next group's are issued before the current group is
+    // solved.  Steps past n - 1 (the top of the first group) find w = 0 and
+    // change nothing; L above the diagonal is 0, so no lane needs a mask.
+    if (w == 0) {
+        const double* yr = Lr + (size_t)n * ldr;
+        double z0 = lane < n ? yr[lane] : 0.0;
+        double z1 = lane + 64 < n ? yr[64 + lane] : 0.0;
+        double x0 = 0.0, x1 = 0.0;
+        const int i0 = lane < ldr ? lane : 0;  // stays inside a row of L for small n
+        struct Grp {
+            double s0[4], s1[4], c[4][4];  // rows k0 - u of L; c[u][v] = L(k0-u, k0-v)
+        };
+        auto load = [&](int k0, bool upper, Grp& g) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 - u, kr = k < n ? k : n - 1;
+                const double* row = Lr + (size_t)kr * ldr;
+                g.s0[u] = row[i0];
+                if (upper) g.s1[u] = row[64 + lane];  // n > 64: inside L
+#pragma unroll
+                for (int v = u + 1; v < 4; ++v) g.c[u][v] = row[k0 - v < n ? k0 - v : n - 1];
+            }
+        };
+        auto solve = [&](int k0, bool upper, const Grp& g) {
+            const int off = upper ? 64 : 0;
+            double xk[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xk[v] = readlane_f64(upper ? z1 : z0, k0 - v - off);
+#pragma unroll
+            for (int v = 1; v < 4; ++v)
+#pragma unroll
+                for (int u = 0; u < v; ++u) xk[v] -= g.c[u][v] * xk[u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (upper)
+                    x1 = lane + 64 == k0 - u ? xk[u] : x1;
+                else
+                    x0 = lane == k0 - u ? xk[u] : x0;
+                z0 -= g.s0[u] * xk[u];
+                if (upper) z1 -= g.s1[u] * xk[u];
+            }
+        };
+        Grp ga, gb;
+        if (n > 64) {
+            int k0 = 64 + ((n - 64 + 3) & ~3) - 1;
+            load(k0, true, ga);
+            for (;;) {
+                if (k0 - 4 >= 64) load(k0 - 4, true, gb);
+                solve(k0, true, ga);
+                k0 -= 4;
+                if (k0 < 64) break;
+                if (k0 - 4 >= 64) load(k0 - 4, true, ga);
+                solve(k0, true, gb);
+                k0 -= 4;
+                if (k0 < 64) break;
+            }
+        }
+        {
+            const int top = n < 64 ? n : 64;
+            int k0 = ((top + 3) & ~3) - 1;
+            load(k0, false, ga);
+            for (;;) {
+                if (k0 - 4 >= 0) load(k0 - 4, false, gb);
+                solve(k0, false, ga);
+                k0 -= 4;
+                if (k0 < 0) break;
+                if (k0 - 4 >= 0) load(k0 - 4, false, ga);
+                solve(k0, false, gb);
+                k0 -= 4;
+                if (k0 < 0) break;
+            }
+        }
+        if (lane < n) x[lane] = x0;
+        if (lane + 64 < n) x[64 + lane] = x1;
+    }
+    __syncthreads();
+    return 0;
+}
+
 // leading dimension of the LDS copy: odd, so that consecutive rows fall in
 // different LDS banks
 __host__ __device__ inline int chol_ld(int n) { return n | 1; }
@@ -475,9 +760,11 @@ constexpr int CTRL_THREADS = 1024;
 constexpr int CTRL_CHOL_LDS_MAX_N = 132;  // 1024 + 132 x 133 doubles < 160 KiB
 
 __global__ __launch_bounds__(CTRL_THREADS) void chol_solve_kernel(int n, double* A, double* b, int* info) {
-    extern __shared__ double sm[];
+    extern __shared__ __align__(16) double sm[];
     int rc;
-    if (n <= CHOL_LDS_MAX_N) {
+    if (rch_fits(n, blockDim.x)) {
+        rc = chol_solve_regs(n, A, b, b, sm);
+    } else if (n <= CHOL_LDS_MAX_N) {
         // LDS: rd (n), rhs (n), M (n x ld)
         const int ld = chol_ld(n);
         double* rd = sm;
@@ -495,7 +782,8 @@ __global__ __launch_bounds__(CTRL_THREADS) void chol_solve_kernel(int n, double*
 }
 
 hipError_t launch_chol_solve(int n, double* A, double* b, int* info, hipStream_t s) {
-    size_t lds = sizeof(double) * (size_t)(n <= CHOL_LDS_MAX_N ? (size_t)n * chol_ld(n) + 2 * n : n);
+    size_t lds = sizeof(double) * (rch_fits(n, CTRL_THREADS) ? rch_lds_doubles(n)
+                                   : (size_t)(n <= CHOL_LDS_MAX_N ? (size_t)n * chol_ld(n) + 2 * n : n));
     hipError_t ea = ensure_dynamic_lds((const void*)chol_solve_kernel, lds);
     if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(CTRL_THREADS), lds, s, n, A, b, info);
@@ -523,7 +811,7 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 }
 
 __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayout rl, const double* red) {
-    extern __shared__ double sm[];
+    extern __shared__ __align__(16) double sm[];
     double* scratch = sm;                                                    // max(CTRL_THREADS, 2 n1)
     double* lmat = sm + (CTRL_THREADS > 2 * sl.n1 ? CTRL_THREADS : 2 * sl.n1);  // Cholesky matrix when it fits
     __shared__ int s_next;                   // 0 = continue to EVAL_AT_BASE, 1 = return
@@ -726,7 +1014,14 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
     if (s_next) return;
     // Newton direction: H dir = -g, H assembled by the contraction
     int rc;
-    if (n1 <= CTRL_CHOL_LDS_MAX_N) {
+    if (rch_fits(n1, blockDim.x)) {
+        double* bv = scratch;
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
+        __syncthreads();
+        rc = chol_solve_regs(n1, H, bv, bv, lmat);
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
+        __syncthreads();
+    } else if (n1 <= CTRL_CHOL_LDS_MAX_N) {
         // LDS: scratch = [rd (n1) | rhs (n1)], lmat = H with an odd leading dimension
         const int ld = chol_ld(n1);
         double* rd = scratch;
@@ -770,7 +1065,10 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
 
 size_t control_lds_bytes(int n1) {
     size_t lds = sizeof(double) * (size_t)(CTRL_THREADS > 2 * n1 ? CTRL_THREADS : 2 * n1);
-    if (n1 <= CTRL_CHOL_LDS_MAX_N) lds += sizeof(double) * (size_t)n1 * chol_ld(n1);
+    if (rch_fits(n1, CTRL_THREADS))
+        lds += sizeof(double) * rch_lds_doubles(n1);
+    else if (n1 <= CTRL_CHOL_LDS_MAX_N)
+        lds += sizeof(double) * (size_t)n1 * chol_ld(n1);
     return lds;
 }
 

@@ -138,7 +138,7 @@ def test_prepare_f32_bit_exact(m, d):
     assert abs(L - rL) <= 1e-14 * rL
 
 
-@pytest.mark.parametrize("n", [1, 2, 11, 101, 141, 300])
+@pytest.mark.parametrize("n", [1, 2, 3, 11, 63, 64, 65, 101, 127, 128, 141, 300])
 def test_chol_solve_parity(n):
     from paper_2605_31425_amd import meb
     rng = np.random.default_rng(n)
@@ -150,6 +150,39 @@ def test_chol_solve_parity(n):
     assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
     with pytest.raises(meb.MebError):
         meb.chol_solve(dev(-np.eye(n)), dev(b))
+
+
+@pytest.mark.parametrize("n", [5, 64, 101, 127])
+def test_chol_solve_ill_conditioned_backward_error(n):
+    # condition number 1e10, like the Hessians late in a run: compare the
+    # backward error (residual), which a stable solve keeps near eps
+    from paper_2605_31425_amd import meb
+    rng = np.random.default_rng(100 + n)
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    A = (Q * np.logspace(0, 10, n)) @ Q.T
+    A = 0.5 * (A + A.T)
+    b = rng.normal(size=n)
+    y = meb.chol_solve(dev(A), dev(b)).cpu().numpy()
+    res = np.abs(A @ y - b).max()
+    assert res <= 64 * n * np.finfo(float).eps * np.abs(A).max() * np.abs(y).max()
+
+
+@pytest.mark.parametrize("n", [2, 40, 101, 127])
+def test_chol_solve_detects_late_negative_pivot(n):
+    # positive diagonal, one negative eigenvalue: the failure shows only in a
+    # later pivot
+    from paper_2605_31425_amd import meb
+    rng = np.random.default_rng(200 + n)
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    ev = np.linspace(1.0, 2.0, n)
+    ev[rng.integers(n)] = -1.0
+    A = (Q * ev) @ Q.T
+    A = 0.5 * (A + A.T)
+    assert np.all(np.diag(A) > 0) or n == 2
+    if n == 2:
+        A = np.array([[1.0, 2.0], [2.0, 1.0]])
+    with pytest.raises(meb.MebError):
+        meb.chol_solve(dev(A), dev(rng.normal(size=n)))
 
 
 def test_al_eval_deterministic_bitwise():
