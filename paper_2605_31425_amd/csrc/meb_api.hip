@@ -534,6 +534,7 @@ int Job::on_ready(hipStream_t s) {
             if (r == 0) {
                 x1 = x;
                 sigma1 = hh[S_SIGMA];
+                warm1 = rstatus == 1;
                 st.ms_phase[0] = now_ms() - t_mark;
                 t_mark = now_ms();
                 tol_red = o.tol_red * L;
@@ -566,16 +567,24 @@ int Job::on_ready(hipStream_t s) {
                 tol_red = tol_red < 0 ? 0.0 : std::max(4.0 * tol_red, 1e-6 * L);
                 return screen(s);
             }
-            // gather retained rows (FP64 data) and the FP32 multipliers as warm start
+            // gather retained rows (FP64 data) and, when the screening run
+            // converged, its multipliers and penalty as warm start; a run that
+            // stopped at the FP32 rounding floor or its iteration limit hands
+            // over only its point (multipliers zero, sigma_0)
             HIPCHK(launch_gather(C, R, nullptr, nullptr, MEB_F64, w.keep, n_red, d, w.Cred, R ? w.Rred : nullptr,
                                  nullptr, nullptr, s));
-            HIPCHK(launch_gather(nullptr, nullptr, w.U32, w.V32, MEB_F32, w.keep, n_red, d, nullptr, nullptr, w.U64,
-                                 w.V64, s));
+            if (warm1) {
+                HIPCHK(launch_gather(nullptr, nullptr, w.U32, w.V32, MEB_F32, w.keep, n_red, d, nullptr, nullptr,
+                                     w.U64, w.V64, s));
+            } else {
+                HIPCHK(launch_fill_bytes_zero(w.U64, sizeof(double) * (size_t)n_red, s));
+                HIPCHK(launch_fill_bytes_zero(w.V64, sizeof(double) * (size_t)n_red * d, s));
+            }
             st.ms_phase[1] = now_ms() - t_mark;
             xw.assign(n1, 0.0);
             xw[0] = x1[0];
             for (int k = 0; k < d; ++k) xw[1 + k] = c1[k] + x1[1 + k];
-            sigma_w = sigma1;
+            sigma_w = warm1 ? sigma1 : sigma0_raw;
             rounds = 0;
             keep_h.clear();
             keep_sorted.clear();

@@ -11,14 +11,18 @@
 // Work mapping of the evaluation pass: a group of G lanes (G a power of two,
 // 1..64) owns one ball; lane gl of the group owns elements
 // (j G + gl) VEC + q, q < VEC, j < nl of the row, so one wave-wide load
-// instruction reads 64/G consecutive rows and stays coalesced.  Every wave
+// instruction reads 64/G consecutive rows and stays coalesced; the scalar
+// work per ball then runs one ball per lane (see pass_body).  Every wave
 // streams its own contiguous range of balls, accumulates per-lane partial
-// sums in FP64, and writes one partial record; records are reduced in a
-// fixed order, so results are bitwise reproducible.
+// sums (working precision, flushed periodically into FP64), and writes one
+// partial record; records are reduced in a fixed order, so results are
+// bitwise reproducible.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <type_traits>
 
 #include "meb_internal.h"
 
@@ -67,17 +71,70 @@ __device__ __forceinline__ double swz_xor16(double v) {
 }
 
 // Sum over each aligned group of G lanes (G a power of two, wave-uniform),
-// returned in every lane of the group.  Each step adds a lane's partner
-// value, so all lanes of a group end with bitwise the same sum.
+// returned in every lane of the group.  Each step adds the value of a
+// partner lane that is paired with it symmetrically, so all lanes of a group
+// end with bitwise the same sum.  The steps run from the widest down, as a
+// switch on log2 G that falls through: scalar branches only.
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int G) {
-    if (G >= 2) v += dpp_move<DPP_XOR1>(v);
-    if (G >= 4) v += dpp_move<DPP_XOR2>(v);
-    if (G >= 8) v += dpp_move<DPP_HALF_MIRROR>(v);
-    if (G >= 16) v += dpp_move<DPP_MIRROR>(v);
-    if (G >= 32) v += swz_xor16(v);
-    if (G >= 64) v += __shfl_xor(v, 32, WAVE);
+    const int lg = __builtin_amdgcn_readfirstlane(31 - __builtin_clz(G));
+    switch (lg) {
+        case 6:
+            v += __shfl_xor(v, 32, WAVE);
+            [[fallthrough]];
+        case 5:
+            v += swz_xor16(v);
+            [[fallthrough]];
+        case 4:
+            v += dpp_move<DPP_MIRROR>(v);
+            [[fallthrough]];
+        case 3:
+            v += dpp_move<DPP_HALF_MIRROR>(v);
+            [[fallthrough]];
+        case 2:
+            v += dpp_move<DPP_XOR2>(v);
+            [[fallthrough]];
+        case 1:
+            v += dpp_move<DPP_XOR1>(v);
+            [[fallthrough]];
+        default:
+            break;
+    }
     return v;
+}
+
+// group_sum of N values at once (one switch for all of them)
+template <typename T, int N>
+__device__ __forceinline__ void group_sum_n(T (&v)[N], int G) {
+    const int lg = __builtin_amdgcn_readfirstlane(31 - __builtin_clz(G));
+    switch (lg) {
+        case 6:
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] += __shfl_xor(v[k], 32, WAVE);
+            [[fallthrough]];
+        case 5:
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] += swz_xor16(v[k]);
+            [[fallthrough]];
+        case 4:
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] += dpp_move<DPP_MIRROR>(v[k]);
+            [[fallthrough]];
+        case 3:
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] += dpp_move<DPP_HALF_MIRROR>(v[k]);
+            [[fallthrough]];
+        case 2:
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] += dpp_move<DPP_XOR2>(v[k]);
+            [[fallthrough]];
+        case 1:
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] += dpp_move<DPP_XOR1>(v[k]);
+            [[fallthrough]];
+        default:
+            break;
+    }
 }
 
 // Sum across groups: combines lanes with equal (lane % G).
@@ -120,6 +177,154 @@ template <>
 __device__ __forceinline__ double tsqrt<double>(double x) { return sqrt(x); }
 template <>
 __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
+
+// ---------------------------------------------------------------------------
+// Streaming rows into LDS (global_load_lds): each wave keeps a ring of
+// DMA_STAGES blocks of DMA_BLK bytes of its contiguous row range in flight.
+// The copies do not pass through registers, so many bytes stay in flight per
+// wave at any register count.  Completion is tracked by vmcnt, in issue order
+// among loads.  LDS accesses that may run while copies are in flight are
+// written as inline assembly: the compiler would otherwise make each of them
+// wait for every copy in flight.
+// ---------------------------------------------------------------------------
+constexpr int DMA_LOADS = 8;                  // dword copies of 256 bytes per block
+constexpr int DMA_BLK = DMA_LOADS * 256;      // bytes per block
+constexpr int DMA_STAGES = 4;                 // blocks per ring
+constexpr int DMA_RING = DMA_BLK * DMA_STAGES;
+
+// LDS byte address of a pointer into shared memory
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char*)p;
+}
+
+// wait until at most N vector-memory operations of this wave are in flight
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt holds 6 bits");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x70 | 0xF00);
+}
+
+// wait for a copy that has at least `after` vector-memory loads of this wave
+// issued after it (loads complete in issue order)
+__device__ __forceinline__ void wait_vm_after(int64_t after) {
+    if (after >= 63)
+        wait_vm<63>();
+    else if (after >= 48)
+        wait_vm<48>();
+    else if (after >= 32)
+        wait_vm<32>();
+    else if (after >= 16)
+        wait_vm<16>();
+    else if (after >= 8)
+        wait_vm<8>();
+    else
+        wait_vm<0>();
+}
+
+template <int BYTES>
+struct LdsWord;
+template <>
+struct LdsWord<4> {
+    typedef uint32_t type;
+};
+template <>
+struct LdsWord<8> {
+    typedef uint32_t type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct LdsWord<16> {
+    typedef uint32_t type __attribute__((ext_vector_type(4)));
+};
+
+// two LDS reads of BYTES each, issued back to back, then one wait
+template <int BYTES>
+__device__ __forceinline__ void lds_read2(uint32_t a0, uint32_t a1, typename LdsWord<BYTES>::type& v0,
+                                          typename LdsWord<BYTES>::type& v1) {
+    if constexpr (BYTES == 4)
+        asm volatile("ds_read_b32 %0, %2\n\tds_read_b32 %1, %3\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(v0), "=&v"(v1)
+                     : "v"(a0), "v"(a1)
+                     : "memory");
+    else if constexpr (BYTES == 8)
+        asm volatile("ds_read_b64 %0, %2\n\tds_read_b64 %1, %3\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(v0), "=&v"(v1)
+                     : "v"(a0), "v"(a1)
+                     : "memory");
+    else
+        asm volatile("ds_read_b128 %0, %2\n\tds_read_b128 %1, %3\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(v0), "=&v"(v1)
+                     : "v"(a0), "v"(a1)
+                     : "memory");
+}
+
+// eight LDS reads of BYTES each, then one wait
+template <int BYTES>
+__device__ __forceinline__ void lds_read8(const uint32_t (&a)[8], typename LdsWord<BYTES>::type (&v)[8]) {
+#define MEB_LDS_READ8(OP)                                                                                  \
+    asm volatile(OP " %0, %8\n\t" OP " %1, %9\n\t" OP " %2, %10\n\t" OP " %3, %11\n\t" OP " %4, %12\n\t" OP \
+                 " %5, %13\n\t" OP " %6, %14\n\t" OP " %7, %15\n\ts_waitcnt lgkmcnt(0)"                        \
+                 : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]), "=&v"(v[6]),       \
+                   "=&v"(v[7])                                                                                  \
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7])          \
+                 : "memory")
+    if constexpr (BYTES == 4)
+        MEB_LDS_READ8("ds_read_b32");
+    else if constexpr (BYTES == 8)
+        MEB_LDS_READ8("ds_read_b64");
+    else
+        MEB_LDS_READ8("ds_read_b128");
+#undef MEB_LDS_READ8
+}
+
+// four LDS reads of BYTES each, then one wait
+template <int BYTES>
+__device__ __forceinline__ void lds_read4w(const uint32_t (&a)[4], typename LdsWord<BYTES>::type (&v)[4]) {
+#define MEB_LDS_READ4W(OP)                                                                                 \
+    asm volatile(OP " %0, %4\n\t" OP " %1, %5\n\t" OP " %2, %6\n\t" OP " %3, %7\n\ts_waitcnt lgkmcnt(0)"      \
+                 : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3])                                          \
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3])                                                  \
+                 : "memory")
+    if constexpr (BYTES == 4)
+        MEB_LDS_READ4W("ds_read_b32");
+    else if constexpr (BYTES == 8)
+        MEB_LDS_READ4W("ds_read_b64");
+    else
+        MEB_LDS_READ4W("ds_read_b128");
+#undef MEB_LDS_READ4W
+}
+
+// four LDS reads of one T each, then one wait
+template <typename T>
+__device__ __forceinline__ void lds_read4(const uint32_t (&a)[4], T (&v)[4]) {
+#define MEB_LDS_READ4(OP)                                                                                  \
+    asm volatile(OP " %0, %4\n\t" OP " %1, %5\n\t" OP " %2, %6\n\t" OP " %3, %7\n\ts_waitcnt lgkmcnt(0)"      \
+                 : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3])                                          \
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3])                                                  \
+                 : "memory")
+    if constexpr (sizeof(T) == 4)
+        MEB_LDS_READ4("ds_read_b32");
+    else
+        MEB_LDS_READ4("ds_read_b64");
+#undef MEB_LDS_READ4
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_store1(uint32_t a, T v) {
+    if constexpr (sizeof(T) == 4)
+        asm volatile("ds_write_b32 %0, %1" : : "v"(a), "v"(v) : "memory");
+    else
+        asm volatile("ds_write_b64 %0, %1" : : "v"(a), "v"(v) : "memory");
+}
+
+template <typename T>
+__device__ __forceinline__ T lds_load1(uint32_t a) {
+    T v;
+    if constexpr (sizeof(T) == 4)
+        asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(a) : "memory");
+    else
+        asm volatile("ds_read_b64 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(a) : "memory");
+    return v;
+}
 
 // Distance of (t, s) with ||s|| = n to the second-order cone.
 template <typename T>
@@ -175,6 +380,17 @@ __device__ __forceinline__ void store_vec(T* p, const RowVec<T, VEC>& r) {
     }
 }
 
+// Square root in the projections of the evaluation pass: FP64 correctly
+// rounded; FP32 (the screening precision) the hardware instruction, within
+// about one ulp.
+template <typename T>
+__device__ __forceinline__ T psqrt(T x) {
+    if constexpr (sizeof(T) == 8)
+        return sqrt(x);
+    else
+        return __builtin_amdgcn_sqrtf(x);
+}
+
 // Per-ball projection quantities.
 template <typename T>
 struct BallProj {
@@ -188,7 +404,7 @@ struct BallProj {
 template <typename T>
 __device__ __forceinline__ BallProj<T> project(T t, T nn, T sig) {
     BallProj<T> b;
-    b.n = tsqrt<T>(nn);
+    b.n = psqrt<T>(nn);
     if (b.n <= t) {
         b.cs = 0;
         b.up = sig * t;
@@ -226,21 +442,48 @@ struct FlushPeriod<float> {
     static constexpr int steps = 64;  // FP32 partial sums cover at most 64 balls per lane
 };
 
-// LDS of the pass: y and dir in FP64 (2d), a block reduction buffer, y and
-// dir in the working precision (2d + 4), then per wave a flush scratch of
-// WAVE x FLW values.  FLW = NLMAX * VEC when a wave can hold several groups
-// (that needs at most 8 elements per lane), else 0.
+// LDS of the pass, in order: y and dir in FP64 (2d), a block reduction
+// buffer, y and dir in the working precision (2d + 4); per wave the batch
+// slots (BAT_N group sums of WAVE balls); one region that phase 1 uses for
+// the waves' row rings (instances with NLMAX <= 4, which can stream rows
+// through LDS) and phase 2 for the waves' flush scratch of WAVE x FLW values
+// (FLW = NLMAX * VEC when a wave can hold several groups, which needs at most
+// 16 elements per lane, else 0); then, with rings, per wave the radii and
+// multipliers of two batches.
+constexpr int BAT_N = 5;
 template <int VEC, int NLMAX>
 __host__ __device__ constexpr int pass_flush_width() {
-    return NLMAX * VEC <= 8 ? NLMAX * VEC : 0;
+    return NLMAX * VEC <= 16 ? NLMAX * VEC : 0;
+}
+__host__ __device__ constexpr bool pass_ring_capable(int nlmax) { return nlmax <= 4; }
+template <typename T>
+__host__ __device__ inline size_t pass_lds_head(int d) {  // in doubles, even (16-byte multiple)
+    return (2 * (size_t)d + PASS_THREADS + (sizeof(T) * (2 * (size_t)d + 4) + 7) / 8 + 1) & ~(size_t)1;
 }
 template <typename T>
-__host__ __device__ inline size_t pass_lds_head(int d) {  // in doubles
-    return 2 * (size_t)d + PASS_THREADS + (sizeof(T) * (2 * (size_t)d + 4) + 7) / 8;
+__host__ __device__ inline size_t pass_lds_bat_offset(int d) {  // bytes
+    return sizeof(double) * pass_lds_head<T>(d);
+}
+template <typename T, int VEC, int NLMAX>
+__host__ __device__ inline size_t pass_lds_ring_offset(int d) {  // bytes; also the flush scratch
+    return pass_lds_bat_offset<T>(d) + sizeof(T) * (size_t)WPB * WAVE * BAT_N;
+}
+template <typename T, int VEC, int NLMAX>
+__host__ __device__ inline size_t pass_lds_ur_offset(int d) {
+    const size_t flush = sizeof(T) * (size_t)WPB * WAVE * pass_flush_width<VEC, NLMAX>();
+    const size_t ring = pass_ring_capable(NLMAX) ? (size_t)WPB * DMA_RING : 0;
+    static_assert(!pass_ring_capable(NLMAX) || sizeof(T) * WAVE * pass_flush_width<VEC, NLMAX>() <= DMA_RING,
+                  "a wave's flush scratch fits its ring");
+    return pass_lds_ring_offset<T, VEC, NLMAX>(d) + (ring > flush ? ring : flush);
+}
+// and 16 zero bytes, read by lanes that own no part of a row
+template <typename T, int VEC, int NLMAX>
+__host__ __device__ inline size_t pass_lds_zero_offset(int d) {
+    return pass_lds_ur_offset<T, VEC, NLMAX>(d) + (pass_ring_capable(NLMAX) ? (size_t)WPB * 4 * WAVE * sizeof(T) : 0);
 }
 template <typename T, int VEC, int NLMAX>
 __host__ __device__ inline size_t pass_lds_bytes(int d) {
-    return sizeof(double) * pass_lds_head<T>(d) + sizeof(T) * (size_t)WPB * WAVE * pass_flush_width<VEC, NLMAX>();
+    return pass_lds_zero_offset<T, VEC, NLMAX>(d) + (pass_ring_capable(NLMAX) ? 16 : 0);
 }
 
 // Loads and stores of data that other blocks (possibly on other XCDs, with
@@ -316,7 +559,7 @@ __device__ __forceinline__ void reduce_block_records(const double* rec, int nrec
 template <typename T, int VEC, int NLMAX>
 struct BallLoad {
     RowVec<T, VEC> c[NLMAX];
-    T r, u;
+    T u;
 };
 
 // The evaluation pass over one wave's contiguous range of balls.
@@ -327,7 +570,7 @@ struct BallLoad {
 //         at y (the single-evaluation entry point);
 // KIND 2: multiplier update at x_j, its KKT terms, and the first evaluation of
 //         the next outer iteration at sigma_{k+1}.
-// TRL: Armijo trials per lane (ceil(NT / G) rounded up to 1, 3 or 9).
+// TRL: a launch-variant tag of the instance, not used by the body.
 //
 // Phase 1 streams the wave's balls.  With e = c_i - y and v = v_i (zero
 // unless u_i != 0), everything a ball contributes to the scalar sums follows
@@ -340,15 +583,18 @@ struct BallLoad {
 // (few, except in the first passes of a run) and accumulates the vector sums
 // and writes the updated V rows.
 //
-// Every lane of a ball's group computes the ball's scalars redundantly (the
-// group sums leave the same value in all of them); the group leader's copy
-// is the one that reaches the record.  Lanes that own no part of a load read
-// a valid address of the same row and discard it.  Phase-1 loads are
-// software-pipelined two groups deep (the loop body is unrolled over two
-// load buffers).
+// Phase 1 works in batches of WAVE balls.  The dot products of a ball are
+// spread over its group of G lanes and group-summed; the group leader puts
+// them in the ball's batch slot in LDS.  After a batch, lane l takes ball l
+// of the batch for everything per ball -- projections, the scalar sums, the
+// Armijo trials, the list entries -- so that scalar work runs on all 64
+// lanes instead of once per group.  Lanes that own no part of a load read a
+// valid address of the same row and discard it.  Phase-1 loads are
+// software-pipelined two steps deep (the loop body is unrolled over two load
+// buffers).
 template <typename T, int VEC, int NLMAX, int KIND, int TRL>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& cfg, int blk) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     const double* st = a.state;
     const int d = a.d;
     const int G = cfg.G;
@@ -372,6 +618,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
         part += dk * dk;
     }
     l_red[threadIdx.x] = part;
+    if constexpr (pass_ring_capable(NLMAX)) {
+        if (threadIdx.x < 4)
+            reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(lds) +
+                                        pass_lds_zero_offset<T, VEC, NLMAX>(d))[threadIdx.x] = 0u;
+    }
     __syncthreads();
     for (int o = PASS_THREADS / 2; o > 0; o >>= 1) {
         if (threadIdx.x < o) l_red[threadIdx.x] += l_red[threadIdx.x + o];
@@ -412,7 +663,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     T* l_cT = reinterpret_cast<T*>(l_red + PASS_THREADS);
     T* l_dT = l_cT + d;
     constexpr int FLW = pass_flush_width<VEC, NLMAX>();
-    T* l_fl = reinterpret_cast<T*>(lds + pass_lds_head<T>(d)) + wid * WAVE * FLW;
+    // a wave's flush scratch lies inside its own ring (used after its copies)
+    T* l_fl = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(lds) + pass_lds_ring_offset<T, VEC, NLMAX>(d) +
+                                   (size_t)wid * (pass_ring_capable(NLMAX) ? DMA_RING : WAVE * FLW * sizeof(T)));
     for (int k = threadIdx.x; k < d; k += PASS_THREADS) {
         l_cT[k] = (T)l_c[k];
         l_dT[k] = (T)l_dc[k];
@@ -434,27 +687,31 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     // ------------------------------------------------------------------
     // phase 1
     // ------------------------------------------------------------------
-    T sacc[A_N];  // per-ball scalars, the same in every lane of a group
-    T tacc[TRL];
-    T tam[TRL];  // 1 - eta of this lane's trials
-    bool tok[TRL];
-#pragma unroll
-    for (int r = 0; r < TRL; ++r) {
-        const int l = r * G + gl;
-        tok[r] = l < NT;
-        tam[r] = tok[r] ? T(1) - (T)a.etas[l] : T(1);
-    }
+    // (a) dot products: a step covers bpw balls, one per group of G lanes,
+    //     and the group sums go to the wave's batch slots in LDS;
+    // (b) every S = WAVE / bpw steps (a batch of WAVE balls), each lane takes
+    //     one ball of the batch for the scalar part: projections, sums,
+    //     Armijo trials, the mid and active lists.
+    // Rows reach the dot products either through the wave's LDS ring
+    // (cfg.dma: rows short enough that a step fits a ring block) or through
+    // registers, two steps deep.
+    const int S = WAVE / bpw;
+    T* l_bat = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(lds) + pass_lds_bat_offset<T>(d)) +
+               wid * (BAT_N * WAVE);
+    const uint32_t bat_addr = lds_addr(l_bat);
+    T sacc[A_N];  // this lane's balls' scalar sums
+    T tacc[NT];   // this lane's balls' Armijo trial sums
     T mx_p = 0, mx_d = 0, mx_c = 0;
     auto zero_scalars = [&]() {
 #pragma unroll
         for (int k = 0; k < A_N; ++k) sacc[k] = T(0);
 #pragma unroll
-        for (int k = 0; k < TRL; ++k) tacc[k] = T(0);
+        for (int k = 0; k < NT; ++k) tacc[k] = T(0);
     };
     auto flush_scalars = [&]() {
         T sred[A_N];
 #pragma unroll
-        for (int k = 0; k < A_N; ++k) sred[k] = group_sum<T>(leader ? sacc[k] : T(0), WAVE);
+        for (int k = 0; k < A_N; ++k) sred[k] = group_sum<T>(sacc[k], WAVE);
         if (lane == 0) {
             rec[rl.su] += (double)sred[A_SU];
             rec[rl.z1] += (double)sred[A_Z1];
@@ -469,10 +726,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
         }
         if (have_dir) {
 #pragma unroll
-            for (int r = 0; r < TRL; ++r) {
-                const T v = cross_group_sum_t<T>(tacc[r], G);
-                const int l = r * G + lane;
-                if (lane < G && l < NT) rec[rl.trial + l] += (double)v;
+            for (int l = 0; l < NT; ++l) {
+                const T v = group_sum<T>(tacc[l], WAVE);
+                if (lane == 0) rec[rl.trial + l] += (double)v;
             }
         }
         zero_scalars();
@@ -485,59 +741,97 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     int32_t* act_idx = a.act_idx + gw * cfg.bw;
     T* act_coef = static_cast<T*>(a.act_coef) + gw * cfg.bw * ACT_NC;
 
-    // rows of the group's ball; past the wave's end, its last ball again
-    auto load = [&](int64_t b0, BallLoad<T, VEC, NLMAX>& L) {
-        int64_t i = b0 + gi;
-        i = i < wend ? i : wend - 1;
-        L.r = R ? R[i] : T(0);
-        L.u = U ? U[i] : T(0);
+    // y and dir in the lane's columns (loop invariant)
+    // (zero in parts the lane does not own; the row values there are zero too)
+    RowVec<T, VEC> cyv[NLMAX], dyv[NLMAX];
 #pragma unroll
-        for (int j = 0; j < NLMAX; ++j) L.c[j] = load_vec<T, VEC>(C + i * d + col[j]);
-    };
-
-    auto process = [&](int64_t b0, BallLoad<T, VEC, NLMAX>& L) {
-        const int64_t i = b0 + gi;
-        const bool active = i < wend;
-        const T ri = L.r;
-        const T ui = active ? L.u : T(0);
-        const bool hasv = V && (ui != T(0));
-        // dot products of e = c_i - y and v with each other and with dir
-        T ee = 0, ed = 0, ev = 0, vv = 0, vd = 0;
+    for (int j = 0; j < NLMAX; ++j) {
+        cyv[j] = load_vec<T, VEC>(l_cT + col[j]);
+        dyv[j] = load_vec<T, VEC>(l_dT + col[j]);
 #pragma unroll
-        for (int j = 0; j < NLMAX; ++j) {
-            const RowVec<T, VEC> cy = load_vec<T, VEC>(l_cT + col[j]);
-            RowVec<T, VEC> dy{};
-            if (KIND != 2 && have_dir) dy = load_vec<T, VEC>(l_dT + col[j]);
-#pragma unroll
-            for (int qq = 0; qq < VEC; ++qq) {
-                const T ek = own[j] ? L.c[j].v[qq] - cy.v[qq] : T(0);
-                ee += ek * ek;
-                if (KIND != 2 && have_dir) ed += ek * dy.v[qq];
-                L.c[j].v[qq] = ek;
-            }
+        for (int q = 0; q < VEC; ++q) {
+            cyv[j].v[q] = own[j] ? cyv[j].v[q] : T(0);
+            dyv[j].v[q] = own[j] ? dyv[j].v[q] : T(0);
         }
-        if (hasv) {
+    }
+
+    // (a) the five dot products of the groups' balls of steps s .. s + NB - 1
+    // (rows in c, zero where the lane owns no part; multipliers in u), into
+    // the balls' batch slots.  NB steps share one set of group sums.
+    auto dots = [&](int64_t s, auto& c, auto& u) {
+        constexpr int NB = sizeof(u) / sizeof(u[0]);
+        T g[2 * NB];  // ||e||^2, <e, dir> per step
+        bool hv[NB];
+        bool anyv = false;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            const int64_t i = wbeg + (s + t) * bpw + gi;
+            const T ui = i < wend ? u[t] : T(0);
+            hv[t] = V && (ui != T(0));
+            anyv = anyv || hv[t];
+            T ee = 0, ed = 0;
 #pragma unroll
             for (int j = 0; j < NLMAX; ++j) {
-                const RowVec<T, VEC> vr = load_vec<T, VEC>(V + i * d + col[j]);
-                RowVec<T, VEC> dy{};
-                if (KIND != 2 && have_dir) dy = load_vec<T, VEC>(l_dT + col[j]);
 #pragma unroll
                 for (int qq = 0; qq < VEC; ++qq) {
-                    const T vk = own[j] ? vr.v[qq] : T(0);
-                    ev += L.c[j].v[qq] * vk;
-                    vv += vk * vk;
-                    if (KIND != 2 && have_dir) vd += vk * dy.v[qq];
+                    const T ek = c[t][j].v[qq] - cyv[j].v[qq];
+                    ee += ek * ek;
+                    if (KIND != 2 && have_dir) ed += ek * dyv[j].v[qq];
+                    c[t][j].v[qq] = ek;
                 }
             }
+            g[2 * t] = ee;
+            g[2 * t + 1] = ed;
         }
-        ee = group_sum<T>(ee, G);
-        if (KIND != 2 && have_dir) ed = group_sum<T>(ed, G);
-        if (__any(hasv)) {
-            ev = group_sum<T>(ev, G);
-            vv = group_sum<T>(vv, G);
-            if (KIND != 2 && have_dir) vd = group_sum<T>(vd, G);
+        group_sum_n<T, 2 * NB>(g, G);
+        T gv[3 * NB];  // <e, v>, ||v||^2, <v, dir> per step
+#pragma unroll
+        for (int k = 0; k < 3 * NB; ++k) gv[k] = T(0);
+        if (__any(anyv)) {
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+                if (hv[t]) {
+                    const int64_t i = wbeg + (s + t) * bpw + gi;
+#pragma unroll
+                    for (int j = 0; j < NLMAX; ++j) {
+                        const RowVec<T, VEC> vr = load_vec<T, VEC>(V + i * d + col[j]);
+#pragma unroll
+                        for (int qq = 0; qq < VEC; ++qq) {
+                            const T vk = own[j] ? vr.v[qq] : T(0);
+                            gv[3 * t] += c[t][j].v[qq] * vk;
+                            gv[3 * t + 1] += vk * vk;
+                            if (KIND != 2 && have_dir) gv[3 * t + 2] += vk * dyv[j].v[qq];
+                        }
+                    }
+                }
+            }
+            group_sum_n<T, 3 * NB>(gv, G);
         }
+        if (leader) {
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+                const uint32_t sa = bat_addr + (uint32_t)(((int)((s + t) % S) * bpw + gi) * (int)sizeof(T));
+                lds_store1<T>(sa + 0 * WAVE * sizeof(T), g[2 * t]);
+                lds_store1<T>(sa + 1 * WAVE * sizeof(T), g[2 * t + 1]);
+                lds_store1<T>(sa + 2 * WAVE * sizeof(T), gv[3 * t]);
+                lds_store1<T>(sa + 3 * WAVE * sizeof(T), gv[3 * t + 1]);
+                lds_store1<T>(sa + 4 * WAVE * sizeof(T), gv[3 * t + 2]);
+            }
+        }
+    };
+
+    // (b) the scalar part of ball b0 + lane, with its radius and multiplier
+    auto scalars = [&](int64_t b0, T ri, T ui_in) {
+        const int64_t i = b0 + lane;
+        const bool active = i < wend;
+        const uint32_t la = bat_addr + (uint32_t)(lane * (int)sizeof(T));
+        const T ee = lds_load1<T>(la + 0 * WAVE * sizeof(T));
+        const T ed = lds_load1<T>(la + 1 * WAVE * sizeof(T));
+        const T ev = lds_load1<T>(la + 2 * WAVE * sizeof(T));
+        const T vv = lds_load1<T>(la + 3 * WAVE * sizeof(T));
+        const T vd = lds_load1<T>(la + 4 * WAVE * sizeof(T));
+        const T ui = active ? ui_in : T(0);
+        const bool hasv = V && (ui != T(0));
         sacc[A_BYTES] += active ? row_bytes + (hasv ? es_bytes * (T)d : T(0)) : T(0);
 
         // the ball at (y, w, sigma_a): s = e + v / sigma_a
@@ -563,7 +857,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 mx_p = fmax(mx_p, cone_dist<T>(tp, tsqrt<T>(ee)));
                 mx_d = fmax(mx_d, cone_dist<T>(un, pa.gam * pa.n));
                 mx_c = fmax(mx_c, fabs(tp * un - pa.gam * es));
-                if (Uo && leader) Uo[i] = un;
+                if (Uo) Uo[i] = un;
                 sacc[A_BYTES] += (Uo ? es_bytes : T(0)) + ((Vo && un != T(0)) ? es_bytes * (T)d : T(0));
             }
             if constexpr (is_mult) {
@@ -598,24 +892,24 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
             sacc[A_NM] += (pe.cs == 2) ? T(1) : T(0);
             sacc[A_SG] += (pe.cs == 2) ? pe.gam : T(0);
         }
-        // Armijo trials along x_base + eta dir: lane gl takes trials gl, gl + G, ...
+        // Armijo trials along x_base + eta dir
         if (KIND != 2 && have_dir) {
             const T q = ed + inv_a * vd;  // <s, dir>
 #pragma unroll
-            for (int r = 0; r < TRL; ++r) {
-                const T am = tam[r];
+            for (int l = 0; l < NT; ++l) {
+                const T am = T(1) - (T)a.etas[l];  // 1 - eta
                 const T tl = te + am * dirr;
                 T n2 = nne + T(2) * am * q + am * am * dc2;
                 n2 = n2 > T(0) ? n2 : T(0);
                 const T z = project<T>(tl, n2, sig_e).Z;
-                tacc[r] += (active && tok[r]) ? z : T(0);
+                tacc[l] += active ? z : T(0);
             }
         }
         // mid list of the rank-one Hessian part: coef_i = -sigma t_i / (2 n_i^3)
         if (a.want_mid) {
             const bool is_mid = active && pe.cs == 2;
-            const unsigned long long bal = __ballot(is_mid && leader);
-            if (is_mid && leader) {
+            const unsigned long long bal = __ballot(is_mid);
+            if (is_mid) {
                 const unsigned long long lower = bal & ((1ull << lane) - 1ull);
                 const int pos = mid_count + __popcll(lower);
                 mid_idx[pos] = (int32_t)i;
@@ -628,8 +922,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
         {
             const bool wrt = want_kkt && Vo && un != T(0);
             const bool is_act = active && (pe.cs != 1 || (want_kkt && un != T(0)));
-            const unsigned long long bal = __ballot(is_act && leader);
-            if (is_act && leader) {
+            const unsigned long long bal = __ballot(is_act);
+            if (is_act) {
                 const unsigned long long lower = bal & ((1ull << lane) - 1ull);
                 const int pos = act_count + __popcll(lower);
                 act_idx[pos] = (int32_t)i;
@@ -647,20 +941,239 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
         }
     };
 
-    BallLoad<T, VEC, NLMAX> LA, LB;
-    const int64_t chunk = (int64_t)bpw * FlushPeriod<T>::steps;
-    for (int64_t c0 = wbeg; c0 < wend; c0 += chunk) {
-        const int64_t c1 = min(wend, c0 + chunk);
-        load(c0, LA);
-        for (int64_t b0 = c0; b0 < c1; b0 += 2 * bpw) {
-            const bool more = b0 + bpw < c1;
-            if (more) load(b0 + bpw, LB);
-            process(b0, LA);
-            if (!more) break;
-            if (b0 + 2 * bpw < c1) load(b0 + 2 * bpw, LA);
-            process(b0 + bpw, LB);
+    const int64_t nsteps = (wend - wbeg + bpw - 1) / bpw;
+    const int64_t nbatch = (nsteps + S - 1) / S;
+    // radius and multiplier of ball b0 + lane (clamped to the range)
+    auto fetch_ur = [&](int64_t b0, T& r, T& u) {
+        int64_t i = b0 + lane;
+        i = i < wend ? i : wend - 1;
+        r = R ? R[i] : T(0);
+        u = U ? U[i] : T(0);
+    };
+    int nbat = 0;  // batches since the last flush
+    auto after_batch = [&](int64_t bb) {
+        if (++nbat == FlushPeriod<T>::steps || bb + 1 == nbatch) {
+            flush_scalars();
+            nbat = 0;
         }
-        flush_scalars();
+    };
+    bool done = false;
+    if constexpr (pass_ring_capable(NLMAX)) {
+        if (cfg.dma) {
+            // rows through the LDS ring: stream bytes [S0, S0 + SB) of C.  The
+            // radii and multipliers of each batch are copied the same way, one
+            // batch ahead.  nld counts this wave's copies (one load each).
+            // Offsets within the wave's range fit 32 bits (the host checks).
+            const int rowB = d * (int)sizeof(T);
+            const int64_t S0 = wbeg * (int64_t)rowB, total = a.m * (int64_t)rowB;
+            const int SB = (int)(wend - wbeg) * rowB;
+            const int nblk = (SB + DMA_BLK - 1) / DMA_BLK;
+            unsigned char* ring = reinterpret_cast<unsigned char*>(lds) + pass_lds_ring_offset<T, VEC, NLMAX>(d) +
+                                  (size_t)wid * DMA_RING;
+            const uint32_t ring_addr = lds_addr(ring);
+            unsigned char* ur = reinterpret_cast<unsigned char*>(lds) + pass_lds_ur_offset<T, VEC, NLMAX>(d) +
+                                (size_t)wid * 4 * WAVE * sizeof(T);  // [parity][U, R][WAVE]
+            const uint32_t ur_addr = lds_addr(ur);
+            const uint32_t zero_addr =
+                lds_addr(reinterpret_cast<unsigned char*>(lds) + pass_lds_zero_offset<T, VEC, NLMAX>(d));
+            const char* Cb = static_cast<const char*>(a.C) + S0;
+            const int64_t Clim = total - 4 - S0;  // last dword of C, relative to S0
+            int issued = 0, landed = -1, nld = 0;
+            auto issue = [&]() {
+                const int k = issued++;
+                unsigned char* dst = ring + (k & (DMA_STAGES - 1)) * DMA_BLK;
+                const char* bk = Cb + (int64_t)k * DMA_BLK;  // wave-uniform
+                if ((int64_t)k * DMA_BLK + DMA_BLK - 4 <= Clim) {
+#pragma unroll
+                    for (int q = 0; q < DMA_LOADS; ++q)
+                        __builtin_amdgcn_global_load_lds(bk + q * 256 + lane * 4, dst + q * 256, 4, 0, 0);
+                } else {  // the block passes the end of C: clamp to its last dword
+#pragma unroll
+                    for (int q = 0; q < DMA_LOADS; ++q) {
+                        int64_t o = (int64_t)k * DMA_BLK + q * 256 + lane * 4;
+                        o = o <= Clim ? o : Clim;
+                        __builtin_amdgcn_global_load_lds(Cb + o, dst + q * 256, 4, 0, 0);
+                    }
+                }
+                nld += DMA_LOADS;
+            };
+            // relative bytes [0, end) in LDS: every block up to the one holding
+            // byte end - 1 has landed
+            auto ensure = [&](int end) {
+                const int need = (end - 1) / DMA_BLK;
+                if (landed < need) {
+                    landed = need;
+                    wait_vm_after((issued - 1 - landed) * DMA_LOADS);
+                }
+            };
+            // relative bytes below `done_to` are consumed: refill their blocks
+            auto refill = [&](int done_to) {
+                const int top = min(nblk, done_to / DMA_BLK + DMA_STAGES);
+                while (issued < top) issue();
+            };
+            // radii and multipliers of balls b0 .. b0 + WAVE - 1 into slot par
+            auto issue_ur = [&](int64_t b0, int par) {
+                const char* srcs[2] = {static_cast<const char*>(a.U), static_cast<const char*>(a.R)};
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    if (!srcs[k]) continue;
+                    unsigned char* dst = ur + (size_t)(par * 2 + k) * WAVE * sizeof(T);
+#pragma unroll
+                    for (int q = 0; q < (int)sizeof(T) / 4; ++q) {
+                        int64_t o = b0 * (int64_t)sizeof(T) + q * 256 + lane * 4;
+                        const int64_t lim = a.m * (int64_t)sizeof(T) - 4;
+                        o = o <= lim ? o : lim;
+                        __builtin_amdgcn_global_load_lds(srcs[k] + o, dst + q * 256, 4, 0, 0);
+                        ++nld;
+                    }
+                }
+            };
+            refill(0);
+            issue_ur(wbeg, 0);
+            int ur_mark = nld;  // copies issued up to the current batch's radii and multipliers
+            const int nsteps32 = (int)nsteps;
+            for (int bb = 0; bb < (int)nbatch; ++bb) {
+                const int par = bb & 1;
+                wait_vm_after(nld - ur_mark);
+                int ur_next = 0;
+                if (bb + 1 < (int)nbatch) {
+                    issue_ur(wbeg + (int64_t)(bb + 1) * WAVE, par ^ 1);
+                    ur_next = nld;
+                }
+                const uint32_t u_addr = ur_addr + (uint32_t)((par * 2 + 0) * WAVE * sizeof(T));
+                const uint32_t r_addr = ur_addr + (uint32_t)((par * 2 + 1) * WAVE * sizeof(T));
+                const int s0 = bb * S, s1 = min(nsteps32, s0 + S);
+                const int nrange = (int)(wend - wbeg);
+                // ring address of part j of the group's ball of step s
+                auto row_addr = [&](int s, int j) -> uint32_t {
+                    int il = s * bpw + gi;
+                    il = il < nrange ? il : nrange - 1;
+                    return own[j] ? ring_addr + (uint32_t)((il * rowB + col[j] * (int)sizeof(T)) & (DMA_RING - 1))
+                                  : zero_addr;
+                };
+                auto u_addr_of = [&](int s) -> uint32_t {
+                    return u_addr + (uint32_t)(((s - s0) * bpw + gi) * (int)sizeof(T));
+                };
+                // a round of NB steps: one wait, one read of all rows, one set of
+                // group sums.  Its rows must fit the ring with a block to
+                // spare: NB * bpw * rowB <= (DMA_STAGES - 1) * DMA_BLK.
+                auto round = [&](int s, auto nb_tag) {
+                    constexpr int NB = decltype(nb_tag)::value;
+                    const int end = min(SB, (s + NB) * bpw * rowB);
+                    ensure(end);
+                    RowVec<T, VEC> c[NB][NLMAX];
+                    T u[NB];
+                    static_assert(NB == 1 || NLMAX == 2, "rounds of several steps read two parts per row");
+                    if constexpr (NB == 4) {
+                        uint32_t ra[8];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            ra[2 * t] = row_addr(s + t, 0);
+                            ra[2 * t + 1] = row_addr(s + t, 1);
+                        }
+                        typename LdsWord<VEC * sizeof(T)>::type w[8];
+                        lds_read8<VEC * sizeof(T)>(ra, w);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            __builtin_memcpy(&c[t][0], &w[2 * t], sizeof(c[t][0]));
+                            __builtin_memcpy(&c[t][1], &w[2 * t + 1], sizeof(c[t][1]));
+                        }
+                        for (int t = 0; t < 4; ++t) u[t] = T(0);
+                        if (U) {
+                            const uint32_t ua[4] = {u_addr_of(s), u_addr_of(s + 1), u_addr_of(s + 2), u_addr_of(s + 3)};
+                            lds_read4<T>(ua, u);
+                        }
+                    } else if constexpr (NB == 2) {
+                        const uint32_t ra[4] = {row_addr(s, 0), row_addr(s, 1), row_addr(s + 1, 0), row_addr(s + 1, 1)};
+                        typename LdsWord<VEC * sizeof(T)>::type w[4];
+                        lds_read4w<VEC * sizeof(T)>(ra, w);
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) {
+                            __builtin_memcpy(&c[t][0], &w[2 * t], sizeof(c[t][0]));
+                            __builtin_memcpy(&c[t][1], &w[2 * t + 1], sizeof(c[t][1]));
+                        }
+                        u[0] = U ? lds_load1<T>(u_addr_of(s)) : T(0);
+                        u[1] = U ? lds_load1<T>(u_addr_of(s + 1)) : T(0);
+                    } else if constexpr (NLMAX == 2) {
+                        typename LdsWord<VEC * sizeof(T)>::type w0, w1;
+                        lds_read2<VEC * sizeof(T)>(row_addr(s, 0), row_addr(s, 1), w0, w1);
+                        __builtin_memcpy(&c[0][0], &w0, sizeof(c[0][0]));
+                        __builtin_memcpy(&c[0][1], &w1, sizeof(c[0][1]));
+                        u[0] = U ? lds_load1<T>(u_addr_of(s)) : T(0);
+                    } else {
+                        const uint32_t ra[4] = {row_addr(s, 0), row_addr(s, 1), row_addr(s, 2), row_addr(s, 3)};
+                        typename LdsWord<VEC * sizeof(T)>::type w[4];
+                        lds_read4w<VEC * sizeof(T)>(ra, w);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) __builtin_memcpy(&c[0][j], &w[j], sizeof(c[0][j]));
+                        u[0] = U ? lds_load1<T>(u_addr_of(s)) : T(0);
+                    }
+                    dots(s, c, u);
+                    refill(end);
+                };
+                const int step_bytes = bpw * rowB;
+                int s = s0;
+                if constexpr (NLMAX == 2) {
+                    if ((S & 3) == 0 && 4 * step_bytes <= (DMA_STAGES - 1) * DMA_BLK) {
+                        for (; s + 4 <= s1; s += 4) round(s, std::integral_constant<int, 4>());
+                    } else if ((S & 1) == 0 && 2 * step_bytes <= (DMA_STAGES - 1) * DMA_BLK) {
+                        for (; s + 2 <= s1; s += 2) round(s, std::integral_constant<int, 2>());
+                    }
+                }
+                for (; s < s1; ++s) round(s, std::integral_constant<int, 1>());
+                const T rb = R ? lds_load1<T>(r_addr + (uint32_t)(lane * (int)sizeof(T))) : T(0);
+                const T ub = U ? lds_load1<T>(u_addr + (uint32_t)(lane * (int)sizeof(T))) : T(0);
+                scalars(wbeg + (int64_t)bb * WAVE, rb, ub);
+                after_batch(bb);
+                if (bb + 1 < (int)nbatch) ur_mark = ur_next;
+            }
+            wait_vm<0>();  // no copy may land after the wave moves on
+            done = true;
+        }
+    }
+    if (!done) {
+        // rows of the group's ball of step s; past the wave's end, its last
+        // ball again
+        auto load = [&](int64_t s, BallLoad<T, VEC, NLMAX>& L) {
+            int64_t i = wbeg + s * bpw + gi;
+            i = i < wend ? i : wend - 1;
+            L.u = U ? U[i] : T(0);
+#pragma unroll
+            for (int j = 0; j < NLMAX; ++j) L.c[j] = load_vec<T, VEC>(C + i * d + col[j]);
+        };
+        // zero the parts of a row the lane does not own
+        auto own_only = [&](BallLoad<T, VEC, NLMAX>& L) -> BallLoad<T, VEC, NLMAX>& {
+#pragma unroll
+            for (int j = 0; j < NLMAX; ++j)
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) L.c[j].v[q] = own[j] ? L.c[j].v[q] : T(0);
+            return L;
+        };
+        auto step1 = [&](int64_t s, BallLoad<T, VEC, NLMAX>& L) {
+            RowVec<T, VEC> c[1][NLMAX];
+            own_only(L);
+#pragma unroll
+            for (int j = 0; j < NLMAX; ++j) c[0][j] = L.c[j];
+            T u[1] = {L.u};
+            dots(s, c, u);
+        };
+        BallLoad<T, VEC, NLMAX> LA, LB;
+        if (nsteps > 0) load(0, LA);
+        for (int64_t bb = 0; bb < nbatch; ++bb) {
+            const int64_t s0 = bb * S, s1 = min(nsteps, s0 + S);
+            for (int64_t s = s0; s < s1; s += 2) {
+                if (s + 1 < s1) load(s + 1, LB);
+                step1(s, LA);
+                if (s + 1 >= s1) break;
+                if (s + 2 < nsteps) load(s + 2, LA);
+                step1(s + 1, LB);
+            }
+            if (((s1 - s0) & 1) && s1 < nsteps) load(s1, LA);
+            T rb, ub;
+            fetch_ur(wbeg + bb * WAVE, rb, ub);
+            scalars(wbeg + bb * WAVE, rb, ub);
+            after_batch(bb);
+        }
     }
     {
         const T mp = wave_max_t<T>(mx_p), md = wave_max_t<T>(mx_d), mc = wave_max_t<T>(mx_c);
@@ -843,10 +1356,9 @@ static hipError_t ensure_dynamic_lds(const void* fn, size_t bytes) {
 
 
 // The template instance of the pass for (dtype, config): visits
-// f.go<T, VEC, NLMAX, TRL>().  Valid (vec, nlmax) pairs: G < 64 implies
-// nl <= ceil(8 / vec); G = 64 (one ball per wave) uses the larger nlmax, with
-// one Armijo trial per lane; narrower groups take ceil(NT / G) trials per
-// lane, rounded up to 3 or 9.
+// f.go<T, VEC, NLMAX, TRL>().  G < 64 implies nl <= ceil(16 / vec) (FP32;
+// 8 / vec for FP64); G = 64 (one ball per wave) uses the larger nlmax.  TRL
+// tags instances by group width.
 template <typename T, int VEC, int NLMAX, class F>
 static hipError_t visit_trl(const PassConfig& cfg, F& f) {
     if (cfg.G >= 16) return f.template go<T, VEC, NLMAX, 1>();
@@ -857,14 +1369,12 @@ static hipError_t visit_trl(const PassConfig& cfg, F& f) {
 template <typename T, int VEC, class F>
 static hipError_t visit_vec(const PassConfig& cfg, F& f) {
     if (cfg.G < 64) {
-        if constexpr (VEC == 4) return visit_trl<T, VEC, 2>(cfg, f);
-        if constexpr (VEC == 2) {
-            if (cfg.nlmax == 2) return visit_trl<T, VEC, 2>(cfg, f);
-            return visit_trl<T, VEC, 4>(cfg, f);
-        }
         if (cfg.nlmax == 2) return visit_trl<T, VEC, 2>(cfg, f);
         if (cfg.nlmax == 4) return visit_trl<T, VEC, 4>(cfg, f);
-        return visit_trl<T, VEC, 8>(cfg, f);
+        if constexpr (VEC == 4) return visit_trl<T, VEC, 4>(cfg, f);
+        if constexpr (VEC == 2) return visit_trl<T, VEC, 8>(cfg, f);
+        if (cfg.nlmax == 8) return visit_trl<T, VEC, 8>(cfg, f);
+        return visit_trl<T, VEC, 16>(cfg, f);
     }
     if (cfg.nlmax <= 2) return f.template go<T, VEC, 2, 1>();
     if (cfg.nlmax == 4) return f.template go<T, VEC, 4, 1>();

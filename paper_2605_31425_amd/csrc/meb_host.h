@@ -271,6 +271,7 @@ struct Job {
     double L = 0, tau_raw = 0, sigma0_raw = 0;
     std::vector<double> c1, x1, xw, xfin;
     double sigma1 = 0, sigma_w = 0;
+    bool warm1 = true;  // the screening run converged: its multipliers warm-start the refinement
     double tol_red = 0;
     int screen_tries = 0;
     int64_t n_red = 0;

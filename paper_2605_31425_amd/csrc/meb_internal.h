@@ -43,7 +43,8 @@ enum StateSlot : int {
     S_HAVE_DIR,      // 1 if dir holds a Newton direction to line-search
     S_GD,            // <g(x_base), dir>
     S_LSH,           // halvings spent on the current direction
-    S_STATUS,        // 0 running, 1 converged, 2 max iterations / stall, -1 numeric failure
+    S_STATUS,        // 0 running, 1 converged, 2 max iterations / stall, 3 rounding floor
+                     // of a low-precision run reached, -1 numeric failure
     S_KKT,           // last normalized KKT_max
     S_KKT_P0, S_KKT_P1, S_KKT_P2, S_KKT_P3, S_KKT_P4,
     S_BEST_KKT,
@@ -54,6 +55,7 @@ enum StateSlot : int {
     S_SUMK,          // rows of the rank-one Hessian contraction, summed over passes
     S_MAXK,          // largest such row count of one pass
     S_HSKIP,         // 1 if the contraction of the last pass was skipped
+    S_FLOOR,         // 1 if the last inner solve of a low-precision run stopped at the rounding floor
     S_NSCALAR = 48
 };
 
@@ -149,6 +151,7 @@ struct PassConfig {
     int blocks;   // grid size
     int64_t bw;   // balls per wave (multiple of 64 / G)
     int nwaves;   // blocks * waves_per_block
+    int dma;      // rows stream through the waves' LDS rings
 };
 
 PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu);

@@ -872,6 +872,9 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
                 if (st[S_K] >= st[S_MAX_OUTER] || st[S_STALL] >= st[S_STALL_OUTER]) {
                     st[S_STATUS] = 2.0;
                     done = 1;
+                } else if (st[S_FLOOR] != 0.0) {
+                    st[S_STATUS] = 3.0;
+                    done = 1;
                 }
             }
             if (done) {
@@ -998,13 +1001,19 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
         const double lhs = 2.0 * sN * fabs(ag / L) + sN * sN * gg;
         const double rhs = st[S_RHO] * (red[rl.dm] + tN * xx / (L * L));
         const double floor_g = 8.0 * eps * (1.0 + sgm * red[rl.rs]);
-        const bool stop = (lhs <= rhs) || (sqrt(gg) <= floor_g) || (st[S_J] >= st[S_MAX_INNER]);
+        const bool rel = lhs <= rhs;
+        const bool flo = sqrt(gg) <= floor_g;
+        const bool stop = rel || flo || (st[S_J] >= st[S_MAX_INNER]);
         if (st[S_VERBOSE] >= 2.0)
             printf("[meb]   eval x0=%.17g |g|=%.6e lhs=%.6e rhs=%.6e floor=%.3e dm=%.6e stop=%d\n", xb[0], sqrt(gg),
                    lhs, rhs, floor_g, red[rl.dm], (int)stop);
         if (stop) {
             st[S_MODE] = (double)PM_MULT;
             st[S_HAVE_DIR] = 0.0;
+            // in a low-precision (screening) run, an inner solve that ends at
+            // the rounding floor means the working precision is exhausted:
+            // the run ends after this multiplier update
+            st[S_FLOOR] = (flo && !rel && eps > 1e-10) ? 1.0 : 0.0;
             s_next = 1;
         } else {
             s_next = 0;

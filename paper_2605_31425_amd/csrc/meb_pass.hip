@@ -5,34 +5,82 @@
 
 namespace meb {
 
-PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
-    PassConfig c;
-    // 16-byte loads where the row length allows; about 8 elements per lane
-    // (G lanes per ball), 64 lanes for long rows
-    if (dtype != 0 && d % 4 == 0)
-        c.vec = 4;
-    else
-        c.vec = (d % 2 == 0) ? 2 : 1;
-    const int per_lane = (dtype == 0) ? 4 : 8;  // elements per lane
+int pass_blocks_per_cu(int dtype, const PassConfig& cfg, int d);
+
+// Lane groups for rows of d elements at per_lane elements per lane.
+static void group_shape(PassConfig& c, int d, int per_lane) {
     int need = (d + per_lane - 1) / per_lane;
     int G = 1;
     while (G < need && G < 64) G <<= 1;
     c.G = G;
     c.nl = (d + G * c.vec - 1) / (G * c.vec);
     c.nlmax = c.nl <= 2 ? 2 : (c.nl <= 4 ? 4 : (c.nl <= 8 ? 8 : 16));
+}
+
+PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
+    PassConfig c;
+    // 16-byte loads where the row length allows
+    if (dtype != 0 && d % 4 == 0)
+        c.vec = 4;
+    else
+        c.vec = (d % 2 == 0) ? 2 : 1;
+    const int esize = dtype == 0 ? 8 : 4;
+    // Rows stream through the waves' LDS rings when a step's rows fit a ring
+    // with a block to spare.  In FP32, wide lane groups pay more for group
+    // sums and per-step overhead than they save, so groups take about 16
+    // elements per lane; FP64 rows (and FP32 rows that would need more than
+    // four loads per lane) take 4 (at most four loads, and a step of at most
+    // 2 KiB).  Rows too long for the ring (64 lanes per ball) go through
+    // registers.
+    auto ring_fits = [&]() {
+        return pass_ring_capable(c.nlmax) && (int64_t)(WAVE / c.G) * d * esize <= (DMA_STAGES - 1) * DMA_BLK;
+    };
+    group_shape(c, d, dtype == 0 ? 4 : 16);
+    c.dma = ring_fits() ? 1 : 0;
+    if (!c.dma) {
+        group_shape(c, d, 4);
+        c.dma = ring_fits() ? 1 : 0;
+    }
     c.waves_per_block = WPB;
-    const int bpw = WAVE / G;
-    // enough waves to fill the machine, each streaming a contiguous range
-    int64_t max_waves = (int64_t)num_cu * 16;
+    const int bpw = WAVE / c.G;
+    // enough waves to fill the machine once, each streaming a contiguous
+    // range: as many as fit on a compute unit at once
+    int per_cu = pass_blocks_per_cu(dtype, c, d);
+    if (per_cu < 1) per_cu = 1;
+    int64_t max_waves = (int64_t)num_cu * per_cu * WPB;
+    // the in-kernel reduction takes at most RED_GROUP * SYNC_GROUPS blocks
+    if (max_waves > (int64_t)RED_GROUP * SYNC_GROUPS * WPB) max_waves = (int64_t)RED_GROUP * SYNC_GROUPS * WPB;
     int64_t steps = (m + bpw - 1) / bpw;
     int64_t waves = steps < max_waves ? steps : max_waves;
     if (waves < 1) waves = 1;
     int64_t steps_per_wave = (steps + waves - 1) / waves;
     c.bw = steps_per_wave * bpw;
+    // the ring path keeps offsets within a wave's range in 32 bits
+    if (c.bw * d * esize >= ((int64_t)1 << 30)) c.dma = 0;
     waves = (m + c.bw - 1) / c.bw;
     c.blocks = (int)((waves + WPB - 1) / WPB);
     c.nwaves = c.blocks * WPB;
     return c;
+}
+
+// resident blocks per compute unit of the instance a configuration uses
+struct Occupancy {
+    int d;
+    int n = 0;
+    template <typename T, int VEC, int NLMAX, int TRL>
+    hipError_t go() {
+        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(d);
+        const hipError_t ea = ensure_dynamic_lds((const void*)pass_kernel<T, VEC, NLMAX, TRL>, lds);
+        if (ea != hipSuccess) return ea;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)pass_kernel<T, VEC, NLMAX, TRL>,
+                                                            PASS_THREADS, lds);
+    }
+};
+
+int pass_blocks_per_cu(int dtype, const PassConfig& cfg, int d) {
+    Occupancy f{d};
+    if (visit_pass(dtype, cfg, f) != hipSuccess) return 4;
+    return f.n;
 }
 
 struct SingleLaunch {

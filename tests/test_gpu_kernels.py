@@ -17,8 +17,8 @@ from tests.gpu_common import cone_multipliers, dev, gpu, near_point
 
 pytestmark = gpu
 
-SHAPES = [(1, 3), (7, 1), (130, 2), (1000, 3), (4097, 10), (3001, 17), (2500, 64), (1999, 100), (601, 129),
-          (300, 512), (150, 1001)]
+SHAPES = [(1, 3), (7, 1), (130, 2), (1000, 3), (1500, 5), (2222, 7), (4097, 10), (3001, 17), (2500, 64),
+          (1999, 100), (601, 129), (300, 512), (150, 1001)]
 
 
 def _inst(seed, m, d, balls=True):

@@ -11,6 +11,7 @@ import os
 
 import numpy as np
 import pytest
+import torch
 
 from paper_2605_31425_amd import inputs
 from tests.gpu_common import dev, gpu
@@ -62,3 +63,21 @@ def test_workload_matches_oracle(name, mode):
     assert _max_reach(C, R, c) - r <= 1e-10 * (1 + r)
     if mode == "mixed":
         assert 0 < st["n_red"] <= C.shape[0]
+
+
+@pytest.mark.parametrize("d", [5, 7])
+def test_small_d_many_batches_modes_agree(d):
+    # short rows (several balls per lane group step); 9e6 points give every
+    # wave more than 64 batches of 64 balls, so FP32 partial sums are
+    # flushed several times per pass
+    from paper_2605_31425_amd import meb
+    m = 9_000_000
+    print(f"small d={d} m={m}", flush=True)
+    C, R = inputs.points_ball_sphere(m, d, 11 + d)
+    Cd = torch.from_numpy(C).cuda()
+    r64, c64, s64 = meb.solve(Cd, None, mode="fp64")
+    rmx, cmx, smx = meb.solve(Cd, None, mode="mixed")
+    assert s64["rc"] == 0 and smx["rc"] == 0, (s64, smx)
+    assert abs(rmx - r64) <= 1e-8 * r64, (rmx, r64)
+    for r, c in ((r64, c64), (rmx, cmx)):
+        assert _max_reach(C, None, c) - r <= 1e-10 * (1 + r)
