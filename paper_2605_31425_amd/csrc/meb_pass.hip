@@ -63,17 +63,29 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     return c;
 }
 
-// resident blocks per compute unit of the instance a configuration uses
+// resident blocks per compute unit of the instance a configuration uses: a
+// block puts one wave on each SIMD, so the count is bounded by the waves a
+// SIMD holds at the kernel's register count (512 VGPRs per lane, granule 8),
+// by LDS (160 KiB per compute unit) and by 8 waves per SIMD
 struct Occupancy {
     int d;
     int n = 0;
     template <typename T, int VEC, int NLMAX, int TRL>
     hipError_t go() {
         const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(d);
-        const hipError_t ea = ensure_dynamic_lds((const void*)pass_kernel<T, VEC, NLMAX, TRL>, lds);
+        const void* fn = (const void*)pass_kernel<T, VEC, NLMAX, TRL>;
+        const hipError_t ea = ensure_dynamic_lds(fn, lds);
         if (ea != hipSuccess) return ea;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)pass_kernel<T, VEC, NLMAX, TRL>,
-                                                            PASS_THREADS, lds);
+        hipFuncAttributes at;
+        const hipError_t eb = hipFuncGetAttributes(&at, fn);
+        if (eb != hipSuccess) return eb;
+        const int regs = at.numRegs > 0 ? (at.numRegs + 7) / 8 * 8 : 128;
+        const int by_vgpr = 512 / regs;
+        const size_t per_block = lds + at.sharedSizeBytes;
+        const int by_lds = per_block > 0 ? (int)((160 * 1024) / per_block) : 8;
+        n = by_vgpr < by_lds ? by_vgpr : by_lds;
+        if (n > 8) n = 8;
+        return hipSuccess;
     }
 };
 
