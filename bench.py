@@ -201,8 +201,8 @@ def main():
                     help="only run a plain device copy of this many GiB (3 times), to scale HBM byte counters")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
-              "(the path would shard the balls by rows across GPUs; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {a.gpus} is not supported "
+              "(the path would shard the balls by rows across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
