@@ -248,7 +248,11 @@ struct Pinned {
 };
 thread_local Pinned g_pin;
 
-// Thread-local pool of HIP events for the optional per-pass timing.
+// Thread-local pool of HIP events for the optional per-pass timing.  They
+// are read only after the stream has been synchronized, so they skip the
+// system-scope fence (cache writeback and invalidation) that a default
+// event performs when it is recorded, which would add a gap around every
+// timed launch.
 struct EventPool {
     std::vector<hipEvent_t> ev;
     ~EventPool() {
@@ -257,13 +261,36 @@ struct EventPool {
     hipEvent_t at(size_t i) {
         while (ev.size() <= i) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
             ev.push_back(e);
         }
         return ev[i];
     }
 };
 thread_local EventPool g_events;
+
+// Pinned headers and completion events of the two step batches that the
+// synchronous driver keeps in flight.
+struct PollSlots {
+    double* buf = nullptr;
+    double* hdr[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~PollSlots() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (buf) (void)hipHostFree(buf);
+    }
+    int init() {
+        if (buf) return MEB_OK;
+        for (auto& e : ev)
+            if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIPCHK(hipHostMalloc((void**)&buf, 2 * S_NSCALAR * sizeof(double), hipHostMallocDefault));
+        hdr[0] = buf;
+        hdr[1] = buf + S_NSCALAR;
+        return MEB_OK;
+    }
+};
+thread_local PollSlots g_poll;
 
 // grows a pinned int64 buffer (contents are not kept)
 int grow_pinned(int64_t*& p, size_t& cap, size_t n) {
@@ -652,23 +679,37 @@ int drive_sync(Job& j, hipStream_t s) {
     CHK(j.start(s));
     const bool prof = j.o.profile != 0;
     size_t nev = 0;
+    PollSlots& ps = g_poll;
+    CHK(ps.init());
+    int inflight = 0, head = 0;  // batches enqueued whose header is unread; the oldest one's slot
     while (!j.done()) {
         if (j.stepping()) {
-            const int batch = 4;
-            for (int b = 0; b < batch; ++b) {
-                hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (prof) {
-                    e0 = g_events.at(nev);
-                    e1 = g_events.at(nev + 1);
-                    if (!e0 || !e1) return fail(MEB_ERR_HIP, "hipEventCreate failed");
-                    nev += 2;
+            // Two batches in flight: the next batch is enqueued before the
+            // older one's header is read, so the device does not wait for the
+            // host between batches.  Steps enqueued after the run has ended
+            // leave the state unchanged.
+            while (inflight < 2) {
+                const int batch = 4;
+                for (int b = 0; b < batch; ++b) {
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    if (prof) {
+                        e0 = g_events.at(nev);
+                        e1 = g_events.at(nev + 1);
+                        if (!e0 || !e1) return fail(MEB_ERR_HIP, "hipEventCreate failed");
+                        nev += 2;
+                    }
+                    CHK(j.e->step(j.pa, true, s, e0, e1));
                 }
-                CHK(j.e->step(j.pa, true, s, e0, e1));
+                j.steps += batch;
+                const int slot = (head + inflight) & 1;
+                HIPCHK(hipMemcpyAsync(ps.hdr[slot], j.e->state, sizeof(double) * S_NSCALAR, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipEventRecord(ps.ev[slot], s));
+                ++inflight;
             }
-            j.steps += batch;
-            HIPCHK(hipMemcpyAsync(j.pin.hdr, j.e->state, sizeof(double) * S_NSCALAR, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            const double* hs = j.pin.hdr;
+            HIPCHK(hipEventSynchronize(ps.ev[head]));
+            const double* hs = ps.hdr[head];
+            head ^= 1;
+            --inflight;
             if (j.o.verbose && (int)hs[S_K] != j.last_k) {
                 j.last_k = (int)hs[S_K];
                 fprintf(stderr, "[meb] k=%d sigma=%.3e kkt=%.3e passes=%d newton=%d\n", (int)hs[S_K], hs[S_SIGMA],
@@ -677,6 +718,7 @@ int drive_sync(Job& j, hipStream_t s) {
             const bool ended = (int)hs[S_MODE] == PM_DONE;
             if (ended || j.steps > j.max_steps) {
                 if (prof) {
+                    HIPCHK(hipStreamSynchronize(s));  // the newer batch's events too
                     double ms = 0;
                     for (size_t k = 0; k + 1 < nev; k += 2) {
                         float t = 0.f;
@@ -689,6 +731,8 @@ int drive_sync(Job& j, hipStream_t s) {
                 }
                 j.forced_end = !ended;
                 CHK(j.end_run(s));
+                inflight = 0;  // the newer batch's header is not read (the run is over)
+                head = 0;
             }
         } else {
             HIPCHK(hipStreamSynchronize(s));

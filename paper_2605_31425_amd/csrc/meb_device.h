@@ -75,9 +75,14 @@ __device__ __forceinline__ double swz_xor16(double v) {
 // partner lane that is paired with it symmetrically, so all lanes of a group
 // end with bitwise the same sum.  The steps run from the widest down, as a
 // switch on log2 G that falls through: scalar branches only.
+// log2 G, wave-uniform (folded when G is a compile-time constant)
+__device__ __forceinline__ int group_lg(int G) {
+    return __builtin_constant_p(G) ? 31 - __builtin_clz(G) : __builtin_amdgcn_readfirstlane(31 - __builtin_clz(G));
+}
+
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int G) {
-    const int lg = __builtin_amdgcn_readfirstlane(31 - __builtin_clz(G));
+    const int lg = group_lg(G);
     switch (lg) {
         case 6:
             v += __shfl_xor(v, 32, WAVE);
@@ -106,7 +111,7 @@ __device__ __forceinline__ T group_sum(T v, int G) {
 // group_sum of N values at once (one switch for all of them)
 template <typename T, int N>
 __device__ __forceinline__ void group_sum_n(T (&v)[N], int G) {
-    const int lg = __builtin_amdgcn_readfirstlane(31 - __builtin_clz(G));
+    const int lg = group_lg(G);
     switch (lg) {
         case 6:
 #pragma unroll
@@ -180,7 +185,8 @@ __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
 
 // ---------------------------------------------------------------------------
 // Streaming rows into LDS (global_load_lds): each wave keeps a ring of
-// DMA_STAGES blocks of DMA_BLK bytes of its contiguous row range in flight.
+// cfg.stages blocks (4 or 8) of DMA_BLK bytes of its contiguous row range in
+// flight.
 // The copies do not pass through registers, so many bytes stay in flight per
 // wave at any register count.  Completion is tracked by vmcnt, in issue order
 // among loads.  LDS accesses that may run while copies are in flight are
@@ -189,8 +195,8 @@ __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
 // ---------------------------------------------------------------------------
 constexpr int DMA_LOADS = 8;                  // dword copies of 256 bytes per block
 constexpr int DMA_BLK = DMA_LOADS * 256;      // bytes per block
-constexpr int DMA_STAGES = 4;                 // blocks per ring
-constexpr int DMA_RING = DMA_BLK * DMA_STAGES;
+constexpr int DMA_MIN_STAGES = 4;             // blocks per ring: the layout's minimum
+constexpr int DMA_MAX_STAGES = 8;             // and maximum
 
 // LDS byte address of a pointer into shared memory
 __device__ __forceinline__ uint32_t lds_addr(const void* p) {
@@ -469,21 +475,23 @@ __host__ __device__ inline size_t pass_lds_ring_offset(int d) {  // bytes; also 
     return pass_lds_bat_offset<T>(d) + sizeof(T) * (size_t)WPB * WAVE * BAT_N;
 }
 template <typename T, int VEC, int NLMAX>
-__host__ __device__ inline size_t pass_lds_ur_offset(int d) {
+__host__ __device__ inline size_t pass_lds_ur_offset(int d, int stages) {
     const size_t flush = sizeof(T) * (size_t)WPB * WAVE * pass_flush_width<VEC, NLMAX>();
-    const size_t ring = pass_ring_capable(NLMAX) ? (size_t)WPB * DMA_RING : 0;
-    static_assert(!pass_ring_capable(NLMAX) || sizeof(T) * WAVE * pass_flush_width<VEC, NLMAX>() <= DMA_RING,
+    const size_t ring = pass_ring_capable(NLMAX) ? (size_t)WPB * stages * DMA_BLK : 0;
+    static_assert(!pass_ring_capable(NLMAX) ||
+                      sizeof(T) * WAVE * pass_flush_width<VEC, NLMAX>() <= DMA_MIN_STAGES * DMA_BLK,
                   "a wave's flush scratch fits its ring");
     return pass_lds_ring_offset<T, VEC, NLMAX>(d) + (ring > flush ? ring : flush);
 }
 // and 16 zero bytes, read by lanes that own no part of a row
 template <typename T, int VEC, int NLMAX>
-__host__ __device__ inline size_t pass_lds_zero_offset(int d) {
-    return pass_lds_ur_offset<T, VEC, NLMAX>(d) + (pass_ring_capable(NLMAX) ? (size_t)WPB * 4 * WAVE * sizeof(T) : 0);
+__host__ __device__ inline size_t pass_lds_zero_offset(int d, int stages) {
+    return pass_lds_ur_offset<T, VEC, NLMAX>(d, stages) +
+           (pass_ring_capable(NLMAX) ? (size_t)WPB * 4 * WAVE * sizeof(T) : 0);
 }
 template <typename T, int VEC, int NLMAX>
-__host__ __device__ inline size_t pass_lds_bytes(int d) {
-    return pass_lds_zero_offset<T, VEC, NLMAX>(d) + (pass_ring_capable(NLMAX) ? 16 : 0);
+__host__ __device__ inline size_t pass_lds_bytes(int d, int stages) {
+    return pass_lds_zero_offset<T, VEC, NLMAX>(d, stages) + (pass_ring_capable(NLMAX) ? 16 : 0);
 }
 
 // Loads and stores of data that other blocks (possibly on other XCDs, with
@@ -570,7 +578,9 @@ struct BallLoad {
 //         at y (the single-evaluation entry point);
 // KIND 2: multiplier update at x_j, its KKT terms, and the first evaluation of
 //         the next outer iteration at sigma_{k+1}.
-// TRL: a launch-variant tag of the instance, not used by the body.
+// TRL: the group width G when the instance is specialized for one (8, 32:
+//      G is then a compile-time constant), else a tag of its class of widths
+//      (1, 3, 9) and G comes from the configuration.
 //
 // Phase 1 streams the wave's balls.  With e = c_i - y and v = v_i (zero
 // unless u_i != 0), everything a ball contributes to the scalar sums follows
@@ -597,7 +607,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     extern __shared__ __align__(16) double lds[];
     const double* st = a.state;
     const int d = a.d;
-    const int G = cfg.G;
+    const int G = (TRL == 8 || TRL == 32) ? TRL : cfg.G;
     const int nl = cfg.nl;
     const RecLayout rl = a.rl;
     const StateLayout sl = a.sl;
@@ -621,7 +631,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     if constexpr (pass_ring_capable(NLMAX)) {
         if (threadIdx.x < 4)
             reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(lds) +
-                                        pass_lds_zero_offset<T, VEC, NLMAX>(d))[threadIdx.x] = 0u;
+                                        pass_lds_zero_offset<T, VEC, NLMAX>(d, cfg.stages))[threadIdx.x] = 0u;
     }
     __syncthreads();
     for (int o = PASS_THREADS / 2; o > 0; o >>= 1) {
@@ -665,7 +675,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     constexpr int FLW = pass_flush_width<VEC, NLMAX>();
     // a wave's flush scratch lies inside its own ring (used after its copies)
     T* l_fl = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(lds) + pass_lds_ring_offset<T, VEC, NLMAX>(d) +
-                                   (size_t)wid * (pass_ring_capable(NLMAX) ? DMA_RING : WAVE * FLW * sizeof(T)));
+                                   (size_t)wid * (pass_ring_capable(NLMAX) ? cfg.stages * DMA_BLK : WAVE * FLW * sizeof(T)));
     for (int k = threadIdx.x; k < d; k += PASS_THREADS) {
         l_cT[k] = (T)l_c[k];
         l_dT[k] = (T)l_dc[k];
@@ -968,20 +978,21 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
             const int64_t S0 = wbeg * (int64_t)rowB, total = a.m * (int64_t)rowB;
             const int SB = (int)(wend - wbeg) * rowB;
             const int nblk = (SB + DMA_BLK - 1) / DMA_BLK;
+            const int stages = cfg.stages, ring_bytes = stages * DMA_BLK;  // power-of-two ring
             unsigned char* ring = reinterpret_cast<unsigned char*>(lds) + pass_lds_ring_offset<T, VEC, NLMAX>(d) +
-                                  (size_t)wid * DMA_RING;
+                                  (size_t)wid * ring_bytes;
             const uint32_t ring_addr = lds_addr(ring);
-            unsigned char* ur = reinterpret_cast<unsigned char*>(lds) + pass_lds_ur_offset<T, VEC, NLMAX>(d) +
+            unsigned char* ur = reinterpret_cast<unsigned char*>(lds) + pass_lds_ur_offset<T, VEC, NLMAX>(d, stages) +
                                 (size_t)wid * 4 * WAVE * sizeof(T);  // [parity][U, R][WAVE]
             const uint32_t ur_addr = lds_addr(ur);
             const uint32_t zero_addr =
-                lds_addr(reinterpret_cast<unsigned char*>(lds) + pass_lds_zero_offset<T, VEC, NLMAX>(d));
+                lds_addr(reinterpret_cast<unsigned char*>(lds) + pass_lds_zero_offset<T, VEC, NLMAX>(d, stages));
             const char* Cb = static_cast<const char*>(a.C) + S0;
             const int64_t Clim = total - 4 - S0;  // last dword of C, relative to S0
             int issued = 0, landed = -1, nld = 0;
             auto issue = [&]() {
                 const int k = issued++;
-                unsigned char* dst = ring + (k & (DMA_STAGES - 1)) * DMA_BLK;
+                unsigned char* dst = ring + (k & (stages - 1)) * DMA_BLK;
                 const char* bk = Cb + (int64_t)k * DMA_BLK;  // wave-uniform
                 if ((int64_t)k * DMA_BLK + DMA_BLK - 4 <= Clim) {
 #pragma unroll
@@ -1008,7 +1019,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
             };
             // relative bytes below `done_to` are consumed: refill their blocks
             auto refill = [&](int done_to) {
-                const int top = min(nblk, done_to / DMA_BLK + DMA_STAGES);
+                const int top = min(nblk, done_to / DMA_BLK + stages);
                 while (issued < top) issue();
             };
             // radii and multipliers of balls b0 .. b0 + WAVE - 1 into slot par
@@ -1048,7 +1059,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 auto row_addr = [&](int s, int j) -> uint32_t {
                     int il = s * bpw + gi;
                     il = il < nrange ? il : nrange - 1;
-                    return own[j] ? ring_addr + (uint32_t)((il * rowB + col[j] * (int)sizeof(T)) & (DMA_RING - 1))
+                    return own[j] ? ring_addr + (uint32_t)((il * rowB + col[j] * (int)sizeof(T)) & (ring_bytes - 1))
                                   : zero_addr;
                 };
                 auto u_addr_of = [&](int s) -> uint32_t {
@@ -1056,7 +1067,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 };
                 // a round of NB steps: one wait, one read of all rows, one set of
                 // group sums.  Its rows must fit the ring with a block to
-                // spare: NB * bpw * rowB <= (DMA_STAGES - 1) * DMA_BLK.
+                // spare: NB * bpw * rowB <= (stages - 1) * DMA_BLK.
                 auto round = [&](int s, auto nb_tag) {
                     constexpr int NB = decltype(nb_tag)::value;
                     const int end = min(SB, (s + NB) * bpw * rowB);
@@ -1114,9 +1125,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 const int step_bytes = bpw * rowB;
                 int s = s0;
                 if constexpr (NLMAX == 2) {
-                    if ((S & 3) == 0 && 4 * step_bytes <= (DMA_STAGES - 1) * DMA_BLK) {
+                    if ((S & 3) == 0 && 4 * step_bytes <= (stages - 1) * DMA_BLK) {
                         for (; s + 4 <= s1; s += 4) round(s, std::integral_constant<int, 4>());
-                    } else if ((S & 1) == 0 && 2 * step_bytes <= (DMA_STAGES - 1) * DMA_BLK) {
+                    } else if ((S & 1) == 0 && 2 * step_bytes <= (stages - 1) * DMA_BLK) {
                         for (; s + 2 <= s1; s += 2) round(s, std::integral_constant<int, 2>());
                     }
                 }
@@ -1198,14 +1209,19 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 for (int q = 0; q < VEC; ++q) vsv[j][q] = vsw[j][q] = vkv[j][q] = T(0);
         };
         // sum over the groups of lanes with equal gl (through the wave's LDS
-        // scratch when a wave holds several groups; program order within the
-        // wave orders the LDS writes before the reads)
+        // scratch when a wave holds several groups).  The wave's LDS accesses
+        // complete in issue order; the compiler barriers keep that order in
+        // the code, since a lane reads what other lanes wrote (addresses the
+        // compiler may see as disjoint from the lane's own writes when G is a
+        // compile-time constant).
         auto flush_vec = [&](T (&A)[NLMAX][VEC], int off) {
             if (G < WAVE && FLW > 0) {
+                asm volatile("" ::: "memory");  // earlier reads of the scratch stay before these writes
 #pragma unroll
                 for (int j = 0; j < NLMAX; ++j)
 #pragma unroll
                     for (int q = 0; q < VEC; ++q) l_fl[(j * VEC + q) * WAVE + lane] = A[j][q];
+                asm volatile("" ::: "memory");  // the writes stay before the reads
                 if (lane < G) {
 #pragma unroll
                     for (int j = 0; j < NLMAX; ++j) {
@@ -1358,9 +1374,16 @@ static hipError_t ensure_dynamic_lds(const void* fn, size_t bytes) {
 // The template instance of the pass for (dtype, config): visits
 // f.go<T, VEC, NLMAX, TRL>().  G < 64 implies nl <= ceil(16 / vec) (FP32;
 // 8 / vec for FP64); G = 64 (one ball per wave) uses the larger nlmax.  TRL
-// tags instances by group width.
+// tags instances by group width; the group shapes of rows of about a hundred
+// elements (FP32: 8 lanes of four 4-wide parts, FP64: 32 lanes of two 2-wide
+// parts) have instances of their own with G fixed at compile time, used when
+// cfg.spec allows.
 template <typename T, int VEC, int NLMAX, class F>
 static hipError_t visit_trl(const PassConfig& cfg, F& f) {
+    if constexpr (std::is_same<T, float>::value && VEC == 4 && NLMAX == 4)
+        if (cfg.spec && cfg.G == 8) return f.template go<T, VEC, NLMAX, 8>();
+    if constexpr (std::is_same<T, double>::value && VEC == 2 && NLMAX == 2)
+        if (cfg.spec && cfg.G == 32) return f.template go<T, VEC, NLMAX, 32>();
     if (cfg.G >= 16) return f.template go<T, VEC, NLMAX, 1>();
     if (cfg.G >= 4) return f.template go<T, VEC, NLMAX, 3>();
     return f.template go<T, VEC, NLMAX, 9>();

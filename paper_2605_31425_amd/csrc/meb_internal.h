@@ -152,6 +152,8 @@ struct PassConfig {
     int64_t bw;   // balls per wave (multiple of 64 / G)
     int nwaves;   // blocks * waves_per_block
     int dma;      // rows stream through the waves' LDS rings
+    int stages;   // ring blocks per wave (DMA_MIN_STAGES or DMA_MAX_STAGES)
+    int spec;     // the instance specialized for this group width may be used
 };
 
 PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu);
@@ -241,8 +243,8 @@ struct TickList {
 // takes one launch per template instance among the items; the other two
 // kernels one launch per TICK_MAX items.
 // The pass of a group of items that share one template instance.
-hipError_t launch_pass_group(const BatchItem* dtab, const TickList& L, int blocks, int max_d, int dtype,
-                             const PassConfig& cfg, hipStream_t s);
+hipError_t launch_pass_group(const BatchItem* dtab, const TickList& L, int blocks, int max_d, int max_stages,
+                             int dtype, const PassConfig& cfg, hipStream_t s);
 hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* slots, int n, hipStream_t s);
 int pass_variant(int dtype, const PassConfig& cfg);
 size_t control_lds_bytes(int n1);

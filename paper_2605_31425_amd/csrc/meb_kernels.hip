@@ -1145,16 +1145,17 @@ hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* 
             for (int k = 0; k < cn; ++k) {
                 if (done[k]) continue;
                 int grp[TICK_MAX];
-                int ng = 0, max_d = 0;
+                int ng = 0, max_d = 0, max_stages = 0;
                 for (int q = k; q < cn; ++q)
                     if (!done[q] && ids[q] == ids[k]) {
                         grp[ng++] = sl[q];
                         done[q] = true;
                         if (htab[sl[q]].pa.d > max_d) max_d = htab[sl[q]].pa.d;
+                        if (htab[sl[q]].pc.stages > max_stages) max_stages = htab[sl[q]].pc.stages;
                     }
                 const int blocks = make_list(htab, grp, ng, L, [](const BatchItem& it) { return it.pc.blocks; });
-                const hipError_t e =
-                    launch_pass_group(dtab, L, blocks, max_d, htab[grp[0]].pa.dtype, htab[grp[0]].pc, s);
+                const hipError_t e = launch_pass_group(dtab, L, blocks, max_d, max_stages, htab[grp[0]].pa.dtype,
+                                                       htab[grp[0]].pc, s);
                 if (e != hipSuccess) return e;
             }
         }

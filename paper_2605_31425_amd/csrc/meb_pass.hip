@@ -33,7 +33,7 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     // 2 KiB).  Rows too long for the ring (64 lanes per ball) go through
     // registers.
     auto ring_fits = [&]() {
-        return pass_ring_capable(c.nlmax) && (int64_t)(WAVE / c.G) * d * esize <= (DMA_STAGES - 1) * DMA_BLK;
+        return pass_ring_capable(c.nlmax) && (int64_t)(WAVE / c.G) * d * esize <= (DMA_MIN_STAGES - 1) * DMA_BLK;
     };
     group_shape(c, d, dtype == 0 ? 4 : 16);
     c.dma = ring_fits() ? 1 : 0;
@@ -44,35 +44,61 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     c.waves_per_block = WPB;
     const int bpw = WAVE / c.G;
     // enough waves to fill the machine once, each streaming a contiguous
-    // range: as many as fit on a compute unit at once
-    int per_cu = pass_blocks_per_cu(dtype, c, d);
-    if (per_cu < 1) per_cu = 1;
-    int64_t max_waves = (int64_t)num_cu * per_cu * WPB;
-    // the in-kernel reduction takes at most RED_GROUP * SYNC_GROUPS blocks
-    if (max_waves > (int64_t)RED_GROUP * SYNC_GROUPS * WPB) max_waves = (int64_t)RED_GROUP * SYNC_GROUPS * WPB;
-    int64_t steps = (m + bpw - 1) / bpw;
+    // range: as many as fit on a compute unit at once (for the instance the
+    // configuration selects).  The deeper ring (more bytes in flight per
+    // wave) is taken when the LDS it needs does not lower that count, i.e.
+    // when registers bound the occupancy anyway.
+    auto resident_waves = [&]() -> int64_t {
+        c.stages = DMA_MIN_STAGES;
+        int per_cu = pass_blocks_per_cu(dtype, c, d);
+        if (c.dma) {
+            PassConfig deep = c;
+            deep.stages = DMA_MAX_STAGES;
+            if (pass_blocks_per_cu(dtype, deep, d) >= per_cu) c.stages = DMA_MAX_STAGES;
+        }
+        if (per_cu < 1) per_cu = 1;
+        int64_t mw = (int64_t)num_cu * per_cu * WPB;
+        // the in-kernel reduction takes at most RED_GROUP * SYNC_GROUPS blocks
+        if (mw > (int64_t)RED_GROUP * SYNC_GROUPS * WPB) mw = (int64_t)RED_GROUP * SYNC_GROUPS * WPB;
+        return mw;
+    };
+    c.spec = 0;
+    int64_t max_waves = resident_waves();
+    const int64_t steps = (m + bpw - 1) / bpw;
+    // The instances specialized for one group width run fewer instructions
+    // per step.  The FP64 one needs more than 256 registers per lane, which
+    // halves the waves a SIMD holds; it is taken only for short passes (at
+    // most eight steps per wave at full occupancy), which are bound by the
+    // latency of their few steps rather than by occupancy.
+    c.spec = (dtype != 0 || steps <= 8 * max_waves) ? 1 : 0;
+    if (c.spec) max_waves = resident_waves();
     int64_t waves = steps < max_waves ? steps : max_waves;
     if (waves < 1) waves = 1;
     int64_t steps_per_wave = (steps + waves - 1) / waves;
     c.bw = steps_per_wave * bpw;
     // the ring path keeps offsets within a wave's range in 32 bits
-    if (c.bw * d * esize >= ((int64_t)1 << 30)) c.dma = 0;
+    if (c.bw * d * esize >= ((int64_t)1 << 30)) {
+        c.dma = 0;
+        c.stages = DMA_MIN_STAGES;
+    }
     waves = (m + c.bw - 1) / c.bw;
     c.blocks = (int)((waves + WPB - 1) / WPB);
     c.nwaves = c.blocks * WPB;
     return c;
 }
 
-// resident blocks per compute unit of the instance a configuration uses: a
+// resident blocks per compute unit of the instance a configuration uses (at
+// its ring depth): a
 // block puts one wave on each SIMD, so the count is bounded by the waves a
 // SIMD holds at the kernel's register count (512 VGPRs per lane, granule 8),
 // by LDS (160 KiB per compute unit) and by 8 waves per SIMD
 struct Occupancy {
     int d;
+    int stages;
     int n = 0;
     template <typename T, int VEC, int NLMAX, int TRL>
     hipError_t go() {
-        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(d);
+        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(d, stages);
         const void* fn = (const void*)pass_kernel<T, VEC, NLMAX, TRL>;
         const hipError_t ea = ensure_dynamic_lds(fn, lds);
         if (ea != hipSuccess) return ea;
@@ -90,7 +116,7 @@ struct Occupancy {
 };
 
 int pass_blocks_per_cu(int dtype, const PassConfig& cfg, int d) {
-    Occupancy f{d};
+    Occupancy f{d, cfg.stages};
     if (visit_pass(dtype, cfg, f) != hipSuccess) return 4;
     return f.n;
 }
@@ -101,7 +127,7 @@ struct SingleLaunch {
     hipStream_t s;
     template <typename T, int VEC, int NLMAX, int TRL>
     hipError_t go() {
-        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(a.d);
+        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(a.d, cfg.stages);
         const hipError_t ea = ensure_dynamic_lds((const void*)pass_kernel<T, VEC, NLMAX, TRL>, lds);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL((pass_kernel<T, VEC, NLMAX, TRL>), dim3(cfg.blocks), dim3(PASS_THREADS), lds, s, a, cfg);
@@ -114,7 +140,7 @@ struct VariantId {
     int id = -1;
     template <typename T, int VEC, int NLMAX, int TRL>
     hipError_t go() {
-        id = (sizeof(T) == 8 ? 100000 : 0) + VEC * 1000 + NLMAX * 10 + TRL;
+        id = (sizeof(T) == 8 ? 1000000 : 0) + VEC * 10000 + NLMAX * 100 + TRL;
         return hipSuccess;
     }
 };

@@ -9,10 +9,11 @@ struct BatchPassLaunch {
     const TickList& L;
     int blocks;
     int max_d;
+    int max_stages;
     hipStream_t s;
     template <typename T, int VEC, int NLMAX, int TRL>
     hipError_t go() {
-        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(max_d);
+        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(max_d, max_stages);
         const hipError_t ea = ensure_dynamic_lds((const void*)pass_batch_kernel<T, VEC, NLMAX, TRL>, lds);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL((pass_batch_kernel<T, VEC, NLMAX, TRL>), dim3(blocks), dim3(PASS_THREADS), lds, s, tab, L);
@@ -20,9 +21,9 @@ struct BatchPassLaunch {
     }
 };
 
-hipError_t launch_pass_group(const BatchItem* dtab, const TickList& L, int blocks, int max_d, int dtype,
-                             const PassConfig& cfg, hipStream_t s) {
-    BatchPassLaunch f{dtab, L, blocks, max_d, s};
+hipError_t launch_pass_group(const BatchItem* dtab, const TickList& L, int blocks, int max_d, int max_stages,
+                             int dtype, const PassConfig& cfg, hipStream_t s) {
+    BatchPassLaunch f{dtab, L, blocks, max_d, max_stages, s};
     return visit_pass(dtype, cfg, f);
 }
 

@@ -10,7 +10,7 @@ struct EvalLaunch {
     hipStream_t s;
     template <typename T, int VEC, int NLMAX, int TRL>
     hipError_t go() {
-        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(a.d);
+        const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(a.d, cfg.stages);
         const hipError_t ea = ensure_dynamic_lds((const void*)pass_eval_kernel<T, VEC, NLMAX, TRL>, lds);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL((pass_eval_kernel<T, VEC, NLMAX, TRL>), dim3(cfg.blocks), dim3(PASS_THREADS), lds, s, a,
