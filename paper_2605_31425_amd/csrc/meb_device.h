@@ -751,17 +751,32 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     int32_t* act_idx = a.act_idx + gw * cfg.bw;
     T* act_coef = static_cast<T*>(a.act_coef) + gw * cfg.bw * ACT_NC;
 
-    // y and dir in the lane's columns (loop invariant)
-    // (zero in parts the lane does not own; the row values there are zero too)
-    RowVec<T, VEC> cyv[NLMAX], dyv[NLMAX];
+    // y and dir in the lane's columns (zero in parts the lane does not own;
+    // the row values there are zero too).  Instances that stream rows
+    // through LDS read them from LDS at every step (the zero slot where the
+    // lane owns no part), which keeps 2 NLMAX VEC registers free across the
+    // scalar part; the others keep them in registers.
+    constexpr bool YLDS = pass_ring_capable(NLMAX);
+    RowVec<T, VEC> cyv[YLDS ? 1 : NLMAX], dyv[YLDS ? 1 : NLMAX];
+    uint32_t ya[YLDS ? NLMAX : 1], da[YLDS ? NLMAX : 1];
+    if constexpr (YLDS) {
+        const uint32_t zero_slot =
+            lds_addr(reinterpret_cast<unsigned char*>(lds) + pass_lds_zero_offset<T, VEC, NLMAX>(d, cfg.stages));
 #pragma unroll
-    for (int j = 0; j < NLMAX; ++j) {
-        cyv[j] = load_vec<T, VEC>(l_cT + col[j]);
-        dyv[j] = load_vec<T, VEC>(l_dT + col[j]);
+        for (int j = 0; j < NLMAX; ++j) {
+            ya[j] = own[j] ? lds_addr(l_cT + col[j]) : zero_slot;
+            da[j] = own[j] ? lds_addr(l_dT + col[j]) : zero_slot;
+        }
+    } else {
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) {
-            cyv[j].v[q] = own[j] ? cyv[j].v[q] : T(0);
-            dyv[j].v[q] = own[j] ? dyv[j].v[q] : T(0);
+        for (int j = 0; j < NLMAX; ++j) {
+            cyv[j] = load_vec<T, VEC>(l_cT + col[j]);
+            dyv[j] = load_vec<T, VEC>(l_dT + col[j]);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                cyv[j].v[q] = own[j] ? cyv[j].v[q] : T(0);
+                dyv[j].v[q] = own[j] ? dyv[j].v[q] : T(0);
+            }
         }
     }
 
@@ -770,6 +785,36 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     // the balls' batch slots.  NB steps share one set of group sums.
     auto dots = [&](int64_t s, auto& c, auto& u) {
         constexpr int NB = sizeof(u) / sizeof(u[0]);
+        RowVec<T, VEC> cy[NLMAX], dy[NLMAX];
+        if constexpr (YLDS) {
+            typedef typename LdsWord<VEC * sizeof(T)>::type W;
+            if constexpr (NLMAX == 4) {
+                const uint32_t ad[8] = {ya[0], ya[1], ya[2], ya[3], da[0], da[1], da[2], da[3]};
+                W w[8];
+                lds_read8<VEC * sizeof(T)>(ad, w);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    __builtin_memcpy(&cy[j], &w[j], sizeof(cy[j]));
+                    __builtin_memcpy(&dy[j], &w[4 + j], sizeof(dy[j]));
+                }
+            } else {
+                static_assert(NLMAX == 2, "ring instances have two or four parts per row");
+                const uint32_t ad[4] = {ya[0], ya[1], da[0], da[1]};
+                W w[4];
+                lds_read4w<VEC * sizeof(T)>(ad, w);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    __builtin_memcpy(&cy[j], &w[j], sizeof(cy[j]));
+                    __builtin_memcpy(&dy[j], &w[2 + j], sizeof(dy[j]));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NLMAX; ++j) {
+                cy[j] = cyv[j];
+                dy[j] = dyv[j];
+            }
+        }
         T g[2 * NB];  // ||e||^2, <e, dir> per step
         bool hv[NB];
         bool anyv = false;
@@ -784,9 +829,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
             for (int j = 0; j < NLMAX; ++j) {
 #pragma unroll
                 for (int qq = 0; qq < VEC; ++qq) {
-                    const T ek = c[t][j].v[qq] - cyv[j].v[qq];
+                    const T ek = c[t][j].v[qq] - cy[j].v[qq];
                     ee += ek * ek;
-                    if (KIND != 2 && have_dir) ed += ek * dyv[j].v[qq];
+                    if (KIND != 2 && have_dir) ed += ek * dy[j].v[qq];
                     c[t][j].v[qq] = ek;
                 }
             }
@@ -810,7 +855,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                             const T vk = own[j] ? vr.v[qq] : T(0);
                             gv[3 * t] += c[t][j].v[qq] * vk;
                             gv[3 * t + 1] += vk * vk;
-                            if (KIND != 2 && have_dir) gv[3 * t + 2] += vk * dyv[j].v[qq];
+                            if (KIND != 2 && have_dir) gv[3 * t + 2] += vk * dy[j].v[qq];
                         }
                     }
                 }

@@ -62,16 +62,22 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
         if (mw > (int64_t)RED_GROUP * SYNC_GROUPS * WPB) mw = (int64_t)RED_GROUP * SYNC_GROUPS * WPB;
         return mw;
     };
-    c.spec = 0;
-    int64_t max_waves = resident_waves();
     const int64_t steps = (m + bpw - 1) / bpw;
     // The instances specialized for one group width run fewer instructions
-    // per step.  The FP64 one needs more than 256 registers per lane, which
-    // halves the waves a SIMD holds; it is taken only for short passes (at
-    // most eight steps per wave at full occupancy), which are bound by the
-    // latency of their few steps rather than by occupancy.
-    c.spec = (dtype != 0 || steps <= 8 * max_waves) ? 1 : 0;
-    if (c.spec) max_waves = resident_waves();
+    // per step.  One is taken unless it holds fewer waves per compute unit
+    // than the generic instance (more registers) and the pass is long (more
+    // than eight steps per wave at the generic instance's occupancy): short
+    // passes are bound by the latency of their few steps, not by occupancy.
+    c.spec = 0;
+    const int64_t mw_generic = resident_waves();
+    const int stages_generic = c.stages;
+    c.spec = 1;
+    int64_t max_waves = resident_waves();
+    if (max_waves < mw_generic && steps > 8 * mw_generic) {
+        c.spec = 0;
+        c.stages = stages_generic;
+        max_waves = mw_generic;
+    }
     int64_t waves = steps < max_waves ? steps : max_waves;
     if (waves < 1) waves = 1;
     int64_t steps_per_wave = (steps + waves - 1) / waves;
