@@ -797,17 +797,34 @@ hipError_t launch_chol_solve(int n, double* A, double* b, int* info, hipStream_t
 // solver).  Writes S_MODE = PM_DONE when the run ends.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double block_sum(double v, double* scratch) {
-    __syncthreads();
-    scratch[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) scratch[threadIdx.x] += scratch[threadIdx.x + o];
-        __syncthreads();
+// Sums of N values over the block, returned in every thread: each wave sums
+// its lanes (symmetric cross-lane steps, so every lane holds the same sum),
+// then every thread adds the wave sums from LDS in wave order.  The order is
+// fixed, so the result is reproducible; three barriers for all N values.
+template <int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], double* scratch) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = group_sum<double>(v[k], WAVE);
+    __syncthreads();  // earlier readers of the scratch are done
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) scratch[w * N + k] = v[k];
     }
-    const double r = scratch[0];
     __syncthreads();
-    return r;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double t = 0.0;
+        for (int q = 0; q < nw; ++q) t += scratch[q * N + k];
+        v[k] = t;
+    }
+    __syncthreads();  // the scratch may be rewritten after this
+}
+
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+    double a[1] = {v};
+    block_sum_n<1>(a, scratch);
+    return a[0];
 }
 
 __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayout rl, const double* red) {
@@ -913,9 +930,9 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
             pdx += dir[k] * dx;
             pxx += dx * dx;
         }
-        const double dd = block_sum(pdd, scratch);
-        const double dxd = block_sum(pdx, scratch);
-        const double xx = block_sum(pxx, scratch);
+        double sums[3] = {pdd, pdx, pxx};
+        block_sum_n<3>(sums, scratch);
+        const double dd = sums[0], dxd = sums[1], xx = sums[2];
         if (threadIdx.x == 0) {
             const double z0 = red[rl.trial + NT - 1];
             const double psi0 = xb[0] + 0.5 * sg * z0 - red[rl.ww] / (2.0 * sg) + tau / (2.0 * sg) * xx;
@@ -989,9 +1006,9 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
         pag += (ab[k] - xb[k]) * g;
         pxx += dx * dx;
     }
-    const double gg = block_sum(pgg, scratch);
-    const double ag = block_sum(pag, scratch);
-    const double xx = block_sum(pxx, scratch);
+    double sums[3] = {pgg, pag, pxx};
+    block_sum_n<3>(sums, scratch);
+    const double gg = sums[0], ag = sums[1], xx = sums[2];
     const double sgm = st[S_SIGMA];
     if (threadIdx.x == 0) {
         st[S_J] += 1.0;
