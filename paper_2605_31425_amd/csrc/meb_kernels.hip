@@ -67,30 +67,36 @@ __device__ __forceinline__ void syrk_body(const SyrkArgs& a, int bx, int by, int
     const int w0 = by * per, w1 = min(a.nwaves, w0 + per);
     const int nseg = max(0, w1 - w0);
     // exclusive prefix of the segment counts: each thread sums a run of
-    // four, the runs are scanned in LDS, then each run is written out
+    // four, the runs are scanned within each wave by shuffles and across the
+    // four waves through LDS, then each run is written out
     {
-        __shared__ int runs[256];
+        __shared__ int wtot[256 / WAVE];
         const int q0 = threadIdx.x * 4;
+        const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
         int c[4], t = 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             c[u] = (q0 + u < nseg) ? a.mid_cnt[w0 + q0 + u] : 0;
             t += c[u];
         }
-        runs[threadIdx.x] = t;
-        __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {
-            const int v = threadIdx.x >= o ? runs[threadIdx.x - o] : 0;
-            __syncthreads();
-            runs[threadIdx.x] += v;
-            __syncthreads();
+        int inc = t;  // inclusive scan of the runs within the wave
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int y = __shfl_up(inc, o, WAVE);
+            if (lane >= o) inc += y;
         }
-        int run = runs[threadIdx.x] - t;
+        if (lane == WAVE - 1) wtot[wv] = inc;
+        __syncthreads();
+        int before = 0;
+        for (int q = 0; q < wv; ++q) before += wtot[q];
+        int run = before + inc - t;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (q0 + u <= nseg) pref[q0 + u] = run;
             run += c[u];
         }
+        // with 4 * 256 segments the closing entry lies past the last run
+        if (threadIdx.x == blockDim.x - 1 && nseg == 4 * (int)blockDim.x) pref[nseg] = run;
         __syncthreads();
     }
     const int total = pref[nseg];
@@ -934,14 +940,17 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
         block_sum_n<3>(sums, scratch);
         const double dd = sums[0], dxd = sums[1], xx = sums[2];
         if (threadIdx.x == 0) {
-            const double z0 = red[rl.trial + NT - 1];
+            double trl[NT];  // the trial sums, loaded together
+#pragma unroll
+            for (int l = 0; l < NT; ++l) trl[l] = red[rl.trial + l];
+            const double z0 = trl[NT - 1];
             const double psi0 = xb[0] + 0.5 * sg * z0 - red[rl.ww] / (2.0 * sg) + tau / (2.0 * sg) * xx;
             const double gd = st[S_GD];
             const double allow = 8.0 * eps * (fabs(psi0) + 1.0);
             int acc = -1;
             for (int l = 0; l < NT - 1; ++l) {
                 const double eta = solver_eta(l);
-                const double dpsi = eta * dir[0] + 0.5 * sg * (red[rl.trial + l] - z0) +
+                const double dpsi = eta * dir[0] + 0.5 * sg * (trl[l] - z0) +
                                     tau / (2.0 * sg) * (2.0 * eta * dxd + eta * eta * dd);
                 if (dpsi <= 1e-4 * eta * gd + allow) {
                     acc = l;
@@ -950,7 +959,7 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
             }
             if (st[S_VERBOSE] >= 2.0)
                 printf("[meb]   armijo acc=%d gd=%.17g psi0=%.17g dpsi1=%.17g\n", acc, gd, psi0,
-                       dir[0] + 0.5 * sg * (red[rl.trial] - z0) + tau / (2.0 * sg) * (2.0 * dxd + dd));
+                       dir[0] + 0.5 * sg * (trl[0] - z0) + tau / (2.0 * sg) * (2.0 * dxd + dd));
             if (acc == 0 && st[S_HSKIP] != 0.0) {
                 // full step, but its Hessian contraction was skipped:
                 // move there and evaluate again
