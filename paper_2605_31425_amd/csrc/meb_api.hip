@@ -136,12 +136,12 @@ BatchItem Engine::item(const PassArgs& a, int* flag) const {
     return it;
 }
 
-int Engine::step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+int Engine::step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int* flag) {
     if (ev0) HIPCHK(hipEventRecord(ev0, s));
     HIPCHK(launch_pass(a, pc, s));
     if (ev1) HIPCHK(hipEventRecord(ev1, s));
     if (a.want_mid) HIPCHK(launch_syrk(syrk_args(a.C, a.Uout ? a.Uout : a.U, a.Vout ? a.Vout : a.V), s));
-    if (control) HIPCHK(launch_control(state, sl, rl, red, nullptr, s));
+    if (control) HIPCHK(launch_control(state, sl, rl, red, flag, s));
     return MEB_OK;
 }
 
@@ -270,20 +270,27 @@ struct EventPool {
 thread_local EventPool g_events;
 
 // Pinned headers and completion events of the two step batches that the
-// synchronous driver keeps in flight.
+// synchronous driver keeps in flight, and the host-mapped mode word that
+// every control step writes (read instead of a header copy unless the
+// driver prints progress).
 struct PollSlots {
     double* buf = nullptr;
     double* hdr[2] = {nullptr, nullptr};
+    int* mode = nullptr;   // host view of the mode word (mapped, coherent)
+    int* dmode = nullptr;  // its device address
     hipEvent_t ev[2] = {nullptr, nullptr};
     ~PollSlots() {
         for (auto e : ev)
             if (e) (void)hipEventDestroy(e);
         if (buf) (void)hipHostFree(buf);
+        if (mode) (void)hipHostFree(mode);
     }
     int init() {
         if (buf) return MEB_OK;
         for (auto& e : ev)
             if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIPCHK(hipHostMalloc((void**)&mode, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHK(hipHostGetDevicePointer((void**)&dmode, mode, 0));
         HIPCHK(hipHostMalloc((void**)&buf, 2 * S_NSCALAR * sizeof(double), hipHostMallocDefault));
         hdr[0] = buf;
         hdr[1] = buf + S_NSCALAR;
@@ -685,9 +692,14 @@ int drive_sync(Job& j, hipStream_t s) {
     while (!j.done()) {
         if (j.stepping()) {
             // Two batches in flight: the next batch is enqueued before the
-            // older one's header is read, so the device does not wait for the
-            // host between batches.  Steps enqueued after the run has ended
-            // leave the state unchanged.
+            // older one's end is observed, so the device does not wait for
+            // the host between batches.  Steps enqueued after the run has
+            // ended leave the state unchanged.  The end is read from the mode
+            // word the control steps write to host memory (a later step's
+            // value at worst, which only reports the end earlier); with
+            // progress printing, from a copy of the state header.
+            const bool copy_hdr = j.o.verbose != 0;
+            if (inflight == 0) *reinterpret_cast<volatile int*>(ps.mode) = PM_EVAL;
             while (inflight < 2) {
                 const int batch = 4;
                 for (int b = 0; b < batch; ++b) {
@@ -698,11 +710,13 @@ int drive_sync(Job& j, hipStream_t s) {
                         if (!e0 || !e1) return fail(MEB_ERR_HIP, "hipEventCreate failed");
                         nev += 2;
                     }
-                    CHK(j.e->step(j.pa, true, s, e0, e1));
+                    CHK(j.e->step(j.pa, true, s, e0, e1, copy_hdr ? nullptr : ps.dmode));
                 }
                 j.steps += batch;
                 const int slot = (head + inflight) & 1;
-                HIPCHK(hipMemcpyAsync(ps.hdr[slot], j.e->state, sizeof(double) * S_NSCALAR, hipMemcpyDeviceToHost, s));
+                if (copy_hdr)
+                    HIPCHK(hipMemcpyAsync(ps.hdr[slot], j.e->state, sizeof(double) * S_NSCALAR, hipMemcpyDeviceToHost,
+                                          s));
                 HIPCHK(hipEventRecord(ps.ev[slot], s));
                 ++inflight;
             }
@@ -710,12 +724,13 @@ int drive_sync(Job& j, hipStream_t s) {
             const double* hs = ps.hdr[head];
             head ^= 1;
             --inflight;
-            if (j.o.verbose && (int)hs[S_K] != j.last_k) {
+            if (copy_hdr && (int)hs[S_K] != j.last_k) {
                 j.last_k = (int)hs[S_K];
                 fprintf(stderr, "[meb] k=%d sigma=%.3e kkt=%.3e passes=%d newton=%d\n", (int)hs[S_K], hs[S_SIGMA],
                         hs[S_KKT], (int)hs[S_NPASS], (int)hs[S_NINNER]);
             }
-            const bool ended = (int)hs[S_MODE] == PM_DONE;
+            const int mode_now = copy_hdr ? (int)hs[S_MODE] : *reinterpret_cast<volatile int*>(ps.mode);
+            const bool ended = mode_now == PM_DONE;
             if (ended || j.steps > j.max_steps) {
                 if (prof) {
                     HIPCHK(hipStreamSynchronize(s));  // the newer batch's events too

@@ -121,7 +121,9 @@ struct Engine {
     // pass (with its reduction) + contraction (with the H assembly)
     // (+ control when `control`); with `ev0` non-null, the pass launch is
     // bracketed by the two events
-    int step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+    // `flag` (nullable, host-mapped) receives the state's mode after the control step
+    int step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+             int* flag = nullptr);
     // clears the arrival counters (before the first kernel of a run)
     int reset_sync(hipStream_t s);
 };
