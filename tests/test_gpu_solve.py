@@ -114,3 +114,15 @@ def test_solve_deterministic():
     a = _solve(C, R, "mixed")
     b = _solve(C, R, "mixed")
     assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_progress_printing_driver_matches():
+    """The driver observes the end of a run through a mode word written by
+    the control step, or, when it prints progress, through a copy of the
+    state header; both see the same steps, so the results are identical."""
+    C, R = inputs.balls_uniform(20000, 12, 31)
+    for mode in MODES:
+        a = _solve(C, R, mode)
+        b = _solve(C, R, mode, verbose=1)
+        assert a[2]["rc"] == 0 and b[2]["rc"] == 0
+        assert a[0] == b[0] and np.array_equal(a[1], b[1]), mode
