@@ -185,8 +185,7 @@ __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
 
 // ---------------------------------------------------------------------------
 // Streaming rows into LDS (global_load_lds): each wave keeps a ring of
-// cfg.stages blocks (4 or 8) of DMA_BLK bytes of its contiguous row range in
-// flight.
+// cfg.stages blocks of DMA_BLK bytes of its contiguous row range in flight.
 // The copies do not pass through registers, so many bytes stay in flight per
 // wave at any register count.  Completion is tracked by vmcnt, in issue order
 // among loads.  LDS accesses that may run while copies are in flight are
@@ -196,7 +195,12 @@ __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
 constexpr int DMA_LOADS = 8;                  // dword copies of 256 bytes per block
 constexpr int DMA_BLK = DMA_LOADS * 256;      // bytes per block
 constexpr int DMA_MIN_STAGES = 4;             // blocks per ring: the layout's minimum
-constexpr int DMA_MAX_STAGES = 8;             // and maximum
+// and maximum.  A wave's outstanding vector-memory operations are counted in
+// six bits (at most 63), and the waits above count every copy in flight:
+// four blocks of eight copies plus the radii and multipliers of the next
+// batch stay below that; eight blocks (64 copies and more) would not.
+constexpr int DMA_MAX_STAGES = 4;
+static_assert(DMA_MAX_STAGES * DMA_LOADS + 4 <= 63, "copies in flight fit the vector-memory counter");
 
 // LDS byte address of a pointer into shared memory
 __device__ __forceinline__ uint32_t lds_addr(const void* p) {

@@ -45,9 +45,9 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     const int bpw = WAVE / c.G;
     // enough waves to fill the machine once, each streaming a contiguous
     // range: as many as fit on a compute unit at once (for the instance the
-    // configuration selects).  The deeper ring (more bytes in flight per
-    // wave) is taken when the LDS it needs does not lower that count, i.e.
-    // when registers bound the occupancy anyway.
+    // configuration selects).  A deeper ring (more bytes in flight per wave),
+    // where the copy counter allows one, is taken when the LDS it needs does
+    // not lower that count, i.e. when registers bound the occupancy anyway.
     auto resident_waves = [&]() -> int64_t {
         c.stages = DMA_MIN_STAGES;
         int per_cu = pass_blocks_per_cu(dtype, c, d);
