@@ -130,6 +130,11 @@ typedef struct meb_stats {
      * count of one pass */
     double mid_rows[2];
     double mid_rows_max[2];
+    /* breakdown guard of the Newton solve (H is positive definite in exact
+     * arithmetic, Section 4): systems solved with a raised diagonal, and
+     * inner solves ended at their iterate because no raise succeeded */
+    int32_t newton_shifted[2];
+    int32_t inner_breaks[2];
 } meb_stats;
 
 /* Fills *opts with the defaults listed above.  Returns MEB_OK. */

@@ -551,6 +551,8 @@ int Job::on_ready(hipStream_t s) {
                 st.pass_launches[0] = run_launches;
                 st.mid_rows[0] = hh[S_SUMK];
                 st.mid_rows_max[0] = hh[S_MAXK];
+                st.newton_shifted[0] = (int)hh[S_NSHIFT];
+                st.inner_breaks[0] = (int)hh[S_NBREAK];
             } else {
                 st.outer[1] += (int)hh[S_K];
                 st.inner[1] += (int)hh[S_NINNER];
@@ -561,8 +563,10 @@ int Job::on_ready(hipStream_t s) {
                 st.pass_launches[1] += run_launches;
                 st.mid_rows[1] += hh[S_SUMK];
                 st.mid_rows_max[1] = std::max(st.mid_rows_max[1], hh[S_MAXK]);
+                st.newton_shifted[1] += (int)hh[S_NSHIFT];
+                st.inner_breaks[1] += (int)hh[S_NBREAK];
             }
-            if (rstatus < 0) return fail(MEB_ERR_NUMERIC, "Newton system not positive definite");
+            if (rstatus < 0) return fail(MEB_ERR_NUMERIC, "numeric failure in the solver run");
             for (int k = 0; k < n1; ++k)
                 if (!std::isfinite(x[k])) return fail(MEB_ERR_NUMERIC, "non-finite iterate");
             if (r == 0) {

@@ -460,7 +460,7 @@ struct FlushPeriod<float> {
 // (FLW = NLMAX * VEC when a wave can hold several groups, which needs at most
 // 16 elements per lane, else 0); then, with rings, per wave the radii and
 // multipliers of two batches.
-constexpr int BAT_N = 5;
+constexpr int BAT_N = 6;
 template <int VEC, int NLMAX>
 __host__ __device__ constexpr int pass_flush_width() {
     return NLMAX * VEC <= 16 ? NLMAX * VEC : 0;
@@ -501,8 +501,22 @@ __host__ __device__ inline size_t pass_lds_bytes(int d, int stages) {
 // Loads and stores of data that other blocks (possibly on other XCDs, with
 // their own L2) read within the same kernel: agent-scope relaxed atomics,
 // i.e. write-through stores and coherent loads, so no cache flush or
-// invalidation is needed.  A block publishes its data before it counts its
-// arrival: the barrier waits for its stores to complete.
+// invalidation is needed.
+//
+// Ordering of a publication (a block stores its partials, then counts its
+// arrival; the block that arrives last reads every partial):
+//  1. every wave of the publishing block waits until its own coherent stores
+//     have completed (published(): vmcnt(0); the workgroup barrier alone
+//     does not wait for outstanding stores, and the compiler emits no wait
+//     for relaxed atomics before it);
+//  2. a workgroup barrier, then one thread counts the arrival with an
+//     agent-scope atomic add: it is issued only after all of the block's
+//     stores are visible at agent scope;
+//  3. the block that sees the count complete reads with coherent loads,
+//     issued after the counter's value returned and a barrier, so every
+//     partial it reads was complete before that count was made.
+// No L2 write-back or invalidation is involved: the partials never sit in a
+// non-coherent cache.
 __device__ __forceinline__ void st_shared_dev(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -512,6 +526,8 @@ __device__ __forceinline__ double ld_shared_dev(const double* p) {
 __device__ __forceinline__ int arrive(int* counter) {
     return __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// this wave's stores (and loads) have completed
+__device__ __forceinline__ void published() { wait_vm<0>(); }
 
 // Sum (maximum for the three KKT maxima) of n consecutive records of len
 // doubles, `stride` apart, in index order, into out (written with coherent
@@ -550,12 +566,14 @@ __device__ __forceinline__ void reduce_block_records(const double* rec, int nrec
     const int ng = (nrec + RED_GROUP - 1) / RED_GROUP;
     const int g = blk / RED_GROUP;
     const int gb = g * RED_GROUP, gn = min(RED_GROUP, nrec - gb);
+    published();
     __syncthreads();
     if (threadIdx.x == 0) s_last = arrive(&sync[g]) == gn - 1;
     __syncthreads();
     if (!s_last) return;
     double* gp = (ng == 1) ? red : red + (size_t)(1 + g) * len;
     sum_records(rec + (int64_t)gb * stride, gn, len, stride, rl.kmax, gp, ng > 1);
+    published();
     __syncthreads();
     if (threadIdx.x == 0) {
         sync[g] = 0;
@@ -843,9 +861,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
             g[2 * t + 1] = ed;
         }
         group_sum_n<T, 2 * NB>(g, G);
-        T gv[3 * NB];  // <e, v>, ||v||^2, <v, dir> per step
+        // <e, v>, ||v||^2, <v, dir>, ||s||^2 per step, s = e + v / sigma_a formed
+        // element by element (expanding ||s||^2 from the other products would
+        // cancel when v / sigma_a is close to -e)
+        T gv[4 * NB];
 #pragma unroll
-        for (int k = 0; k < 3 * NB; ++k) gv[k] = T(0);
+        for (int k = 0; k < 4 * NB; ++k) gv[k] = T(0);
         if (__any(anyv)) {
 #pragma unroll
             for (int t = 0; t < NB; ++t) {
@@ -857,14 +878,16 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
 #pragma unroll
                         for (int qq = 0; qq < VEC; ++qq) {
                             const T vk = own[j] ? vr.v[qq] : T(0);
-                            gv[3 * t] += c[t][j].v[qq] * vk;
-                            gv[3 * t + 1] += vk * vk;
-                            if (KIND != 2 && have_dir) gv[3 * t + 2] += vk * dy[j].v[qq];
+                            const T sk = c[t][j].v[qq] + vk * inv_a;
+                            gv[4 * t] += c[t][j].v[qq] * vk;
+                            gv[4 * t + 1] += vk * vk;
+                            if (KIND != 2 && have_dir) gv[4 * t + 2] += vk * dy[j].v[qq];
+                            gv[4 * t + 3] += sk * sk;
                         }
                     }
                 }
             }
-            group_sum_n<T, 3 * NB>(gv, G);
+            group_sum_n<T, 4 * NB>(gv, G);
         }
         if (leader) {
 #pragma unroll
@@ -872,9 +895,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 const uint32_t sa = bat_addr + (uint32_t)(((int)((s + t) % S) * bpw + gi) * (int)sizeof(T));
                 lds_store1<T>(sa + 0 * WAVE * sizeof(T), g[2 * t]);
                 lds_store1<T>(sa + 1 * WAVE * sizeof(T), g[2 * t + 1]);
-                lds_store1<T>(sa + 2 * WAVE * sizeof(T), gv[3 * t]);
-                lds_store1<T>(sa + 3 * WAVE * sizeof(T), gv[3 * t + 1]);
-                lds_store1<T>(sa + 4 * WAVE * sizeof(T), gv[3 * t + 2]);
+                lds_store1<T>(sa + 2 * WAVE * sizeof(T), gv[4 * t]);
+                lds_store1<T>(sa + 3 * WAVE * sizeof(T), gv[4 * t + 1]);
+                lds_store1<T>(sa + 4 * WAVE * sizeof(T), gv[4 * t + 2]);
+                lds_store1<T>(sa + 5 * WAVE * sizeof(T), gv[4 * t + 3]);
             }
         }
     };
@@ -889,13 +913,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
         const T ev = lds_load1<T>(la + 2 * WAVE * sizeof(T));
         const T vv = lds_load1<T>(la + 3 * WAVE * sizeof(T));
         const T vd = lds_load1<T>(la + 4 * WAVE * sizeof(T));
+        const T ssd = lds_load1<T>(la + 5 * WAVE * sizeof(T));
         const T ui = active ? ui_in : T(0);
         const bool hasv = V && (ui != T(0));
         sacc[A_BYTES] += active ? row_bytes + (hasv ? es_bytes * (T)d : T(0)) : T(0);
 
         // the ball at (y, w, sigma_a): s = e + v / sigma_a
         const T t = ri - r1 + ui * inv_a;
-        const T nn = ee + inv_a * (T(2) * ev + inv_a * vv);
+        const T nn = hasv ? ssd : ee;  // ||s||^2, formed element by element
         BallProj<T> pa = project<T>(t, nn, sig_a);
         if (!active) pa.cs = 1, pa.up = T(0), pa.gam = T(0), pa.Z = T(0);
 
@@ -930,7 +955,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 ue = un;
                 sig_e = sig_b;
                 te = ri - r1 + un * inv_b;
-                nne = ca * ca * ee + cb * (T(2) * ca * ev + cb * vv);
+                // ||e + k s||^2 with k = gam / sigma_b; rounding can take the
+                // expansion below zero when k s is close to -e
+                const T kq = ga * inv_b;
+                nne = ee + kq * (T(2) * (ee + inv_a * ev) + kq * nn);
+                nne = nne > T(0) ? nne : T(0);
                 pe = project<T>(te, nne, sig_b);
                 if (!active) pe.cs = 1, pe.up = T(0), pe.gam = T(0), pe.Z = T(0);
             }
@@ -941,10 +970,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
             sacc[A_SU] += pe.up;
             sacc[A_Z1] += pe.Z;
             const T du = pe.up - ue;
-            // ||gam_e s_e - w_v||^2 with gam_e s_e - w_v = A e + B v
-            const T Ac = pe.gam * ca - wa, Bc = pe.gam * cb - wb;
-            const T dv2 = Ac * Ac * ee + Bc * (T(2) * Ac * ev + Bc * vv);
-            sacc[A_DM] += du * du + (active ? dv2 : T(0));
+            // ||gam_e s_e - w_v||^2: balls on the active list (below) add it in
+            // phase 2, element by element; for the others gam_e = 0 and it is
+            // ||v||^2 in an evaluation, 0 in a multiplier update (w+ = 0 there)
+            const bool listed = pe.cs != 1 || (want_kkt && un != T(0));
+            const T dv2 = (KIND != 2) ? vv : T(0);
+            sacc[A_DM] += du * du + ((active && !listed) ? dv2 : T(0));
             sacc[A_WW] += ue * ue + (active ? wwv : T(0));
             sacc[A_RS] += (pe.cs != 1) ? fabs(te) + pe.n : T(0);
             sacc[A_NI] += (pe.cs == 0) ? T(1) : T(0);
@@ -1251,7 +1282,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
     if (act_count > 0) {
         __threadfence_block();
         T vsv[NLMAX][VEC], vsw[NLMAX][VEC], vkv[NLMAX][VEC];
+        T dmv = T(0);  // this lane's part of sum ||gam_e s_e - w_v||^2 over the list
         auto zero_vec = [&]() {
+            dmv = T(0);
 #pragma unroll
             for (int j = 0; j < NLMAX; ++j)
 #pragma unroll
@@ -1317,12 +1350,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 for (int j = 0; j < NLMAX; ++j)
                     if (own[j]) vr[j] = load_vec<T, VEC>(V + i * d + col[j]);
             }
+            // the multiplier in use is (wa e + wb v): (0, 1) in an evaluation,
+            // the updated one in a multiplier update
+            const T wa = (KIND == 2) ? cf[4] : T(0), wb = (KIND == 2) ? cf[5] : T(1);
+            const T da = a1 - wa, db = b1 - wb;
 #pragma unroll
             for (int j = 0; j < NLMAX; ++j)
 #pragma unroll
                 for (int q = 0; q < VEC; ++q) {
                     vsv[j][q] += a1 * er[j].v[q] + b1 * vr[j].v[q];
                     vsw[j][q] += a2 * er[j].v[q] + b2 * vr[j].v[q];
+                    const T dk = da * er[j].v[q] + db * vr[j].v[q];
+                    dmv += dk * dk;
                 }
             if constexpr (want_kkt) {
                 const T a3 = cf[4], b3 = cf[5];
@@ -1338,6 +1377,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 }
             }
             if ((k0 / bpw + 1) % FS == 0 || k0 + bpw >= act_count) {
+                const T dms = wave_sum_t<T>(dmv);
+                if (lane == 0) rec[rl.dm] += (double)dms;
                 flush_vec(vsv, rl.sv);
                 flush_vec(vsw, rl.sw);
                 if constexpr (want_kkt) flush_vec(vkv, rl.kv);

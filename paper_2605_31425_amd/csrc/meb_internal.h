@@ -56,6 +56,8 @@ enum StateSlot : int {
     S_MAXK,          // largest such row count of one pass
     S_HSKIP,         // 1 if the contraction of the last pass was skipped
     S_FLOOR,         // 1 if the last inner solve of a low-precision run stopped at the rounding floor
+    S_NSHIFT,        // Newton systems solved with a raised diagonal (breakdown guard)
+    S_NBREAK,        // inner solves ended because no shift made the factorization succeed
     S_NSCALAR = 48
 };
 

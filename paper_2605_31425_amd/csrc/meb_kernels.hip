@@ -166,6 +166,7 @@ __device__ __forceinline__ void syrk_body(const SyrkArgs& a, int bx, int by, int
     st_shared_dev(out + (ty + 16) * SYRK_T + tx + 16, acc[1][1]);
 
     // the last block of the tile pair assembles its part of H
+    published();
     __syncthreads();
     if (threadIdx.x == 0) s_last = arrive(&a.sync[SYNC_SYRK + bx]) == a.ksplit - 1;
     __syncthreads();
@@ -764,6 +765,12 @@ constexpr int CHOL_LDS_MAX_N = 140;  // 140 x 141 doubles + vectors < 160 KiB
 constexpr int CTRL_THREADS = 1024;
 // the control kernel also keeps CTRL_THREADS doubles of scratch in LDS
 constexpr int CTRL_CHOL_LDS_MAX_N = 132;  // 1024 + 132 x 133 doubles < 160 KiB
+constexpr int CTRL_SHIFT_TRIES = 8;       // raises of the diagonal before an inner solve gives up
+// LDS scratch of the control step: two n1-vectors and the wave sums of a
+// block reduction after them, and at least one double per thread
+__host__ __device__ inline int ctrl_scratch_doubles(int n1) {
+    return CTRL_THREADS > 2 * n1 + 64 ? CTRL_THREADS : 2 * n1 + 64;
+}
 
 __global__ __launch_bounds__(CTRL_THREADS) void chol_solve_kernel(int n, double* A, double* b, int* info) {
     extern __shared__ __align__(16) double sm[];
@@ -835,8 +842,8 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 
 __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayout rl, const double* red) {
     extern __shared__ __align__(16) double sm[];
-    double* scratch = sm;                                                    // max(CTRL_THREADS, 2 n1)
-    double* lmat = sm + (CTRL_THREADS > 2 * sl.n1 ? CTRL_THREADS : 2 * sl.n1);  // Cholesky matrix when it fits
+    double* scratch = sm;                            // ctrl_scratch_doubles(n1)
+    double* lmat = sm + ctrl_scratch_doubles(sl.n1);  // Cholesky matrix when it fits
     __shared__ int s_next;                   // 0 = continue to EVAL_AT_BASE, 1 = return
     __shared__ double s_eta;
     const int mode = (int)st[S_MODE];
@@ -1047,38 +1054,79 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
     }
     __syncthreads();
     if (s_next) return;
-    // Newton direction: H dir = -g, H assembled by the contraction
-    int rc;
-    if (rch_fits(n1, blockDim.x)) {
-        double* bv = scratch;
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
+    // Newton direction: H dir = -g, H assembled by the contraction.  H is
+    // positive definite through its (tau/sigma) I term in exact arithmetic
+    // (Section 4); rounding in its assembly can still produce a pivot that is
+    // not positive.  Breakdown guard: the diagonal is raised by
+    // mu = max(tau/sigma, 4 eps mean_k H_kk), then 16 mu, 256 mu, ... (at
+    // most CTRL_SHIFT_TRIES raises) and the system solved again -- a shifted
+    // system still gives a descent direction for the line search; if no shift
+    // succeeds, the inner solve ends at the current iterate.
+    const bool large = !rch_fits(n1, blockDim.x) && n1 > CTRL_CHOL_LDS_MAX_N;
+    double* hdiag = scratch + n1;  // the large path factorizes H in place: its diagonal is kept here
+    if (large) {
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) hdiag[k] = H[k * n1 + k];
         __syncthreads();
-        rc = chol_solve_regs(n1, H, bv, bv, lmat);
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
-        __syncthreads();
-    } else if (n1 <= CTRL_CHOL_LDS_MAX_N) {
-        // LDS: scratch = [rd (n1) | rhs (n1)], lmat = H with an odd leading dimension
-        const int ld = chol_ld(n1);
-        double* rd = scratch;
-        double* bv = scratch + n1;
-        for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) lmat[(e / n1) * ld + e % n1] = H[e];
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
-        __syncthreads();
-        rc = chol_solve_lds(n1, ld, lmat, bv, rd);
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
-        __syncthreads();
-    } else {
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = -gb[k];
-        __syncthreads();
-        rc = chol_solve_block_large(n1, H, dir, scratch);
+    }
+    int rc = 1;
+    double mu0 = 0.0, mu = 0.0;
+    for (int attempt = 0; attempt <= CTRL_SHIFT_TRIES && rc != 0; ++attempt) {
+        if (attempt == 1) {
+            double ptr = 0.0;
+            for (int k = threadIdx.x; k < n1; k += blockDim.x) ptr += large ? hdiag[k] : H[k * n1 + k];
+            const double tr = block_sum(ptr, scratch + 2 * n1);
+            mu0 = fmax(tau / sgm, 4.0 * eps * fabs(tr) / n1);
+        }
+        if (attempt > 0) {
+            const double mu_new = mu0 * (double)(1u << (4 * (attempt - 1)));
+            if (large) {
+                // restore the lower triangle from the untouched upper one
+                for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) {
+                    const int i = e / n1, j = e % n1;
+                    if (i > j) H[e] = H[j * n1 + i];
+                    if (i == j) H[e] = hdiag[i] + mu_new;
+                }
+            } else {
+                for (int k = threadIdx.x; k < n1; k += blockDim.x) H[k * n1 + k] += mu_new - mu;
+            }
+            mu = mu_new;
+            __syncthreads();
+        }
+        if (rch_fits(n1, blockDim.x)) {
+            double* bv = scratch;
+            for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
+            __syncthreads();
+            rc = chol_solve_regs(n1, H, bv, bv, lmat);
+            for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
+            __syncthreads();
+        } else if (n1 <= CTRL_CHOL_LDS_MAX_N) {
+            // LDS: scratch = [rd (n1) | rhs (n1)], lmat = H with an odd leading dimension
+            const int ld = chol_ld(n1);
+            double* rd = scratch;
+            double* bv = scratch + n1;
+            for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) lmat[(e / n1) * ld + e % n1] = H[e];
+            for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
+            __syncthreads();
+            rc = chol_solve_lds(n1, ld, lmat, bv, rd);
+            for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
+            __syncthreads();
+        } else {
+            for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = -gb[k];
+            __syncthreads();
+            rc = chol_solve_block_large(n1, H, dir, scratch);
+        }
     }
     if (rc != 0) {
+        // no shift helped: end the inner solve here (multiplier update next)
         if (threadIdx.x == 0) {
-            st[S_STATUS] = -1.0;
-            st[S_MODE] = (double)PM_DONE;
+            st[S_NBREAK] += 1.0;
+            st[S_MODE] = (double)PM_MULT;
+            st[S_HAVE_DIR] = 0.0;
+            st[S_FLOOR] = 0.0;
         }
         return;
     }
+    if (threadIdx.x == 0 && mu > 0.0) st[S_NSHIFT] += 1.0;
     double pgd = 0.0;
     for (int k = threadIdx.x; k < n1; k += blockDim.x) pgd += gb[k] * dir[k];
     const double gd = block_sum(pgd, scratch);
@@ -1099,7 +1147,7 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
 }
 
 size_t control_lds_bytes(int n1) {
-    size_t lds = sizeof(double) * (size_t)(CTRL_THREADS > 2 * n1 ? CTRL_THREADS : 2 * n1);
+    size_t lds = sizeof(double) * (size_t)ctrl_scratch_doubles(n1);
     if (rch_fits(n1, CTRL_THREADS))
         lds += sizeof(double) * rch_lds_doubles(n1);
     else if (n1 <= CTRL_CHOL_LDS_MAX_N)

@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("status", ctypes.c_int32), ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 4),
                 ("pass_ms", ctypes.c_double * 2), ("pass_bytes", ctypes.c_double * 2),
                 ("pass_launches", ctypes.c_int32 * 2), ("reserved", ctypes.c_int32),
-                ("mid_rows", ctypes.c_double * 2), ("mid_rows_max", ctypes.c_double * 2)]
+                ("mid_rows", ctypes.c_double * 2), ("mid_rows_max", ctypes.c_double * 2),
+                ("newton_shifted", ctypes.c_int32 * 2), ("inner_breaks", ctypes.c_int32 * 2)]
 
     def as_dict(self):
         return dict(outer=list(self.outer), inner=list(self.inner), passes=list(self.passes), kkt=list(self.kkt),
@@ -53,7 +54,8 @@ class Stats(ctypes.Structure):
                     reinsert_rounds=self.reinsert_rounds, status=self.status, ms_total=self.ms_total,
                     ms_phase=list(self.ms_phase), pass_ms=list(self.pass_ms), pass_bytes=list(self.pass_bytes),
                     pass_launches=list(self.pass_launches), mid_rows=list(self.mid_rows),
-                    mid_rows_max=list(self.mid_rows_max))
+                    mid_rows_max=list(self.mid_rows_max), newton_shifted=list(self.newton_shifted),
+                    inner_breaks=list(self.inner_breaks))
 
 
 class ServerResult(ctypes.Structure):
