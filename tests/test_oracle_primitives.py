@@ -192,3 +192,55 @@ def test_lcg_generator_first_values():
     Cb, Rb = inputs.lcg_instance(4097 * 2, 1)  # 8194 scalars
     flat = np.stack([Rb, Cb[:, 0]], 1).ravel()
     assert flat[4096] == flat[0] and len(set(flat[:4096])) == 4096
+
+
+def _three_case_instance():
+    """Three balls in R^2 whose z_i = (r_i - r + u_i/sigma, c_i - c + v_i/sigma)
+    fall in the three projection cases at x = (1, 0, 0), sigma = 2, tau = 1,
+    xbar = (0.5, 0, 1), each with a non-zero multiplier (u_i, v_i) in Q:
+      A (third case): c = (2.4, 3.2), r = 1,   w = (2, 1.2, 1.6)  -> z = (1, 3, 4)
+      B (interior):   c = (0.5, 0),   r = 1.5, w = (1, 0.5, 0)    -> z = (1, 0.75, 0)
+      C (polar):      c = (0, 0.2),   r = 0,   w = (0.5, 0, 0.4)  -> z = (-0.75, 0, 0.4)
+    """
+    C = np.array([[2.4, 3.2], [0.5, 0.0], [0.0, 0.2]])
+    R = np.array([1.0, 1.5, 0.0])
+    U = np.array([2.0, 1.0, 0.5])
+    V = np.array([[1.2, 1.6], [0.5, 0.0], [0.0, 0.4]])
+    return C, R, U, V, np.array([1.0, 0.0, 0.0]), np.array([0.5, 0.0, 1.0]), 2.0, 1.0
+
+
+def test_al_eval_three_cases_worked_by_hand():
+    # Worked out by hand from the closed-form projection (Section 2), Psi of
+    # the proximal subproblem (Section 3), its gradient and the generalized
+    # Hessian (Section 4) and the multiplier update (Algorithm 1):
+    #   A: t = 1, s = (3, 4), n = 5: Pi = 3 (1, 0.6, 0.8) = (3, 1.8, 2.4), ||Pi||^2 = 18,
+    #      sigma Pi = (6, 3.6, 4.8), change (4, 2.4, 3.2): 32;  ||w||^2 = 4 + 1.44 + 2.56 = 8
+    #   B: Pi = z = (1, 0.75, 0), ||Pi||^2 = 1.5625, sigma Pi = (2, 1.5, 0), change (1, 1, 0): 2;
+    #      ||w||^2 = 1.25
+    #   C: Pi = 0, change -w: 0.41;  ||w||^2 = 0.41
+    #   Psi = r + sigma/2 * 19.5625 - 9.66 / (2 sigma) + tau/(2 sigma) * 1.25
+    #       = 1 + 19.5625 - 2.415 + 0.3125 = 18.46
+    #   g = (1, 0, 0) - sigma (4, 2.55, 2.4) + tau/sigma (0.5, 0, -1) = (-6.75, -5.1, -5.3)
+    #   H = tau/sigma I + sigma (I + P_A), P_A = 1/2 [[1, w^T], [w, 1.2 I - 0.2 w w^T]], w = (0.6, 0.8)
+    C, R, U, V, x, xbar, sigma, tau = _three_case_instance()
+    ev = oracle.al_eval(C, R, U, V, x, xbar, sigma, tau)
+    assert list(ev["counts"]) == [1, 1, 1]
+    np.testing.assert_allclose(ev["psi"], 18.46, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(ev["g"], [-6.75, -5.1, -5.3], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(ev["dmult"], 34.41, rtol=0, atol=1e-13)
+    H = np.array([[3.5, 0.6, 0.8], [0.6, 3.628, -0.096], [0.8, -0.096, 3.572]])
+    np.testing.assert_allclose(ev["H"], H, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(ev["U"], [6.0, 2.0, 0.0], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(ev["V"], [[3.6, 4.8], [1.5, 0.0], [0.0, 0.0]], rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("ball,psi,dmult", [(0, 1 + 18 - 2 + 0.3125, 32.0), (1, 1 + 1.5625 - 0.3125 + 0.3125, 2.0),
+                                            (2, 1 + 0 - 0.1025 + 0.3125, 0.41)])
+def test_al_eval_single_case_multiplier_terms(ball, psi, dmult):
+    # each ball alone: the -||w||^2 / (2 sigma) term and the multiplier change
+    # carry the case's hand value (a sign or factor slip in either fails)
+    C, R, U, V, x, xbar, sigma, tau = _three_case_instance()
+    sl = slice(ball, ball + 1)
+    ev = oracle.al_eval(C[sl], R[sl], U[sl], V[sl], x, xbar, sigma, tau)
+    np.testing.assert_allclose(ev["psi"], psi, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(ev["dmult"], dmult, rtol=0, atol=1e-13)
