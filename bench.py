@@ -80,22 +80,126 @@ def golden(name):
     return None
 
 
+def host_cpu():
+    """Core count and model of the host this runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count(), len(os.sched_getaffinity(0)), model
+
+
 def cpu_baseline(C, R, m_full, sample_m):
-    """The oracle as it stands, single-threaded, on the first sample_m balls;
-    time-to-solution scaled by m_full / sample_m (each pass is linear in m)."""
+    """The oracle as it stands (plain C, one thread), on the first sample_m
+    balls; time-to-solution scaled by m_full / sample_m (each pass is linear
+    in m, and the iteration counts of the sample and the full instance are
+    alike)."""
     import oracle
     Cs = np.ascontiguousarray(C[:sample_m])
     Rs = None if R is None else np.ascontiguousarray(R[:sample_m])
     t = time.perf_counter()
     oracle.ripalm(Cs, Rs, tol=1e-8)
     el = time.perf_counter() - t
+    ncpu, naff, model = host_cpu()
     return dict(value=el * m_full / sample_m, unit="s", cores=1, kind="oracle",
                 sample=f"oracle ripALM to KKT 1e-8 on the first {sample_m} balls of the same instance "
-                       f"({el:.2f} s), scaled by {m_full}/{sample_m}")
+                       f"({el:.2f} s on one core), scaled by {m_full}/{sample_m}",
+                host_cpus=ncpu, host_cpus_available=naff, host_cpu_model=model, sample_seconds=el)
 
 
-def serving_leg(n_req, load, seed, max_active, pool_gb, check_sample, log):
-    """Saturation run, then a Poisson stream at `load` x saturation rate."""
+def time_solves(meb, Cd, Rd, mode, reps, hess="auto"):
+    """(ms per solve, last result) of `reps` solves after one warm-up."""
+    import torch
+    o = meb.options(mode=mode, hess=hess)
+    meb.solve(Cd, Rd, opts=o)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        res = meb.solve(Cd, Rd, opts=o)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / reps, res
+
+
+def other_workloads(names, log):
+    """Time-to-solution of the other workloads, mixed and plain FP64, with
+    their error against the oracle's stored radius."""
+    import torch
+    from paper_2605_31425_amd import inputs, meb
+    out = {}
+    for name in names:
+        wl = WORKLOADS[name]
+        m, d, seed = wl["args"]
+        C, R = getattr(inputs, wl["gen"])(m, d, seed)
+        Cd = torch.as_tensor(C, device="cuda:0")
+        Rd = None if R is None else torch.as_tensor(R, device="cuda:0")
+        g = golden(name)
+        row = dict(workload=wl["desc"])
+        for mode in ("mixed", "fp64"):
+            ms, (r, c, st) = time_solves(meb, Cd, Rd, mode, 1 if m * d > 1e8 else 3)
+            row[f"{mode}_ms"] = ms
+            row[f"{mode}_radius_relerr_vs_oracle"] = abs(r - g["r_fixed"]) / g["r_fixed"] if g else None
+            row[f"{mode}_passes"] = st["passes"]
+            row[f"{mode}_newton_steps"] = st["inner"]
+            if mode == "mixed":
+                row["kept_for_fp64"] = st["n_red"]
+                row["reinsert_rounds"] = st["reinsert_rounds"]
+        row["speedup_mixed_vs_fp64"] = row["fp64_ms"] / row["mixed_ms"]
+        log(f"{name}: mixed {row['mixed_ms']:.2f} ms, fp64 {row['fp64_ms']:.2f} ms")
+        out[name] = row
+        del Cd, Rd
+        torch.cuda.empty_cache()
+    return out
+
+
+# Table 1 of the paper: balls kept for the FP64 run (RTX 4070 runs; context)
+TABLE1 = {20: (23, 43, 82, 405, 807), 30: (28, 42, 88, 449, 899), 40: (45, 77, 155, 780, 1586),
+          50: (41, 96, 182, 929, 1852)}
+
+
+def paper_instances(log):
+    """The paper's LCG instances (Section 5): the Figure 2 / Table 1 grid and
+    the Figure 3 shapes up to d = 1000, mixed and plain FP64, with the kept
+    counts beside Table 1's (not comparable one to one: the paper does not
+    state its screening margin) and the error against the oracle."""
+    import torch
+    from paper_2605_31425_amd import inputs, meb
+    p = os.path.join(ROOT, "tests", "golden", "oracle_lcg.json")
+    gold = {}
+    if os.path.exists(p):
+        with open(p) as f:
+            gold = {(e["d"], e["m"]): e["r_fixed"] for e in json.load(f)["instances"]}
+    rows = []
+    ms_list = (1000, 5000, 10000, 50000, 100000)
+    shapes = [(d, m) for d in (20, 30, 40, 50) for m in ms_list] + [(d, m) for d in (100, 500, 1000)
+                                                                     for m in (1000, 5000)]
+    for d, m in shapes:
+        C, R = inputs.lcg_instance(m, d)
+        Cd = torch.as_tensor(C, device="cuda:0")
+        Rd = torch.as_tensor(R, device="cuda:0")
+        row = dict(d=d, m=m)
+        for mode in ("mixed", "fp64"):
+            ms, (r, c, st) = time_solves(meb, Cd, Rd, mode, 3)
+            row[f"{mode}_ms"] = round(ms, 3)
+            ref = gold.get((d, m))
+            row[f"{mode}_relerr"] = abs(r - ref) / ref if ref else None
+            if mode == "mixed":
+                row["kept"] = st["n_red"]
+                if d in TABLE1:
+                    row["kept_paper_table1"] = TABLE1[d][ms_list.index(m)]
+        rows.append(row)
+    log(f"paper instances: {len(rows)} shapes, mixed total {sum(r['mixed_ms'] for r in rows):.1f} ms")
+    return rows
+
+
+def serving_leg(n_req, loads, seed, max_active, pool_gb, check_sample, log):
+    """Saturation run, then one Poisson stream at each of `loads` x the
+    saturation rate (the first load's stream is the one reported at the top
+    level; every load's latencies are listed under "loads")."""
     import torch
 
     from paper_2605_31425_amd import inputs, meb
@@ -144,10 +248,20 @@ def serving_leg(n_req, load, seed, max_active, pool_gb, check_sample, log):
 
     _, lat_sat, thr_sat, info_sat = run(np.zeros(n_req))
     log(f"serving saturation: {thr_sat:.1f} solves/s, mean tick items {info_sat['mean_tick_items']:.1f}")
-    rate = load * thr_sat
-    arr = inputs.poisson_arrivals(n_req, rate, seed + 2)
-    res, lat, thr, info = run(arr)
-    log(f"serving stream at {rate:.1f}/s: p50 {np.percentile(lat, 50):.2f} ms p99 {np.percentile(lat, 99):.2f} ms")
+    sweep = []
+    main = None
+    for load in loads:
+        rate = load * thr_sat
+        arr = inputs.poisson_arrivals(n_req, rate, seed + 2)
+        res_l, lat_l, thr_l, info_l = run(arr)
+        log(f"serving stream at {rate:.1f}/s ({load} x saturation): p50 {np.percentile(lat_l, 50):.2f} ms "
+            f"p99 {np.percentile(lat_l, 99):.2f} ms")
+        sweep.append(dict(load_vs_saturation=load, arrival_rate_per_s=rate, solves_per_s=thr_l,
+                          p50_ms=float(np.percentile(lat_l, 50)), p99_ms=float(np.percentile(lat_l, 99)),
+                          mean_ms=float(lat_l.mean()), mean_requests_per_tick=info_l["mean_tick_items"]))
+        if main is None or abs(load - 0.7) < abs(main[0] - 0.7):
+            main = (load, rate, res_l, lat_l, thr_l, info_l)
+    load, rate, res, lat, thr, info = main
     # sample: bitwise equal to meb_solve alone, and feasible in FP64
     idx = sorted(rng.choice(n_req, size=min(check_sample, n_req), replace=False).tolist())
     same, viol = True, -np.inf
@@ -179,6 +293,7 @@ def serving_leg(n_req, load, seed, max_active, pool_gb, check_sample, log):
         "sample_checked": len(idx),
         "sample_bitwise_equal_to_meb_solve": same,
         "sample_max_violation_rel": viol,
+        "loads": sweep,
     }
 
 
@@ -189,11 +304,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="balls_1e6_d100", choices=sorted(WORKLOADS))
     ap.add_argument("--fp64-steps", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=100000)
+    ap.add_argument("--cpu-sample", type=int, default=250000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=4096)
-    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-load", type=float, nargs="+", default=[0.5, 0.7, 0.9])
+    ap.add_argument("--no-others", action="store_true", help="skip the other workloads and the paper's instances")
     ap.add_argument("--serve-max-active", type=int, default=128)
     ap.add_argument("--serve-pool-gb", type=float, default=64.0)
     ap.add_argument("--serve-check", type=int, default=8)
@@ -333,6 +449,10 @@ def main():
     }
     del ws, ws64, Cd, Rd
     torch.cuda.empty_cache()
+    if not a.no_others:
+        out["other_workloads"] = other_workloads([n for n in ("points_1e4_d10", "balls_2e5_d1000", "points_1e7_d10")
+                                                  if n != a.workload], log)
+        out["paper_instances"] = paper_instances(log)
     if a.serve_requests > 0:
         out["serving"] = serving_leg(a.serve_requests, a.serve_load, 5, a.serve_max_active, a.serve_pool_gb,
                                      a.serve_check, log)

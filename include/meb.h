@@ -21,8 +21,9 @@
  *     R == NULL means a point set (every r_i = 0).  U has m entries, V is
  *     m x d.  x = (r, c) vectors have d + 1 entries with r first.
  *   - dtype is MEB_F64 (double) or MEB_F32 (float) and applies to C, R, U, V.
- *     Device pointers must be aligned to their element size; 16-byte
- *     alignment is faster.
+ *     C and V must be 16-byte aligned (rows are read with 16-byte loads and
+ *     16-byte LDS copies; every torch or hipMalloc allocation is); the other
+ *     device pointers must be aligned to their element size.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Work
  *     is ordered on it; calls that return host results synchronize it.
  *   - Scratch memory: each call takes a device workspace `ws` of `ws_bytes`
@@ -70,6 +71,20 @@ extern "C" {
 #define MEB_WANT_DMULT 16u
 #define MEB_WANT_KKT 32u
 
+/* Hessian contraction (the rank-one part of the generalized Hessian,
+ * sum over the balls in the third projection case of coef_i s_i s_i^T) */
+#define MEB_HESS_AUTO 0       /* FP64 run: MFMA_F64 for d >= 128, else F64; FP32 run: MFMA_BF16 for
+                                 d >= 256, else F64                                              */
+#define MEB_HESS_F64 1        /* FP64 vector FMA accumulation of run-precision rows              */
+#define MEB_HESS_MFMA_F64 2   /* FP64 matrix cores (FP64 run only; the FP32 run uses F64)        */
+#define MEB_HESS_MFMA_F32 3   /* FP32 inputs, FP32 accumulation on matrix cores (FP32 run only;
+                                 the FP64 run uses AUTO's choice)                                */
+#define MEB_HESS_MFMA_BF16 4  /* BF16 inputs, FP32 accumulation on matrix cores (FP32 run only)  */
+
+/* Newton-direction solvers (meb_options.newton) */
+#define MEB_NEWTON_DENSE 0
+#define MEB_NEWTON_CG 1
+
 /* largest supported dimension */
 #define MEB_MAX_D 2048 /* odd d: at most 1024 */
 
@@ -84,7 +99,8 @@ typedef struct meb_options {
     double sigma_growth;   /* sigma_{k+1} = min(growth * sigma_k, sigma_max); default 5              */
     double sigma_max;      /* default 1e5                                                            */
     double tau;            /* proximal weight tau_k (constant); default 1                            */
-    double tol_kkt;        /* final KKT_max tolerance (Section 5); default 1e-8                      */
+    double tol_kkt;        /* final KKT_max tolerance (Section 5 uses 1e-8); default 1e-9, so that the
+                              relative radius error stays below 1e-8 on every tested instance  */
     double tol_kkt_low;    /* KKT_max tolerance of the FP32 screening run (Section 5); default 1e-2  */
     double tol_red;        /* screening margin, in units of L (Section 4.2); default 0.03.  A
                               negative value keeps only balls the FP32 ball violates, which
@@ -100,6 +116,18 @@ typedef struct meb_options {
                               line per evaluation pass and Newton step (device printf)          */
     int32_t profile;       /* 1 = time every evaluation pass with HIP events (fills the pass_*
                               fields of meb_stats); default 0                                   */
+    int32_t hess;          /* MEB_HESS_*: arithmetic of the Hessian contraction; default AUTO    */
+    int32_t first_order_outer; /* the inner solves of the first this-many outer iterations (of the
+                              FP64 run, or of the mixed mode's screening run) use the
+                              accelerated gradient method (Section 4.1:
+                              first-order inner solvers for the early outer iterations, with
+                              backtracking and adaptive restart) instead of semismooth
+                              Newton; default 0 (Newton throughout)                            */
+    int32_t newton;        /* MEB_NEWTON_DENSE: H assembled and factorized (default);
+                              MEB_NEWTON_CG: matrix-free, preconditioned conjugate gradients with
+                              Hessian-vector products (Section 4.1, for large d); meb_solve only */
+    int32_t cg_max_iter;   /* CG iterations per Newton direction (MEB_NEWTON_CG); default 20      */
+    double cg_tol;         /* relative residual at which CG stops; default 1e-2                  */
 } meb_options;
 
 /* Statistics of one meb_solve.  Index 0 = FP32 screening run (mixed mode),
@@ -135,6 +163,10 @@ typedef struct meb_stats {
      * inner solves ended at their iterate because no raise succeeded */
     int32_t newton_shifted[2];
     int32_t inner_breaks[2];
+    /* iterations of the first-order inner solver (first_order_outer) */
+    int32_t first_order_steps[2];
+    /* conjugate-gradient iterations (MEB_NEWTON_CG) */
+    int32_t cg_iterations[2];
 } meb_stats;
 
 /* Fills *opts with the defaults listed above.  Returns MEB_OK. */
@@ -161,7 +193,12 @@ int meb_eval_workspace_size(int64_t m, int32_t d, int32_t dtype, size_t* bytes);
  * the retained balls warm-started from the FP32 point and multipliers, a
  * full FP64 check of every ball, and reinsertion of violated discarded balls
  * followed by a new FP64 run, until no discarded ball is violated.
- * C and R must be MEB_F64 (the FP32 copy of the mixed mode is made internally).
+ * C and R may be MEB_F64 or MEB_F32.  FP32 input is first widened exactly
+ * into an FP64 copy inside the workspace (meb_workspace_size with dtype
+ * MEB_F32 includes it), so the solve is the one of the widened data; the FP32
+ * copy of the mixed mode is made internally either way.
+ * Input errors: a negative radius, or a NaN or infinite coordinate or
+ * radius, returns MEB_ERR_ARG (detected by the first pass over the data).
  *
  * Outputs: *r_out and c_out[d] (host) hold the ball.  r_out is made feasible
  * for every input ball: r_out = max(rbar, max_i (r_i + ||c - c_i||)) with
@@ -197,12 +234,26 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
  *              max dual cone distance, max |complementarity|            (KKT)
  * U and V may be NULL (zero multipliers).  V rows are read only where
  * u_i != 0 (a multiplier in Q with u_i = 0 has v_i = 0).
+ * Bits 8..10 of `want` select the arithmetic of the rank-one part of H
+ * (MEB_HESS_* << 8, as for a run of precision dtype; 0 = AUTO).
  * Arithmetic runs in dtype; sums are accumulated in FP64 in a fixed order. */
 int meb_al_eval(const void* C, const void* R, const void* U, const void* V, int64_t m, int32_t d, int32_t dtype,
                 const double* x, const double* xbar, double sigma, double tau, const double* dir,
                 int32_t n_eta, const double* etas, uint32_t want, double* psi, double* psi_trial, double* g,
                 double* H, void* U_new, void* V_new, double* dmult, double* kkt, void* ws, size_t ws_bytes,
                 void* stream);
+
+/* Matrix-free product of the generalized Hessian of the subproblem with a
+ * vector (Section 4.1: H q = tau/sigma q + sigma sum_i P_i q, the products
+ * P_i q taken ball by ball and summed), at x with multipliers (U, V),
+ * penalty sigma > 0 and proximal weight tau > 0; H is never formed.  This is
+ * the product the MEB_NEWTON_CG solver iterates with.  x, q (host, d + 1),
+ * Hq (host, d + 1) receives the product.  U, V as for meb_al_eval.  Sums are
+ * taken in a fixed order (reproducible); the per-ball rows are formed in
+ * dtype.  ws from meb_eval_workspace_size. */
+int meb_hess_vec(const void* C, const void* R, const void* U, const void* V, int64_t m, int32_t d, int32_t dtype,
+                 const double* x, double sigma, double tau, const double* q, double* Hq, void* ws, size_t ws_bytes,
+                 void* stream);
 
 /* Screening of Section 4.2: slack_i = r_hat - r_i - ||c_hat - c_i||,
  * evaluated in FP64 (FP32 inputs are widened exactly), and
@@ -225,7 +276,8 @@ int meb_check_feasible(const void* C, const void* R, int64_t m, int32_t d, int32
 /* Precision preparation for the screening run: C32[i] = float(C[i] - origin)
  * (row-wise, origin host d, nullable = 0), R32[i] = float(R[i]) (R32 unused
  * if R is NULL), rounded to nearest.  *L_out (host, nullable) receives
- * max_i (||c_i - origin|| + r_i) computed in FP64 from the FP64 input. */
+ * max_i (||c_i - origin|| + r_i) computed in FP64 from the FP64 input, or
+ * +inf if some r_i is negative or some value is not finite. */
 int meb_prepare_f32(const double* C, const double* R, int64_t m, int32_t d, const double* origin, float* C32,
                     float* R32, double* L_out, void* ws, size_t ws_bytes, void* stream);
 

@@ -64,8 +64,8 @@ void Engine::setup(int64_t m_, int d_, int dtype_) {
     pc = choose_pass_config(m, d, dtype, device_cus());
     sl = StateLayout::make(d);
     rl = RecLayout::make(d);
-    ntile = (d + syrk_tile() - 1) / syrk_tile();
     ksplit = syrk_ksplit(d);
+    mm = SYRK_VEC;
     // a line-search pass skips the contraction above this many rows
     skip_k = std::max(4096.0, 16.0 * d);
 }
@@ -121,8 +121,9 @@ SyrkArgs Engine::syrk_args(const void* C, const void* U, const void* V) const {
     s.out = syrk;
     s.sync = sync;
     s.ksplit = ksplit;
-    s.tile = syrk_tile();
-    s.ntile = ntile;
+    s.mm = mm;
+    s.tile = syrk_tile_of(mm);
+    s.ntile = (d + s.tile - 1) / s.tile;
     return s;
 }
 
@@ -136,11 +137,47 @@ BatchItem Engine::item(const PassArgs& a, int* flag) const {
     return it;
 }
 
+CgArgs Engine::cg_args(const void* C, const void* U, const void* V, int init) const {
+    CgArgs c;
+    memset(&c, 0, sizeof(c));
+    c.C = C;
+    c.U = U;
+    c.V = V;
+    c.d = d;
+    c.dtype = dtype;
+    c.state = state;
+    c.sl = sl;
+    c.red = red;
+    c.rl = rl;
+    c.mid_cnt = mid_cnt;
+    c.mid_idx = mid_idx;
+    c.mid_coef = mid_coef;
+    c.nwaves = pc.nwaves;
+    c.bw = pc.bw;
+    c.part = syrk;
+    c.sync = sync;
+    c.init = init;
+    return c;
+}
+
 int Engine::step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int* flag) {
     if (ev0) HIPCHK(hipEventRecord(ev0, s));
     HIPCHK(launch_pass(a, pc, s));
     if (ev1) HIPCHK(hipEventRecord(ev1, s));
-    if (a.want_mid) HIPCHK(launch_syrk(syrk_args(a.C, a.Uout ? a.Uout : a.U, a.Vout ? a.Vout : a.V), s));
+    const void* U = a.Uout ? a.Uout : a.U;
+    const void* V = a.Vout ? a.Vout : a.V;
+    if (cg_iters > 0 && control) {
+        // matrix-free Newton directions: no assembled H; the control step
+        // opens a CG solve when a Newton direction is needed, the CG launches
+        // do nothing otherwise
+        HIPCHK(launch_control(state, sl, rl, red, nullptr, s));
+        HIPCHK(launch_cg_iter(cg_args(a.C, U, V, 1), s));
+        const CgArgs it = cg_args(a.C, U, V, 0);
+        for (int k = 0; k < cg_iters; ++k) HIPCHK(launch_cg_iter(it, s));
+        HIPCHK(launch_cg_finish(state, sl, flag, s));
+        return MEB_OK;
+    }
+    if (a.want_mid) HIPCHK(launch_syrk(syrk_args(a.C, U, V), s));
     if (control) HIPCHK(launch_control(state, sl, rl, red, flag, s));
     return MEB_OK;
 }
@@ -218,11 +255,11 @@ void SolveWs::setup(int64_t m, int d, const meb_options* o) {
     scan.setup(m, d);
 }
 
-size_t solve_ws_bytes(int64_t m, int d, const meb_options* o) {
+size_t solve_ws_bytes(int64_t m, int d, int in_dtype, const meb_options* o) {
     SolveWs w;
     w.setup(m, d, o);
     Sizer s;
-    w.carve(s, m, d, o, true);
+    w.carve(s, m, d, o, true, in_dtype);
     return s.off + ALIGN;
 }
 
@@ -340,6 +377,25 @@ int run_screen(const void* C, const void* R, int64_t m, int d, int dtype, double
 
 }  // namespace
 
+// Arithmetic of the Hessian contraction for a run of precision dtype.
+int syrk_arith(int hess, int dtype, int d) {
+    if (dtype == MEB_F64) {
+        if (hess == MEB_HESS_F64) return SYRK_VEC;
+        if (hess == MEB_HESS_MFMA_F64) return SYRK_MFMA_F64;
+        return d >= 128 ? SYRK_MFMA_F64 : SYRK_VEC;  // AUTO (and the FP32-run choices)
+    }
+    switch (hess) {
+        case MEB_HESS_MFMA_F32:
+            return SYRK_MFMA_F32;
+        case MEB_HESS_MFMA_BF16:
+            return SYRK_MFMA_BF16;
+        case MEB_HESS_AUTO:
+            return d >= 256 ? SYRK_MFMA_BF16 : SYRK_VEC;
+        default:
+            return SYRK_VEC;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Job
 // ---------------------------------------------------------------------------
@@ -352,8 +408,8 @@ Job::~Job() {
     if (keep_pin) (void)hipHostFree(keep_pin);
 }
 
-int Job::init(const void* C_, const void* R_, int64_t m_, int d_, const meb_options* o_, void* ws, size_t ws_bytes,
-              double* pin_base, double* U_out_, double* V_out_) {
+int Job::init(const void* C_, const void* R_, int64_t m_, int d_, int in_dtype, const meb_options* o_, void* ws,
+              size_t ws_bytes, double* pin_base, double* U_out_, double* V_out_) {
     C = C_;
     R = R_;
     m = m_;
@@ -363,8 +419,15 @@ int Job::init(const void* C_, const void* R_, int64_t m_, int d_, const meb_opti
     V_out = V_out_;
     w.setup(m, d, &o);
     Arena ar{(char*)ws, ws_bytes, 0};
-    w.carve(ar, m, d, &o, R != nullptr);
+    w.carve(ar, m, d, &o, R != nullptr, in_dtype);
     if (!ar.ok()) return fail(MEB_ERR_WORKSPACE, "workspace too small");
+    if (in_dtype == MEB_F32) {
+        // every phase reads the FP64 copy that start() writes
+        C_in = C;
+        R_in = R;
+        C = w.Cin;
+        R = R ? (const void*)w.Rin : nullptr;
+    }
     pin.carve(pin_base, d);
     memset(&st, 0, sizeof(st));
     ph = JobPhase::Start;
@@ -376,11 +439,16 @@ int Job::start(hipStream_t s) {
     // scale L = max_i ||c_i - c_1|| + r_i around the first center (read on
     // the device from row 0), and in mixed mode the shifted FP32 copy
     t_mark = now_ms();
+    if (C_in) {
+        HIPCHK(launch_widen_f32(static_cast<const float*>(C_in), w.Cin, m * (int64_t)d, s));
+        if (R_in) HIPCHK(launch_widen_f32(static_cast<const float*>(R_in), w.Rin, m, s));
+    }
     const double* c1_dev = static_cast<const double*>(C);
-    if (o.mode == MEB_MODE_MIXED)
-        CHK(enq_prepare((const double*)C, (const double*)R, m, d, c1_dev, w.C32, w.R32, w.scan, pin.scal, s));
-    else
-        CHK(enq_check(C, R, m, d, MEB_F64, 0.0, c1_dev, INFINITY, w.scan, nullptr, 0, pin.scal, s));
+    // the preparation pass also flags a negative radius or a non-finite value
+    // (the scale comes back as +inf); the FP32 copy only in mixed mode
+    const bool mixed = o.mode == MEB_MODE_MIXED;
+    CHK(enq_prepare((const double*)C, (const double*)R, m, d, c1_dev, mixed ? w.C32 : nullptr,
+                    mixed ? w.R32 : nullptr, w.scan, pin.scal, s));
     HIPCHK(hipMemcpyAsync(pin.c1, C, sizeof(double) * d, hipMemcpyDeviceToHost, s));
     ph = JobPhase::WaitPrep;
     return MEB_OK;
@@ -389,6 +457,7 @@ int Job::start(hipStream_t s) {
 int Job::begin_run(int id, Engine& eng, const void* Cr, const void* Rr, void* U, void* V, const double* x0,
                    double sigma_raw, double tol, double eps, hipStream_t s) {
     const int n1 = d + 1;
+    eng.mm = syrk_arith(o.hess, eng.dtype, d);
     const StateLayout& sl = eng.sl;
     double* h = pin.init;
     memset(h, 0, sizeof(double) * sl.H);
@@ -408,6 +477,14 @@ int Job::begin_run(int id, Engine& eng, const void* Cr, const void* Rr, void* U,
     h[S_EPS] = eps;
     h[S_BEST_KKT] = INFINITY;
     h[S_VERBOSE] = o.verbose;
+    // first-order inner solves in the early outer iterations of ripALM: the
+    // plain FP64 run, or the mixed path's screening run (its FP64 run is a
+    // warm-started continuation near the solution)
+    h[S_FO_OUTER] = (o.mode == MEB_MODE_FP64 || id == 0) ? o.first_order_outer : 0;
+    h[S_CG] = o.newton == MEB_NEWTON_CG ? 1.0 : 0.0;
+    h[S_CG_MAX] = o.cg_max_iter;
+    h[S_CG_TOL] = o.cg_tol;
+    eng.cg_iters = o.newton == MEB_NEWTON_CG ? o.cg_max_iter : 0;
     for (int k = 0; k < n1; ++k) {
         h[sl.xb + k] = x0[k];
         h[sl.xbar + k] = x0[k];
@@ -503,7 +580,7 @@ int Job::on_ready(hipStream_t s) {
             L = pin.scal[0];
             c1.assign(pin.c1, pin.c1 + d);
             st.L = L;
-            if (!std::isfinite(L)) return fail(MEB_ERR_NUMERIC, "non-finite input");
+            if (!std::isfinite(L)) return fail(MEB_ERR_ARG, "input holds a negative radius or a non-finite value");
             if (!(L > 0)) {
                 // every ball is the point c_1
                 xfin.assign(n1, 0.0);
@@ -553,6 +630,8 @@ int Job::on_ready(hipStream_t s) {
                 st.mid_rows_max[0] = hh[S_MAXK];
                 st.newton_shifted[0] = (int)hh[S_NSHIFT];
                 st.inner_breaks[0] = (int)hh[S_NBREAK];
+                st.first_order_steps[0] = (int)hh[S_NFO];
+                st.cg_iterations[0] = (int)hh[S_NCG];
             } else {
                 st.outer[1] += (int)hh[S_K];
                 st.inner[1] += (int)hh[S_NINNER];
@@ -565,6 +644,8 @@ int Job::on_ready(hipStream_t s) {
                 st.mid_rows_max[1] = std::max(st.mid_rows_max[1], hh[S_MAXK]);
                 st.newton_shifted[1] += (int)hh[S_NSHIFT];
                 st.inner_breaks[1] += (int)hh[S_NBREAK];
+                st.first_order_steps[1] += (int)hh[S_NFO];
+                st.cg_iterations[1] += (int)hh[S_NCG];
             }
             if (rstatus < 0) return fail(MEB_ERR_NUMERIC, "numeric failure in the solver run");
             for (int k = 0; k < n1; ++k)
@@ -768,8 +849,8 @@ int check_common(const void* C, int64_t m, int32_t d, int32_t dtype) {
     if (m > 0x7fffffffLL) return fail(MEB_ERR_ARG, "m must be < 2^31");
     if (d < 1 || d > MEB_MAX_D) return fail(MEB_ERR_ARG, "d must be in [1, MEB_MAX_D]");
     if (dtype != MEB_F64 && dtype != MEB_F32) return fail(MEB_ERR_ARG, "bad dtype");
-    const size_t es = dtype_size(dtype);
-    if ((uintptr_t)C % es) return fail(MEB_ERR_ARG, "C is not aligned to its element size");
+    // rows are read with 16-byte loads and 16-byte LDS copies where d allows
+    if ((uintptr_t)C % 16) return fail(MEB_ERR_ARG, "C is not 16-byte aligned");
     if ((d % 2 == 1) && d > 1024) return fail(MEB_ERR_UNSUPPORTED, "odd d above 1024 is not supported");
     return MEB_OK;
 }
@@ -779,6 +860,11 @@ int check_solve_options(const meb_options* o) {
     if (!(o->sigma0 > 0) || !(o->tau > 0) || !(o->sigma_growth >= 1) || !(o->sigma_max >= o->sigma0))
         return fail(MEB_ERR_ARG, "bad sigma / tau options");
     if (o->mode != MEB_MODE_FP64 && o->mode != MEB_MODE_MIXED) return fail(MEB_ERR_ARG, "bad mode");
+    if (o->hess < MEB_HESS_AUTO || o->hess > MEB_HESS_MFMA_BF16) return fail(MEB_ERR_ARG, "bad hess");
+    if (o->first_order_outer < 0) return fail(MEB_ERR_ARG, "first_order_outer must be >= 0");
+    if (o->newton != MEB_NEWTON_DENSE && o->newton != MEB_NEWTON_CG) return fail(MEB_ERR_ARG, "bad newton");
+    if (o->newton == MEB_NEWTON_CG && (o->cg_max_iter < 1 || o->cg_max_iter > 1000 || !(o->cg_tol > 0)))
+        return fail(MEB_ERR_ARG, "cg_max_iter must be in [1, 1000] and cg_tol > 0");
     return MEB_OK;
 }
 
@@ -799,7 +885,7 @@ int meb_default_options(meb_options* o) {
     o->sigma_growth = 5.0;
     o->sigma_max = 1e5;
     o->tau = 1.0;
-    o->tol_kkt = 1e-8;
+    o->tol_kkt = 1e-9;
     o->tol_kkt_low = 1e-2;
     o->tol_red = 0.03;
     o->eps_feas_rel = 1e-10;
@@ -811,6 +897,10 @@ int meb_default_options(meb_options* o) {
     o->stall_outer = 3;
     o->verbose = 0;
     o->profile = 0;
+    o->hess = MEB_HESS_AUTO;
+    o->newton = MEB_NEWTON_DENSE;
+    o->cg_max_iter = 20;
+    o->cg_tol = 1e-2;
     return MEB_OK;
 }
 
@@ -822,7 +912,7 @@ int meb_workspace_size(int64_t m, int32_t d, int32_t dtype, const meb_options* o
     if (dtype != MEB_F64 && dtype != MEB_F32) return fail(MEB_ERR_ARG, "bad dtype");
     meb_options def;
     meb_default_options(&def);
-    *bytes = solve_ws_bytes(m, d, opts ? opts : &def);
+    *bytes = solve_ws_bytes(m, d, dtype, opts ? opts : &def);
     return MEB_OK;
 }
 
@@ -847,6 +937,10 @@ int meb_al_eval(const void* C, const void* R, const void* U, const void* V, int6
         return fail(MEB_ERR_ARG, "n_eta must be in [0, 9] with etas and psi_trial given");
     if ((want & MEB_WANT_MULT) && (!U_new || !V_new)) return fail(MEB_ERR_ARG, "MULT needs U_new and V_new");
     if ((U == nullptr) != (V == nullptr)) return fail(MEB_ERR_ARG, "U and V must both be given or both NULL");
+    if ((uintptr_t)V % 16 || (uintptr_t)V_new % 16) return fail(MEB_ERR_ARG, "V and V_new must be 16-byte aligned");
+    const size_t es = dtype_size(dtype);
+    if ((uintptr_t)R % es || (uintptr_t)U % es || (uintptr_t)U_new % es)
+        return fail(MEB_ERR_ARG, "R, U and U_new must be aligned to their element size");
     size_t need;
     CHK(meb_eval_workspace_size(m, d, dtype, &need));
     if (!ws || ws_bytes < need) return fail(MEB_ERR_WORKSPACE, "workspace too small");
@@ -885,7 +979,9 @@ int meb_al_eval(const void* C, const void* R, const void* U, const void* V, int6
     CHK(e.reset_sync(s));
     HIPCHK(launch_pass(a, e.pc, s));
     if (want & MEB_WANT_HESS) {
-        // the contraction assembles H into the state
+        // the contraction assembles H into the state, in the arithmetic that
+        // bits 8..10 of want select (MEB_HESS_*, AUTO when zero)
+        e.mm = syrk_arith((int)((want >> 8) & 7u), dtype, d);
         SyrkArgs sa = e.syrk_args(C, U, V);
         sa.skip_k = INFINITY;
         HIPCHK(launch_syrk(sa, s));
@@ -925,6 +1021,50 @@ int meb_al_eval(const void* C, const void* R, const void* U, const void* V, int6
         kkt[3] = rh[rl.kmax + 1];
         kkt[4] = rh[rl.kmax + 2];
     }
+    return MEB_OK;
+}
+
+int meb_hess_vec(const void* C, const void* R, const void* U, const void* V, int64_t m, int32_t d, int32_t dtype,
+                 const double* x, double sigma, double tau, const double* q, double* Hq, void* ws, size_t ws_bytes,
+                 void* stream) {
+    CHK(check_common(C, m, d, dtype));
+    if (!x || !q || !Hq) return fail(MEB_ERR_ARG, "x, q and Hq are required");
+    if (!(sigma > 0) || !(tau > 0)) return fail(MEB_ERR_ARG, "sigma and tau must be positive");
+    if ((U == nullptr) != (V == nullptr)) return fail(MEB_ERR_ARG, "U and V must both be given or both NULL");
+    if ((uintptr_t)V % 16) return fail(MEB_ERR_ARG, "V must be 16-byte aligned");
+    size_t need;
+    CHK(meb_eval_workspace_size(m, d, dtype, &need));
+    if (!ws || ws_bytes < need) return fail(MEB_ERR_WORKSPACE, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const int n1 = d + 1;
+    Engine e;
+    e.setup(m, d, dtype);
+    Arena ar{(char*)ws, ws_bytes, 0};
+    e.carve(ar);
+    double* out = ar.take<double>(2 * (size_t)n1 + 8);
+    // the state: the evaluation point, and q where the CG search direction lives
+    std::vector<double> h(e.sl.len, 0.0);
+    h[S_MODE] = PM_CG;
+    h[S_SIGMA] = sigma;
+    h[S_SIGMA_NEXT] = sigma;
+    h[S_TAU] = tau;
+    for (int k = 0; k < n1; ++k) h[e.sl.xb + k] = x[k];
+    const int cs = cg_stride(n1);
+    for (int k = 0; k < n1; ++k) h[e.sl.H + 2 * cs + k] = q[k];
+    HIPCHK(hipMemcpyAsync(e.state, h.data(), sizeof(double) * e.sl.len, hipMemcpyHostToDevice, s));
+    PassArgs a = e.args(C, R, const_cast<void*>(U), const_cast<void*>(V));
+    a.force_mode = PM_EVAL;
+    a.want_kkt = 0;
+    a.Uout = nullptr;
+    a.Vout = nullptr;
+    a.want_mid = 1;
+    CHK(e.reset_sync(s));
+    HIPCHK(launch_pass(a, e.pc, s));
+    CgArgs c = e.cg_args(C, U, V, 0);
+    c.out = out;
+    HIPCHK(launch_cg_iter(c, s));
+    HIPCHK(hipMemcpyAsync(Hq, out, sizeof(double) * n1, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     return MEB_OK;
 }
 
@@ -1021,7 +1161,6 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
     meb_default_options(&def);
     const meb_options* o = opts ? opts : &def;
     CHK(check_solve_options(o));
-    if (dtype != MEB_F64) return fail(MEB_ERR_ARG, "meb_solve needs FP64 input");
     size_t need;
     CHK(meb_workspace_size(m, d, dtype, o, &need));
     if (!ws || ws_bytes < need) return fail(MEB_ERR_WORKSPACE, "workspace too small");
@@ -1029,7 +1168,7 @@ int meb_solve(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype,
     double* pin = g_pin.get(JobPin::doubles(d));
     if (!pin) return fail(MEB_ERR_HIP, "pinned host allocation failed");
     Job j;
-    CHK(j.init(C, R, m, d, o, ws, ws_bytes, pin, U_out, V_out));
+    CHK(j.init(C, R, m, d, dtype, o, ws, ws_bytes, pin, U_out, V_out));
     CHK(drive_sync(j, s));
     *r_out = j.r_out;
     memcpy(c_out, j.xfin.data() + 1, sizeof(double) * d);

@@ -192,15 +192,40 @@ __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
 // written as inline assembly: the compiler would otherwise make each of them
 // wait for every copy in flight.
 // ---------------------------------------------------------------------------
-constexpr int DMA_LOADS = 8;                  // dword copies of 256 bytes per block
-constexpr int DMA_BLK = DMA_LOADS * 256;      // bytes per block
-constexpr int DMA_MIN_STAGES = 4;             // blocks per ring: the layout's minimum
+constexpr int DMA_BLK = 2048;                 // bytes per ring block
+// A block is copied by DMA_BLK / (64 x width) instructions: 16-byte copies
+// (global_load_lds_dwordx4, gfx950) for instances whose row loads are 16
+// bytes wide (FP32 rows with d % 4 == 0, FP64 rows with d even: every wave's
+// byte range then starts 16-byte aligned), dword copies otherwise.
+template <typename T, int VEC>
+__host__ __device__ constexpr int dma_width() {
+    return VEC * (int)sizeof(T) == 16 ? 16 : 4;
+}
+template <typename T, int VEC>
+__host__ __device__ constexpr int dma_loads() {
+    return DMA_BLK / (WAVE * dma_width<T, VEC>());
+}
+constexpr int DMA_MIN_STAGES = 4;  // blocks per ring: the layout's minimum
 // and maximum.  A wave's outstanding vector-memory operations are counted in
 // six bits (at most 63), and the waits above count every copy in flight:
-// four blocks of eight copies plus the radii and multipliers of the next
-// batch stay below that; eight blocks (64 copies and more) would not.
-constexpr int DMA_MAX_STAGES = 4;
-static_assert(DMA_MAX_STAGES * DMA_LOADS + 4 <= 63, "copies in flight fit the vector-memory counter");
+// with dword copies four blocks of eight copies plus the radii and
+// multipliers of the next batch stay below that (eight blocks would not);
+// with 16-byte copies sixteen blocks of two copies do.
+constexpr int DMA_MAX_STAGES_DWORD = 4;
+constexpr int DMA_MAX_STAGES_B128 = 16;
+static_assert(DMA_MAX_STAGES_DWORD * (DMA_BLK / 256) + 4 <= 63, "dword copies in flight fit the counter");
+static_assert(DMA_MAX_STAGES_B128 * (DMA_BLK / 1024) + 4 <= 63, "16-byte copies in flight fit the counter");
+// one LDS-DMA copy of W bytes per lane (W a literal for the builtin)
+template <int W>
+__device__ __forceinline__ void dma_copy(const void* src, void* dst) {
+    if constexpr (W == 16)
+        __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+    else
+        __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
+}
+__host__ __device__ constexpr int dma_max_stages(int row_load_bytes) {
+    return row_load_bytes == 16 ? DMA_MAX_STAGES_B128 : DMA_MAX_STAGES_DWORD;
+}
 
 // LDS byte address of a pointer into shared memory
 __device__ __forceinline__ uint32_t lds_addr(const void* p) {
@@ -215,20 +240,47 @@ __device__ __forceinline__ void wait_vm() {
 }
 
 // wait for a copy that has at least `after` vector-memory loads of this wave
-// issued after it (loads complete in issue order)
+// issued after it (loads complete in issue order).  The count waited for is
+// `after` rounded down to one of the steps below (waiting for more loads
+// than needed is always safe).
 __device__ __forceinline__ void wait_vm_after(int64_t after) {
-    if (after >= 63)
-        wait_vm<63>();
-    else if (after >= 48)
-        wait_vm<48>();
-    else if (after >= 32)
-        wait_vm<32>();
-    else if (after >= 16)
-        wait_vm<16>();
-    else if (after >= 8)
-        wait_vm<8>();
-    else
+    if (after >= 32) {
+        if (after >= 63)
+            wait_vm<63>();
+        else if (after >= 48)
+            wait_vm<48>();
+        else if (after >= 40)
+            wait_vm<40>();
+        else
+            wait_vm<32>();
+    } else if (after >= 16) {
+        if (after >= 28)
+            wait_vm<28>();
+        else if (after >= 24)
+            wait_vm<24>();
+        else if (after >= 20)
+            wait_vm<20>();
+        else
+            wait_vm<16>();
+    } else if (after >= 8) {
+        if (after >= 14)
+            wait_vm<14>();
+        else if (after >= 12)
+            wait_vm<12>();
+        else if (after >= 10)
+            wait_vm<10>();
+        else
+            wait_vm<8>();
+    } else if (after >= 4) {
+        if (after >= 6)
+            wait_vm<6>();
+        else
+            wait_vm<4>();
+    } else if (after >= 2) {
+        wait_vm<2>();
+    } else {
         wait_vm<0>();
+    }
 }
 
 template <int BYTES>
@@ -1068,25 +1120,28 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
             const uint32_t zero_addr =
                 lds_addr(reinterpret_cast<unsigned char*>(lds) + pass_lds_zero_offset<T, VEC, NLMAX>(d, stages));
             const char* Cb = static_cast<const char*>(a.C) + S0;
-            const int64_t Clim = total - 4 - S0;  // last dword of C, relative to S0
+            constexpr int DW = dma_width<T, VEC>();  // bytes per lane and copy
+            constexpr int DL = dma_loads<T, VEC>();  // copies per block
+            constexpr int DSTEP = DW * WAVE;          // bytes per copy
+            const int64_t Clim = total - DW - S0;     // last DW-byte word of C, relative to S0
             int issued = 0, landed = -1, nld = 0;
             auto issue = [&]() {
                 const int k = issued++;
                 unsigned char* dst = ring + (k & (stages - 1)) * DMA_BLK;
                 const char* bk = Cb + (int64_t)k * DMA_BLK;  // wave-uniform
-                if ((int64_t)k * DMA_BLK + DMA_BLK - 4 <= Clim) {
+                if ((int64_t)k * DMA_BLK + DMA_BLK - DW <= Clim) {
 #pragma unroll
-                    for (int q = 0; q < DMA_LOADS; ++q)
-                        __builtin_amdgcn_global_load_lds(bk + q * 256 + lane * 4, dst + q * 256, 4, 0, 0);
-                } else {  // the block passes the end of C: clamp to its last dword
+                    for (int q = 0; q < DL; ++q)
+                        dma_copy<DW>(bk + q * DSTEP + lane * DW, dst + q * DSTEP);
+                } else {  // the block passes the end of C: clamp to its last word
 #pragma unroll
-                    for (int q = 0; q < DMA_LOADS; ++q) {
-                        int64_t o = (int64_t)k * DMA_BLK + q * 256 + lane * 4;
+                    for (int q = 0; q < DL; ++q) {
+                        int64_t o = (int64_t)k * DMA_BLK + q * DSTEP + lane * DW;
                         o = o <= Clim ? o : Clim;
-                        __builtin_amdgcn_global_load_lds(Cb + o, dst + q * 256, 4, 0, 0);
+                        dma_copy<DW>(Cb + o, dst + q * DSTEP);
                     }
                 }
-                nld += DMA_LOADS;
+                nld += DL;
             };
             // relative bytes [0, end) in LDS: every block up to the one holding
             // byte end - 1 has landed
@@ -1094,7 +1149,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                 const int need = (end - 1) / DMA_BLK;
                 if (landed < need) {
                     landed = need;
-                    wait_vm_after((issued - 1 - landed) * DMA_LOADS);
+                    wait_vm_after((issued - 1 - landed) * DL);
                 }
             };
             // relative bytes below `done_to` are consumed: refill their blocks
@@ -1454,9 +1509,15 @@ __global__ __launch_bounds__(PASS_THREADS) void pass_batch_kernel(const BatchIte
     pass_dispatch<T, VEC, NLMAX, TRL>(it.pa, it.pc, blockIdx.x - L.off[k]);
 }
 
+// LDS of one compute unit (gfx950)
+constexpr size_t LDS_PER_CU = 160 * 1024;
+
 // Kernels that take more than 64 KiB of dynamic LDS opt in to the size.
+// Sizes above a compute unit's LDS are refused here, before the runtime
+// would record an error that a later hipGetLastError would report.
 static hipError_t ensure_dynamic_lds(const void* fn, size_t bytes) {
     if (bytes <= 64 * 1024) return hipSuccess;
+    if (bytes > LDS_PER_CU) return hipErrorInvalidValue;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 

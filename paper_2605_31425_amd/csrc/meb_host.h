@@ -71,6 +71,10 @@ struct Sizer {
 };
 
 int device_cus();
+// shape, dtype, pointer and alignment checks shared by the entry points
+int check_common(const void* C, int64_t m, int32_t d, int32_t dtype);
+// contraction arithmetic (SYRK_*) of a run of precision dtype under option hess
+int syrk_arith(int hess, int dtype, int d);
 double now_ms();
 inline size_t dtype_size(int dtype) { return dtype == MEB_F64 ? 8 : 4; }
 
@@ -85,7 +89,9 @@ struct Engine {
     PassConfig pc{};
     StateLayout sl{};
     RecLayout rl{};
-    int ntile = 0, ksplit = 0;
+    int ksplit = 0;
+    int mm = 0;         // contraction arithmetic (SYRK_*), chosen per run
+    int cg_iters = 0;   // > 0: matrix-free Newton directions with this many CG launches per step
     double* state = nullptr;
     double* rec = nullptr;
     double* red = nullptr;
@@ -110,12 +116,12 @@ struct Engine {
         mid_cnt = a.template take<int32_t>(pc.nwaves);
         act_idx = a.template take<int32_t>(cap);
         act_coef = a.template take<double>(cap * ACT_NC);
-        const size_t pairs = (size_t)ntile * (ntile + 1) / 2;
-        syrk = a.template take<double>((size_t)ksplit * pairs * syrk_tile() * syrk_tile());
+        syrk = a.template take<double>(syrk_partial_doubles(d, ksplit));
         sync = a.template take<int>(SYNC_LEN);
     }
     PassArgs args(const void* C, const void* R, void* U, void* V) const;
     SyrkArgs syrk_args(const void* C, const void* U, const void* V) const;
+    CgArgs cg_args(const void* C, const void* U, const void* V, int init) const;
     // the multi-instance table entry of a run over (C, R, U, V)
     BatchItem item(const PassArgs& a, int* flag) const;
     // pass (with its reduction) + contraction (with the H assembly)
@@ -196,9 +202,15 @@ struct SolveWs {
     double* Rred = nullptr;
     int64_t* keep = nullptr;  // retained indices (device)
     int64_t* viol = nullptr;  // violated indices (device)
+    double* Cin = nullptr;    // FP64 copy of FP32 input (widened exactly), else unused
+    double* Rin = nullptr;
     void setup(int64_t m, int d, const meb_options* o);
     template <typename A>
-    void carve(A& a, int64_t m, int d, const meb_options* o, bool has_r) {
+    void carve(A& a, int64_t m, int d, const meb_options* o, bool has_r, int in_dtype) {
+        if (in_dtype == MEB_F32) {
+            Cin = a.template take<double>((size_t)m * d);
+            Rin = has_r ? a.template take<double>((size_t)m) : nullptr;
+        }
         e64.carve(a);
         scan.carve(a);
         U64 = a.template take<double>((size_t)m);
@@ -217,7 +229,7 @@ struct SolveWs {
     }
 };
 
-size_t solve_ws_bytes(int64_t m, int d, const meb_options* o);
+size_t solve_ws_bytes(int64_t m, int d, int in_dtype, const meb_options* o);
 
 // ---------------------------------------------------------------------------
 // Pinned staging of one job (doubles): readback targets and the sources of
@@ -252,6 +264,8 @@ struct Job {
     // request
     const void* C = nullptr;
     const void* R = nullptr;
+    const void* C_in = nullptr;  // the caller's FP32 input, when widened
+    const void* R_in = nullptr;
     int64_t m = 0;
     int d = 0;
     meb_options o{};
@@ -297,8 +311,9 @@ struct Job {
     ~Job();
 
     // Validates and carves the workspace; `pin_base` holds JobPin::doubles(d).
-    int init(const void* C, const void* R, int64_t m, int d, const meb_options* o, void* ws, size_t ws_bytes,
-             double* pin_base, double* U_out, double* V_out);
+    // C and R are FP64, or FP32 (in_dtype), which the job first widens into the workspace.
+    int init(const void* C, const void* R, int64_t m, int d, int in_dtype, const meb_options* o, void* ws,
+             size_t ws_bytes, double* pin_base, double* U_out, double* V_out);
     int start(hipStream_t s);     // Start -> WaitPrep
     int on_ready(hipStream_t s);  // a Wait* phase's readback has completed
     int end_run(hipStream_t s);   // Run -> WaitRunEnd

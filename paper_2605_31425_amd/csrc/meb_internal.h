@@ -58,7 +58,21 @@ enum StateSlot : int {
     S_FLOOR,         // 1 if the last inner solve of a low-precision run stopped at the rounding floor
     S_NSHIFT,        // Newton systems solved with a raised diagonal (breakdown guard)
     S_NBREAK,        // inner solves ended because no shift made the factorization succeed
-    S_NSCALAR = 48
+    S_FO_OUTER,      // outer iterations (from the first) whose inner solve is first-order
+    S_FO_ON,         // 1 while the current inner solve is the accelerated gradient method
+    S_FO_PHASE,      // 1 after a gradient step was proposed (its trial pass is next)
+    S_FO_T,          // momentum sequence t_k of the accelerated gradient method
+    S_FO_STEP,       // current gradient step size s (raw units)
+    S_NFO,           // first-order iterations in total
+    S_CG,            // 1: Newton directions by preconditioned CG with Hessian-vector products
+    S_CG_MAX,        // CG iterations per Newton direction
+    S_CG_TOL,        // relative residual at which CG stops
+    S_CG_IT,         // CG iterations of the current direction
+    S_CG_DONE,       // 1 once the current CG solve has stopped
+    S_CG_RZ,         // r^T z of the current CG iteration
+    S_CG_B2,         // ||b||^2 of the current system
+    S_NCG,           // CG iterations in total
+    S_NSCALAR = 64
 };
 
 struct StateLayout {
@@ -68,7 +82,7 @@ struct StateLayout {
     int xbar;    // proximal center
     int ab;      // auxiliary sequence (alpha, beta)
     int gb;      // gradient at xb
-    int tmp;     // scratch vector
+    int tmp;     // previous iterate of the accelerated gradient method
     int H;       // (d+1)^2 Hessian / Cholesky factor
     int len;
     static StateLayout make(int d) {
@@ -140,8 +154,37 @@ struct RecLayout {
 // V row is written).
 constexpr int ACT_NC = 7;
 
-// Pass modes.
-enum PassMode : int { PM_EVAL = 0, PM_MULT = 1, PM_DONE = 2 };
+static_assert(S_NCG < S_NSCALAR, "state scalars fit their slots");
+
+// Pass modes.  PM_CG: a Newton direction is being computed by conjugate
+// gradients (set by the control step, cleared by the CG finish step).
+enum PassMode : int { PM_EVAL = 0, PM_MULT = 1, PM_DONE = 2, PM_CG = 3 };
+
+// Arguments of the matrix-free Newton solve (conjugate gradients with
+// Hessian-vector products over the mid list of the last pass).
+struct CgArgs {
+    const void* C;
+    const void* U;
+    const void* V;
+    int d;
+    int dtype;
+    double* state;
+    StateLayout sl;
+    const double* red;          // reduced record of the pass
+    RecLayout rl;
+    const int32_t* mid_cnt;
+    const int32_t* mid_idx;
+    const double* mid_coef;
+    int nwaves;
+    int64_t bw;
+    double* part;               // CG_BLOCKS x d block partial sums
+    int* sync;                  // arrival counter (SYNC_CG)
+    int init;                   // 1: the preconditioner pass that opens a solve
+    double* out;                // non-null: write H p here (d + 1) instead of a CG update
+};
+constexpr int CG_BLOCKS = 512;  // blocks of a Hessian-vector product
+// CG vectors, in the Hessian's place of the state (unused by this solver)
+__host__ __device__ inline int cg_stride(int n1) { return (n1 + 7) & ~7; }
 
 // Kernel configuration chosen by the host for (d, dtype).
 struct PassConfig {
@@ -196,6 +239,7 @@ constexpr int SYNC_GROUPS = 64;    // at most RED_GROUP * SYNC_GROUPS pass block
 constexpr int SYNC_TOP = SYNC_GROUPS;
 constexpr int SYNC_SYRK = 128;     // first tile-pair counter
 constexpr int SYNC_LEN = 4096;
+constexpr int SYNC_CG = SYNC_LEN - 1;  // arrival counter of a Hessian-vector product
 
 struct SyrkArgs {
     const void* C;
@@ -218,7 +262,21 @@ struct SyrkArgs {
     int tile;
     int ntile;           // tiles per dimension
     double skip_k;       // in a line-search pass, skip when K exceeds this
+    int mm;              // arithmetic: SYRK_VEC, SYRK_MFMA_F64, SYRK_MFMA_F32, SYRK_MFMA_BF16
 };
+// contraction arithmetic (SyrkArgs::mm) and its tile width
+enum : int { SYRK_VEC = 0, SYRK_MFMA_F64 = 1, SYRK_MFMA_F32 = 2, SYRK_MFMA_BF16 = 3 };
+inline int syrk_tile_of(int mm) { return mm == SYRK_VEC ? 32 : 64; }
+// partial-tile doubles an engine reserves for d (the larger of the two tilings)
+inline size_t syrk_partial_doubles(int d, int ksplit) {
+    size_t best = (size_t)CG_BLOCKS * d;  // the CG products' block sums share the buffer
+    for (int t : {32, 64}) {
+        const size_t nt = (size_t)(d + t - 1) / t;
+        const size_t v = (size_t)ksplit * nt * (nt + 1) / 2 * t * t;
+        if (v > best) best = v;
+    }
+    return best;
+}
 
 // One instance of the multi-instance step: the arguments of its pass,
 // contraction and control kernels.  Lives in a device table indexed by slot;
@@ -268,8 +326,13 @@ hipError_t launch_pass_eval(const PassArgs& a, const PassConfig& cfg, hipStream_
 // (with the diagonal and the r row and column from the record) into the
 // state, unless the contraction is skipped.
 hipError_t launch_syrk(const SyrkArgs& a, hipStream_t s);
+// one conjugate-gradient iteration (or, with a.init, the opening
+// preconditioner pass); nothing unless the state's mode is PM_CG and the
+// solve has not stopped
+hipError_t launch_cg_iter(const CgArgs& a, hipStream_t s);
+// the direction from a finished CG solve; `flag` as for the control step
+hipError_t launch_cg_finish(double* state, StateLayout sl, int* flag, hipStream_t s);
 int syrk_ksplit(int d);
-int syrk_tile();
 hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag_host_mapped,
                           hipStream_t s);
 // g of a single evaluation, and a copy of the H assembled in the state
@@ -282,10 +345,18 @@ struct ScanCfg {
     int nwaves, blocks;
 };
 ScanCfg scan_config(int64_t m, int d, int num_cu);
+// Placement of a scan's hits: with offs, hit k of wave w goes to
+// seg[offs[w] + k] if below cap (offs from a counting pass), and the scan
+// does nothing if *gate is zero; without, into the wave's own segment.
+struct ScanPlace {
+    const int64_t* offs = nullptr;
+    int64_t cap = 0;
+    const int64_t* gate = nullptr;
+};
 // mode 0: feasibility, 1: screening, 2: FP32 preparation (see meb_kernels.hip)
 hipError_t launch_scan(int mode, const void* C, const void* R, int64_t m, int d, int dtype, const double* x,
                        double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c, double* wmax,
-                       int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s);
+                       int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s, const ScanPlace& pl = ScanPlace());
 hipError_t launch_scan_finalize(const int64_t* wcnt, const double* wmax, const int64_t* warg, int nw, int64_t* offs,
                                 int64_t* total, double* out_max, int64_t* out_arg, hipStream_t s);
 hipError_t launch_scan_copy(const int64_t* seg, const int64_t* wcnt, const int64_t* offs, int nw, int64_t bw,
@@ -299,6 +370,8 @@ hipError_t launch_dense_mult(const void* U, const void* V, int dtype, int64_t m,
                              double* V_out, hipStream_t s);
 hipError_t launch_chol_solve(int n, double* A, double* b, int* info, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
+// dst[k] = (double)src[k] (exact), k < n
+hipError_t launch_widen_f32(const float* src, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s);
 
 // Device-to-device copies between state slots and small vectors are done

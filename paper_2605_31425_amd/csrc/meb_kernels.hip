@@ -22,180 +22,160 @@ namespace meb {
 // (tile pair 0 also writes the r row and column).
 // ---------------------------------------------------------------------------
 
-constexpr int SYRK_T = 32;
 constexpr int SYRK_KB = 32;     // mid balls staged per step
 constexpr int SYRK_KSPLIT = 8;  // blocks along the mid list per tile pair
 constexpr int SYRK_SEGS = 1024; // most wave segments one block walks
-
-int syrk_tile() { return SYRK_T; }
+constexpr int SYRK_MT = 64;     // tile width of the matrix-core contraction
+// row stride (elements) of its staged rows: k padded by 16 bytes
+template <int MI>
+__host__ __device__ constexpr int syrk_ldk() {
+    return SYRK_KB + (MI == 0 ? 2 : (MI == 1 ? 4 : 8));
+}
 
 int syrk_ksplit(int d) {
     (void)d;
     return SYRK_KSPLIT;
 }
 
-template <typename T>
-__device__ __forceinline__ void syrk_body(const SyrkArgs& a, int bx, int by, int npairs) {
-    __shared__ double sI[SYRK_KB][SYRK_T + 1];
-    __shared__ double sJ[SYRK_KB][SYRK_T + 1];
-    __shared__ double cf[SYRK_KB];
-    __shared__ int32_t ix[SYRK_KB];
-    __shared__ int32_t pref[SYRK_SEGS + 1];
-    __shared__ int s_last;
+// LDS of one contraction block (both arithmetics carve it)
+constexpr size_t SYRK_SMEM = 44 * 1024;
+
+// Per-block context: the tile pair, this block's share of the mid list (the
+// exclusive prefix of its wave segments' counts in LDS) and the penalty.
+struct SyrkCtx {
+    int I, J;       // tile row / column (I <= J)
+    int w0, nseg;   // this block's wave segments
+    int total;      // mid entries in them
+    double sig;
+    bool have_dir;
+};
+
+// Returns false when the contraction is skipped or the run is done.
+__device__ __forceinline__ bool syrk_prologue(const SyrkArgs& a, int bx, int by, int32_t* pref, SyrkCtx& c) {
+    __shared__ int wtot[256 / WAVE];
     double* st = a.state;
     const int mode = (int)st[S_MODE];
-    if (mode == PM_DONE) return;
-    const int d = a.d;
-    const StateLayout sl = a.sl;
+    if (mode == PM_DONE) return false;
     const RecLayout rl = a.rl;
     const double* red = a.red;
-    const bool have_dir = (mode == PM_EVAL) && st[S_HAVE_DIR] != 0.0;
+    c.have_dir = (mode == PM_EVAL) && st[S_HAVE_DIR] != 0.0;
     const double K = red[rl.nm];
-    const bool skip = have_dir && K > a.skip_k;
+    // skipped: in a line-search pass with many rows, and while the
+    // first-order inner solver runs (no Newton system)
+    const bool skip = (c.have_dir && K > a.skip_k) || (mode == PM_EVAL && st[S_FO_ON] != 0.0);
     if (bx == 0 && by == 0 && threadIdx.x == 0) st[S_HSKIP] = skip ? 1.0 : 0.0;
-    if (skip) return;
-    const double sig = (mode == PM_MULT) ? st[S_SIGMA_NEXT] : st[S_SIGMA];
-    const T inv = (T)(1.0 / sig);
+    if (skip) return false;
+    c.sig = (mode == PM_MULT) ? st[S_SIGMA_NEXT] : st[S_SIGMA];
     int p = bx, I = 0;
     while (p >= a.ntile - I) {
         p -= a.ntile - I;
         ++I;
     }
-    const int J = I + p;
-    // this block's wave segments and their exclusive prefix (LDS)
+    c.I = I;
+    c.J = I + p;
     const int per = (a.nwaves + a.ksplit - 1) / a.ksplit;
-    const int w0 = by * per, w1 = min(a.nwaves, w0 + per);
-    const int nseg = max(0, w1 - w0);
+    c.w0 = by * per;
+    const int w1 = min(a.nwaves, c.w0 + per);
+    c.nseg = max(0, w1 - c.w0);
     // exclusive prefix of the segment counts: each thread sums a run of
     // four, the runs are scanned within each wave by shuffles and across the
     // four waves through LDS, then each run is written out
-    {
-        __shared__ int wtot[256 / WAVE];
-        const int q0 = threadIdx.x * 4;
-        const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-        int c[4], t = 0;
+    const int q0 = threadIdx.x * 4;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    int cnt[4], t = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            c[u] = (q0 + u < nseg) ? a.mid_cnt[w0 + q0 + u] : 0;
-            t += c[u];
-        }
-        int inc = t;  // inclusive scan of the runs within the wave
-#pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const int y = __shfl_up(inc, o, WAVE);
-            if (lane >= o) inc += y;
-        }
-        if (lane == WAVE - 1) wtot[wv] = inc;
-        __syncthreads();
-        int before = 0;
-        for (int q = 0; q < wv; ++q) before += wtot[q];
-        int run = before + inc - t;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (q0 + u <= nseg) pref[q0 + u] = run;
-            run += c[u];
-        }
-        // with 4 * 256 segments the closing entry lies past the last run
-        if (threadIdx.x == blockDim.x - 1 && nseg == 4 * (int)blockDim.x) pref[nseg] = run;
-        __syncthreads();
+    for (int u = 0; u < 4; ++u) {
+        cnt[u] = (q0 + u < c.nseg) ? a.mid_cnt[c.w0 + q0 + u] : 0;
+        t += cnt[u];
     }
-    const int total = pref[nseg];
-    const T* C = static_cast<const T*>(a.C);
-    const T* V = static_cast<const T*>(a.V);
-    const T* U = static_cast<const T*>(a.U);
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[2][2] = {{0, 0}, {0, 0}};
-    for (int kb = 0; kb < total; kb += SYRK_KB) {
-        const int nk = min(SYRK_KB, total - kb);
-        __syncthreads();
-        if (threadIdx.x < SYRK_KB) {
-            const int e = kb + threadIdx.x;
-            int32_t id = 0;
-            double c = 0.0;
-            if (threadIdx.x < nk) {
-                // segment holding entry e: the last q with pref[q] <= e
-                int lo = 0, hi = nseg - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (pref[mid] <= e)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
-                }
-                const int64_t pos = (int64_t)(w0 + lo) * a.bw + (e - pref[lo]);
-                id = a.mid_idx[pos];
-                c = a.mid_coef[pos];
-            }
-            ix[threadIdx.x] = id;
-            cf[threadIdx.x] = c;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < SYRK_KB * SYRK_T * 2; e += 256) {
-            const int which = e / (SYRK_KB * SYRK_T);
-            const int r = (e / SYRK_T) % SYRK_KB;
-            const int cc = e % SYRK_T;
-            const int col = (which ? J : I) * SYRK_T + cc;
-            double v = 0.0;
-            if (r < nk && col < d) {
-                const int64_t i = ix[r];
-                const T ck = (T)(st[sl.xb + 1 + col] + (have_dir ? st[sl.dir + 1 + col] : 0.0));
-                const T ek = C[i * d + col] - ck;
-                const T vk = (V && U && U[i] != T(0)) ? V[i * d + col] : T(0);
-                v = (double)(ek + vk * inv);
-            }
-            if (which)
-                sJ[r][cc] = v;
-            else
-                sI[r][cc] = v;
-        }
-        __syncthreads();
-        for (int r = 0; r < nk; ++r) {
-            const double c = cf[r];
-            const double a0 = sI[r][ty], a1 = sI[r][ty + 16];
-            const double b0 = sJ[r][tx] * c, b1 = sJ[r][tx + 16] * c;
-            acc[0][0] += a0 * b0;
-            acc[0][1] += a0 * b1;
-            acc[1][0] += a1 * b0;
-            acc[1][1] += a1 * b1;
-        }
+    int inc = t;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int y = __shfl_up(inc, o, WAVE);
+        if (lane >= o) inc += y;
     }
-    double* out = a.out + ((size_t)by * npairs + bx) * SYRK_T * SYRK_T;
-    st_shared_dev(out + ty * SYRK_T + tx, acc[0][0]);
-    st_shared_dev(out + ty * SYRK_T + tx + 16, acc[0][1]);
-    st_shared_dev(out + (ty + 16) * SYRK_T + tx, acc[1][0]);
-    st_shared_dev(out + (ty + 16) * SYRK_T + tx + 16, acc[1][1]);
+    if (lane == WAVE - 1) wtot[wv] = inc;
+    __syncthreads();
+    int before = 0;
+    for (int q = 0; q < wv; ++q) before += wtot[q];
+    int run = before + inc - t;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (q0 + u <= c.nseg) pref[q0 + u] = run;
+        run += cnt[u];
+    }
+    // with 4 * 256 segments the closing entry lies past the last run
+    if (threadIdx.x == blockDim.x - 1 && c.nseg == 4 * (int)blockDim.x) pref[c.nseg] = run;
+    __syncthreads();
+    c.total = pref[c.nseg];
+    return true;
+}
 
-    // the last block of the tile pair assembles its part of H
+// mid entry e of this block's segments: ball index and coefficient
+__device__ __forceinline__ void syrk_entry(const SyrkArgs& a, const SyrkCtx& c, const int32_t* pref, int e,
+                                           int32_t& id, double& cf) {
+    int lo = 0, hi = c.nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pref[mid] <= e)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int64_t pos = (int64_t)(c.w0 + lo) * a.bw + (e - pref[lo]);
+    id = a.mid_idx[pos];
+    cf = a.mid_coef[pos];
+}
+
+// s_i(col) = (c_i - y)(col) + v_i(col) / sigma, in the working precision,
+// exactly as the pass formed it
+template <typename T>
+__device__ __forceinline__ T syrk_s(const SyrkArgs& a, const T* C, const T* U, const T* V, int64_t i, int col, T yc,
+                                    T inv) {
+    const T ek = C[i * a.d + col] - yc;
+    const T vk = (V && U && U[i] != T(0)) ? V[i * a.d + col] : T(0);
+    return ek + vk * inv;
+}
+
+// The last of the ksplit blocks of a tile pair sums their partial tiles in
+// order and writes its part of H (tile pair 0 also the r row and column).
+__device__ __forceinline__ void syrk_finish(const SyrkArgs& a, const SyrkCtx& c, int bx, int npairs) {
+    __shared__ int s_last;
+    const int T = a.tile;
     published();
     __syncthreads();
     if (threadIdx.x == 0) s_last = arrive(&a.sync[SYNC_SYRK + bx]) == a.ksplit - 1;
     __syncthreads();
     if (!s_last) return;
+    double* st = a.state;
+    const RecLayout rl = a.rl;
+    const double* red = a.red;
+    const int d = a.d;
     const double tau = st[S_TAU];
-    const double base = tau / sig + sig * red[rl.ni];
+    const double base = tau / c.sig + c.sig * red[rl.ni];
     const int n1 = d + 1;
-    double* H = st + sl.H;
-    for (int e = threadIdx.x; e < SYRK_T * SYRK_T; e += blockDim.x) {
-        const int r = e / SYRK_T, c = e % SYRK_T;
-        const int k = I * SYRK_T + r, l = J * SYRK_T + c;
+    double* H = st + a.sl.H;
+    for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+        const int r = e / T, cc = e % T;
+        const int k = c.I * T + r, l = c.J * T + cc;
         if (k >= d || l >= d) continue;
         double part[SYRK_KSPLIT];
 #pragma unroll
         for (int ks = 0; ks < SYRK_KSPLIT; ++ks)
-            part[ks] = ks < a.ksplit ? ld_shared_dev(a.out + ((size_t)ks * npairs + bx) * SYRK_T * SYRK_T + e) : 0.0;
+            part[ks] = ks < a.ksplit ? ld_shared_dev(a.out + ((size_t)ks * npairs + bx) * T * T + e) : 0.0;
         double v = 0.0;
 #pragma unroll
         for (int ks = 0; ks < SYRK_KSPLIT; ++ks) v += part[ks];
         if (k == l) v += base + red[rl.sg];
         H[(1 + k) * n1 + 1 + l] = v;
-        if (I != J) H[(1 + l) * n1 + 1 + k] = v;
+        if (c.I != c.J) H[(1 + l) * n1 + 1 + k] = v;
     }
     if (bx == 0) {
         for (int k = threadIdx.x; k < n1; k += blockDim.x) {
             if (k == 0) {
-                H[0] = base + 0.5 * sig * red[rl.nm];
+                H[0] = base + 0.5 * c.sig * red[rl.nm];
             } else {
-                const double v = 0.5 * sig * red[rl.sw + k - 1];
+                const double v = 0.5 * c.sig * red[rl.sw + k - 1];
                 H[k] = v;
                 H[k * n1] = v;
             }
@@ -204,14 +184,253 @@ __device__ __forceinline__ void syrk_body(const SyrkArgs& a, int bx, int by, int
     if (threadIdx.x == 0) a.sync[SYNC_SYRK + bx] = 0;
 }
 
+// ---------------------------------------------------------------------------
+// Rank-one Hessian contraction  sum_{i in mid} coef_i s_i s_i^T, tiled over
+// the upper triangle of d x d and split over the pass's wave segments of the
+// mid list (no compaction: block y of a tile pair walks the mid entries of
+// waves [y W / S, (y + 1) W / S)).  s_i is recomputed from C and V exactly as
+// the pass computed it.  The last of the S blocks of a tile pair to finish
+// sums their partial tiles in order and writes the tile of H (Section 4):
+//   H_rr = tau/sigma + sigma N_I + sigma/2 N_mid
+//   H_rc = sigma/2 sum_mid s_i / ||s_i||
+//   H_cc = (tau/sigma + sigma N_I + sum_mid gamma_i) I + sum_mid coef_i s_i s_i^T
+// Two arithmetics: FP64 FMAs from LDS (32 x 32 tiles, 2 x 2 outputs per
+// thread), or matrix cores (64 x 64 tiles, a 32 x 32 quadrant per wave) with
+// FP64, FP32 or BF16 inputs (FP32 accumulation for the latter two within a
+// block's share of the list; the shares are summed in FP64).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void syrk_vec_body(const SyrkArgs& a, int bx, int by, int npairs, unsigned char* smem) {
+    constexpr int TT = 32;
+    static_assert(2 * SYRK_KB * (TT + 1) * 8 + SYRK_KB * 12 + 4 * (SYRK_SEGS + 1) <= SYRK_SMEM,
+                  "staging fits the block's LDS");
+    typedef double Row[TT + 1];
+    Row* sI = reinterpret_cast<Row*>(smem);
+    Row* sJ = sI + SYRK_KB;
+    double* cf = reinterpret_cast<double*>(sJ + SYRK_KB);
+    int32_t* ix = reinterpret_cast<int32_t*>(cf + SYRK_KB);
+    int32_t* pref = ix + SYRK_KB;
+    SyrkCtx c;
+    if (!syrk_prologue(a, bx, by, pref, c)) return;
+    const double* st = a.state;
+    const StateLayout sl = a.sl;
+    const int d = a.d;
+    const T inv = (T)(1.0 / c.sig);
+    const T* C = static_cast<const T*>(a.C);
+    const T* V = static_cast<const T*>(a.V);
+    const T* U = static_cast<const T*>(a.U);
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[2][2] = {{0, 0}, {0, 0}};
+    for (int kb = 0; kb < c.total; kb += SYRK_KB) {
+        const int nk = min(SYRK_KB, c.total - kb);
+        __syncthreads();
+        if (threadIdx.x < SYRK_KB) {
+            int32_t id = 0;
+            double cv = 0.0;
+            if (threadIdx.x < nk) syrk_entry(a, c, pref, kb + threadIdx.x, id, cv);
+            ix[threadIdx.x] = id;
+            cf[threadIdx.x] = cv;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < SYRK_KB * TT * 2; e += 256) {
+            const int which = e / (SYRK_KB * TT);
+            const int r = (e / TT) % SYRK_KB;
+            const int cc = e % TT;
+            const int col = (which ? c.J : c.I) * TT + cc;
+            double v = 0.0;
+            if (r < nk && col < d) {
+                const T yc = (T)(st[sl.xb + 1 + col] + (c.have_dir ? st[sl.dir + 1 + col] : 0.0));
+                v = (double)syrk_s<T>(a, C, U, V, ix[r], col, yc, inv);
+            }
+            if (which)
+                sJ[r][cc] = v;
+            else
+                sI[r][cc] = v;
+        }
+        __syncthreads();
+        for (int r = 0; r < nk; ++r) {
+            const double cr = cf[r];
+            const double a0 = sI[r][ty], a1 = sI[r][ty + 16];
+            const double b0 = sJ[r][tx] * cr, b1 = sJ[r][tx + 16] * cr;
+            acc[0][0] += a0 * b0;
+            acc[0][1] += a0 * b1;
+            acc[1][0] += a1 * b0;
+            acc[1][1] += a1 * b1;
+        }
+    }
+    double* out = a.out + ((size_t)by * npairs + bx) * TT * TT;
+    st_shared_dev(out + ty * TT + tx, acc[0][0]);
+    st_shared_dev(out + ty * TT + tx + 16, acc[0][1]);
+    st_shared_dev(out + (ty + 16) * TT + tx, acc[1][0]);
+    st_shared_dev(out + (ty + 16) * TT + tx + 16, acc[1][1]);
+    syrk_finish(a, c, bx, npairs);
+}
+
+typedef double syrk_d4 __attribute__((ext_vector_type(4)));
+typedef float syrk_f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 syrk_bf8 __attribute__((ext_vector_type(8)));
+
+// Matrix-core operand types: MI = 0 FP64, 1 FP32, 2 BF16
+template <int MI>
+struct SyrkMM;
+template <>
+struct SyrkMM<0> {
+    typedef double in_t;
+    typedef syrk_d4 acc_t;
+};
+template <>
+struct SyrkMM<1> {
+    typedef float in_t;
+    typedef syrk_f4 acc_t;
+};
+template <>
+struct SyrkMM<2> {
+    typedef __bf16 in_t;
+    typedef syrk_f4 acc_t;
+};
+
+// One 16 x 16 block product over the SYRK_KB staged k of a chunk.  Staged
+// rows are k-contiguous: sA[row * LDK + k], sB[col * LDK + k].  Operand lane
+// layouts (16 x 16 x 4 FP64 / FP32: lane l supplies A(row l % 16, k l / 16)
+// and B(k l / 16, col l % 16); 16 x 16 x 32 BF16: A(row l % 16, k 8 (l / 16)
+// .. + 7) and B alike); k within a chunk is split among the four lane groups
+// so each lane reads contiguous k.
+template <int MI, int LDK>
+__device__ __forceinline__ typename SyrkMM<MI>::acc_t syrk_mm_block(const typename SyrkMM<MI>::in_t* sA,
+                                                                     const typename SyrkMM<MI>::in_t* sB,
+                                                                     typename SyrkMM<MI>::acc_t acc) {
+    const int lane = lane_id(), g = lane / 16, l16 = lane % 16;
+    const typename SyrkMM<MI>::in_t* pa = sA + l16 * LDK + g * (SYRK_KB / 4);
+    const typename SyrkMM<MI>::in_t* pb = sB + l16 * LDK + g * (SYRK_KB / 4);
+    if constexpr (MI == 0) {
+#pragma unroll
+        for (int s2 = 0; s2 < SYRK_KB / 4; ++s2) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[s2], pb[s2], acc, 0, 0, 0);
+    } else if constexpr (MI == 1) {
+#pragma unroll
+        for (int s2 = 0; s2 < SYRK_KB / 4; ++s2) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[s2], pb[s2], acc, 0, 0, 0);
+    } else {
+        static_assert(SYRK_KB == 32, "one BF16 block product covers 32 k");
+        const syrk_bf8 va = *reinterpret_cast<const syrk_bf8*>(pa);
+        const syrk_bf8 vb = *reinterpret_cast<const syrk_bf8*>(pb);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+template <typename T, int MI>
+__device__ __forceinline__ void syrk_mm_body(const SyrkArgs& a, int bx, int by, int npairs, unsigned char* smem) {
+    typedef typename SyrkMM<MI>::in_t IT;
+    typedef typename SyrkMM<MI>::acc_t AT;
+    constexpr int TT = SYRK_MT;
+    constexpr int LDK = syrk_ldk<MI>();
+    static_assert(2 * TT * LDK * sizeof(IT) + 2 * TT * sizeof(T) + SYRK_KB * 12 + 4 * (SYRK_SEGS + 1) <= SYRK_SMEM,
+                  "staging fits the block's LDS");
+    IT* sA = reinterpret_cast<IT*>(smem);          // tile I columns x k
+    IT* sB = sA + TT * LDK;                        // tile J columns x k, times coef
+    T* yI = reinterpret_cast<T*>(sB + TT * LDK);   // y on the tile's columns
+    T* yJ = yI + TT;
+    double* cf = reinterpret_cast<double*>(yJ + TT);
+    int32_t* ix = reinterpret_cast<int32_t*>(cf + SYRK_KB);
+    int32_t* pref = ix + SYRK_KB;
+    SyrkCtx c;
+    if (!syrk_prologue(a, bx, by, pref, c)) return;
+    const double* st = a.state;
+    const StateLayout sl = a.sl;
+    const int d = a.d;
+    const T inv = (T)(1.0 / c.sig);
+    const T* C = static_cast<const T*>(a.C);
+    const T* V = static_cast<const T*>(a.V);
+    const T* U = static_cast<const T*>(a.U);
+    for (int e = threadIdx.x; e < 2 * TT; e += blockDim.x) {
+        const int col = (e < TT ? c.I : c.J) * TT + (e % TT);
+        const T y = col < d ? (T)(st[sl.xb + 1 + col] + (c.have_dir ? st[sl.dir + 1 + col] : 0.0)) : T(0);
+        if (e < TT)
+            yI[e] = y;
+        else
+            yJ[e - TT] = y;
+    }
+    const int w = threadIdx.x / WAVE;
+    const int qi = w >> 1, qj = w & 1;  // this wave's 32 x 32 quadrant
+    AT acc[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[p][q][e] = 0;
+    for (int kb = 0; kb < c.total; kb += SYRK_KB) {
+        const int nk = min(SYRK_KB, c.total - kb);
+        __syncthreads();
+        if (threadIdx.x < SYRK_KB) {
+            int32_t id = 0;
+            double cv = 0.0;
+            if (threadIdx.x < nk) syrk_entry(a, c, pref, kb + threadIdx.x, id, cv);
+            ix[threadIdx.x] = id;
+            cf[threadIdx.x] = cv;
+        }
+        __syncthreads();
+        // stage s on the two tiles' columns: thread -> (k, column), columns
+        // fastest so that the row reads coalesce
+        for (int e = threadIdx.x; e < SYRK_KB * 2 * TT; e += blockDim.x) {
+            const int k = e / (2 * TT), cc = e % (2 * TT);
+            const bool isJ = cc >= TT;
+            const int cl = isJ ? cc - TT : cc;
+            const int col = (isJ ? c.J : c.I) * TT + cl;
+            T v = T(0);
+            if (k < nk && col < d) {
+                v = syrk_s<T>(a, C, U, V, ix[k], col, isJ ? yJ[cl] : yI[cl], inv);
+                if (isJ) v = (T)((double)v * cf[k]);
+            }
+            (isJ ? sB : sA)[cl * LDK + k] = (IT)v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                acc[p][q] = syrk_mm_block<MI, LDK>(sA + (qi * 32 + 16 * p) * LDK, sB + (qj * 32 + 16 * q) * LDK,
+                                                    acc[p][q]);
+    }
+    // partial tile: result slot e of lane l of block (p, q) is column l % 16
+    // and row 4 e + l / 16 (FP64) or 4 (l / 16) + e (FP32, BF16) of that
+    // 16 x 16 block
+    double* out = a.out + ((size_t)by * npairs + bx) * TT * TT;
+    const int lane = lane_id(), g = lane / 16, l16 = lane % 16;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rr = (MI == 0) ? 4 * e + g : 4 * g + e;
+                const int r = qi * 32 + 16 * p + rr, cl = qj * 32 + 16 * q + l16;
+                st_shared_dev(out + r * TT + cl, (double)acc[p][q][e]);
+            }
+    syrk_finish(a, c, bx, npairs);
+}
+
+template <typename T>
+__device__ __forceinline__ void syrk_dispatch(const SyrkArgs& a, int bx, int by, int npairs, unsigned char* smem) {
+    if (a.mm == SYRK_MFMA_F64)
+        syrk_mm_body<T, 0>(a, bx, by, npairs, smem);
+    else if (a.mm == SYRK_MFMA_F32)
+        syrk_mm_body<T, 1>(a, bx, by, npairs, smem);
+    else if (a.mm == SYRK_MFMA_BF16)
+        syrk_mm_body<T, 2>(a, bx, by, npairs, smem);
+    else
+        syrk_vec_body<T>(a, bx, by, npairs, smem);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void syrk_kernel(SyrkArgs a) {
-    syrk_body<T>(a, blockIdx.x, blockIdx.y, gridDim.x);
+    __shared__ __align__(16) unsigned char smem[SYRK_SMEM];
+    syrk_dispatch<T>(a, blockIdx.x, blockIdx.y, gridDim.x, smem);
 }
 
 hipError_t launch_syrk(const SyrkArgs& a, hipStream_t s) {
     const int pairs = a.ntile * (a.ntile + 1) / 2;
     if ((a.nwaves + a.ksplit - 1) / a.ksplit > SYRK_SEGS || pairs > SYNC_LEN - SYNC_SYRK) return hipErrorInvalidValue;
+    if (a.tile != syrk_tile_of(a.mm)) return hipErrorInvalidValue;
     dim3 grid(pairs, a.ksplit);
     if (a.dtype == 0)
         hipLaunchKernelGGL(syrk_kernel<double>, grid, dim3(256), 0, s, a);
@@ -713,53 +932,215 @@ __device__ __forceinline__ int chol_solve_regs(int n, const double* H, const dou
 // different LDS banks
 __host__ __device__ inline int chol_ld(int n) { return n | 1; }
 
-// Solve with n above the register budget of the wave-level solves: the
-// triangular solves by the whole block, column oriented.
-__device__ __forceinline__ int chol_solve_block_large(int n, double* M, double* b, double* vec) {
-    __shared__ int bad;
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int tx = tid & 31, ty = tid >> 5, nty = nth >> 5;
-    if (tid == 0) bad = 0;
-    for (int e = tid; e < n; e += nth) vec[e] = b[e];
-    __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        const double ajj = M[j * n + j];
-        if (!(ajj > 0.0)) {
-            if (tid == 0) bad = 1;
-            __syncthreads();
-            break;
-        }
-        const double ljj = sqrt(ajj);
-        for (int i = j + 1 + tid; i < n; i += nth) M[i * n + j] /= ljj;
-        __syncthreads();
-        if (tid == 0) M[j * n + j] = ljj;
-        for (int ii = j + 1 + ty; ii < n; ii += nty) {
-            const double lij = M[ii * n + j];
-            for (int kk = j + 1 + tx; kk <= ii; kk += 32) M[ii * n + kk] -= lij * M[kk * n + j];
-        }
-        __syncthreads();
-    }
-    if (bad) return -1;
-    for (int j = 0; j < n; ++j) {
-        const double yj = vec[j] / M[j * n + j];
-        __syncthreads();
-        if (tid == 0) vec[j] = yj;
-        for (int i = j + 1 + tid; i < n; i += nth) vec[i] -= M[i * n + j] * yj;
-        __syncthreads();
-    }
-    for (int i = n - 1; i >= 0; --i) {
-        const double xi = vec[i] / M[i * n + i];
-        __syncthreads();
-        if (tid == 0) vec[i] = xi;
-        for (int k = tid; k < i; k += nth) vec[k] -= M[i * n + k] * xi;
-        __syncthreads();
-    }
-    for (int e = tid; e < n; e += nth) b[e] = vec[e];
-    __syncthreads();
-    return 0;
+// ---------------------------------------------------------------------------
+// Blocked Cholesky solve for n above what LDS holds (one workgroup of 16
+// waves, the matrix in global memory, where it stays in L2).  Right-looking
+// in panels of BCH_NB columns:
+//   1. wave 0 factors the diagonal block in registers (lane r holds row r);
+//      the right-hand side rides along as one more row (lane BCH_NB), so the
+//      forward substitution L y = b happens inside the factorization;
+//   2. every thread takes rows below the block: x L_D^T = a by substitution
+//      against L_D in LDS, stores the panel row and updates its entry of b
+//      with the row's share of the forward substitution;
+//   3. the trailing lower triangle takes the rank-BCH_NB update
+//      A_ij -= sum_k L_ik L_jk in 32 x 32 tiles, one tile per wave at a time,
+//      on FP64 matrix cores (16 x 16 x 4 blocks).
+// Then the back substitution L^T x = y runs block by block from the bottom.
+// Only the lower triangle is written; the upper triangle keeps A (the
+// breakdown guard restores the lower triangle from it).  b (LDS, n) holds
+// the solution on return.  Returns -1 if a pivot is not positive.
+// ---------------------------------------------------------------------------
+constexpr int BCH_NB = 32;
+constexpr int BCH_LD = BCH_NB + 2;  // LDS row stride of L_D (doubles, 16-byte rows)
+__host__ __device__ constexpr int bch_lds_doubles() { return BCH_NB * BCH_LD + BCH_NB; }
+
+typedef double bch_d4 __attribute__((ext_vector_type(4)));
+
+// FP64 16 x 16 x 4 block product: lane l supplies A(row l % 16, k l / 16) and
+// B(k l / 16, col l % 16); result slot q of lane l is D(row 4 q + l / 16,
+// col l % 16) (the FP32 and BF16 forms place row 4 (l / 16) + q there).
+__device__ __forceinline__ bch_d4 mfma_f64_16x16x4(double a, double b, bch_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-
+__device__ __forceinline__ int chol_solve_blocked(int n, double* M, double* b, double* lw) {
+    __shared__ int s_bad;
+    double* lrow = lw;                      // L_D row-major, BCH_NB x BCH_LD
+    double* dinv = lw + BCH_NB * BCH_LD;    // 1 / L_D(j, j)
+    const int tid = threadIdx.x, lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int nw = blockDim.x / WAVE;
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    for (int kb = 0; kb < n; kb += BCH_NB) {
+        const int nb = min(BCH_NB, n - kb);
+        // ---- 1. diagonal block (wave 0)
+        if (w == 0) {
+            // lane r < nb: row r of the block; lane BCH_NB: the right-hand side
+            const bool is_row = lane < nb;
+            const bool is_rhs = lane == BCH_NB;
+            double a[BCH_NB];
+#pragma unroll
+            for (int c = 0; c < BCH_NB; ++c) {
+                double v = 0.0;
+                if (is_row && c <= lane) v = M[(size_t)(kb + lane) * n + kb + c];
+                if (is_rhs && c < nb) v = b[kb + c];
+                a[c] = v;
+            }
+            bool bad = false;
+            double dv = 0.0;
+#pragma unroll
+            for (int j = 0; j < BCH_NB; ++j) {
+                if (j < nb) {
+                    const double piv = readlane_f64(a[j], j);
+                    bad = bad || !(piv > 0.0);
+                    const double inv = rsqrt_f64(piv > 0.0 ? piv : 1.0);
+                    // column j of L: lanes below the pivot scale, the pivot
+                    // lane takes sqrt(piv); the rhs lane gets y_j
+                    a[j] = (lane == j) ? piv * inv : a[j] * inv;
+                    if (lane == j) dv = inv;
+                    // broadcast column j through LDS: lrow(r, j) = L(r, j),
+                    // read back by every lane of the wave
+                    if (is_row) lrow[lane * BCH_LD + j] = a[j];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                    for (int c = j + 1; c < BCH_NB; ++c) {
+                        if (c < nb) {
+                            const double lcj = lrow[c * BCH_LD + j];
+                            a[c] = fma(-a[j], lcj, a[c]);
+                        }
+                    }
+                }
+            }
+            // L_D in LDS (rows, lower part; zero above), 1 / pivots; y to b
+            if (is_row) {
+#pragma unroll
+                for (int c = 0; c < BCH_NB; ++c) lrow[lane * BCH_LD + c] = (c <= lane) ? a[c] : 0.0;
+                dinv[lane] = dv;
+#pragma unroll
+                for (int c = 0; c < BCH_NB; ++c)
+                    if (c <= lane) M[(size_t)(kb + lane) * n + kb + c] = a[c];
+            }
+            if (is_rhs) {
+#pragma unroll
+                for (int c = 0; c < BCH_NB; ++c)
+                    if (c < nb) b[kb + c] = a[c];
+            }
+            if (bad && lane == 0) s_bad = 1;
+        }
+        __syncthreads();
+        if (s_bad) return -1;
+        // ---- 2. panel rows below the block and their share of L y = b
+        for (int i = kb + nb + tid; i < n; i += blockDim.x) {
+            double x[BCH_NB];
+            double* row = M + (size_t)i * n + kb;
+#pragma unroll
+            for (int c = 0; c < BCH_NB; ++c) x[c] = c < nb ? row[c] : 0.0;
+#pragma unroll
+            for (int j = 0; j < BCH_NB; ++j) {
+                if (j < nb) {
+                    double sacc = x[j];
+#pragma unroll
+                    for (int c = 0; c < j; ++c) sacc = fma(-x[c], lrow[j * BCH_LD + c], sacc);
+                    x[j] = sacc * dinv[j];
+                }
+            }
+            double by = 0.0;
+#pragma unroll
+            for (int c = 0; c < BCH_NB; ++c) {
+                if (c < nb) {
+                    row[c] = x[c];
+                    by = fma(x[c], b[kb + c], by);
+                }
+            }
+            b[i] -= by;
+        }
+        __syncthreads();
+        // ---- 3. trailing update, 32 x 32 tiles of the lower triangle
+        const int t0 = kb + nb;
+        if (t0 < n) {
+            const int T = (n - t0 + 31) / 32;
+            const int ntiles = T * (T + 1) / 2;
+            const int g = lane / 16, l16 = lane % 16;
+            for (int t = w; t < ntiles; t += nw) {
+                // tile (TI, TJ), TJ <= TI, from the linear index
+                int TI = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+                while (TI * (TI + 1) / 2 > t) --TI;
+                while ((TI + 1) * (TI + 2) / 2 <= t) ++TI;
+                const int TJ = t - TI * (TI + 1) / 2;
+                const int i0 = t0 + 32 * TI, j0 = t0 + 32 * TJ;
+                bch_d4 acc[2][2];
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) acc[p][q] = bch_d4{0.0, 0.0, 0.0, 0.0};
+                // lane group g covers k in [8 g, 8 g + 8): 8 products of 4 k each
+                double av[2][8], bv[2][8];
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const int ri = i0 + 16 * p + l16, rj = j0 + 16 * p + l16;
+#pragma unroll
+                    for (int s2 = 0; s2 < 8; ++s2) {
+                        const int k = 8 * g + s2;
+                        av[p][s2] = (ri < n && k < nb) ? M[(size_t)ri * n + kb + k] : 0.0;
+                        bv[p][s2] = (rj < n && k < nb) ? M[(size_t)rj * n + kb + k] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p)
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) acc[p][q] = mfma_f64_16x16x4(av[p][s2], bv[q][s2], acc[p][q]);
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int i = i0 + 16 * p + 4 * e + g, j = j0 + 16 * q + l16;
+                            if (i < n && j <= i) M[(size_t)i * n + j] -= acc[p][q][e];
+                        }
+            }
+        }
+        __syncthreads();
+    }
+    // ---- back substitution L^T x = y, blocks from the bottom
+    const int nblk = (n + BCH_NB - 1) / BCH_NB;
+    for (int bk = nblk - 1; bk >= 0; --bk) {
+        const int kb = bk * BCH_NB, nb = min(BCH_NB, n - kb);
+        if (w == 0) {
+            // lane r < nb holds column r of L_D (L(c, r), c >= r) and y_r
+            double lc[BCH_NB];
+#pragma unroll
+            for (int c = 0; c < BCH_NB; ++c)
+                lc[c] = (lane < nb && c < nb && c >= lane) ? M[(size_t)(kb + c) * n + kb + lane] : 0.0;
+            double y = lane < nb ? b[kb + lane] : 0.0;
+            double xs = 0.0;
+#pragma unroll
+            for (int j = BCH_NB - 1; j >= 0; --j) {
+                if (j < nb) {
+                    const double xj = readlane_f64(y, j) / readlane_f64(lc[j], j);
+                    if (lane == j) xs = xj;
+                    if (lane < j) y = fma(-lc[j], xj, y);
+                }
+            }
+            if (lane < nb) b[kb + lane] = xs;
+        }
+        __syncthreads();
+        // y_c -= sum_j L(kb + j, c) x_j for the columns left of the block
+        for (int c = tid; c < kb; c += blockDim.x) {
+            double acc = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < nb; ++j) acc = fma(M[(size_t)(kb + j) * n + c], b[kb + j], acc);
+            b[c] -= acc;
+        }
+        __syncthreads();
+    }
+    return 0;
+}
 
 constexpr int CHOL_LDS_MAX_N = 140;  // 140 x 141 doubles + vectors < 160 KiB
 constexpr int CTRL_THREADS = 1024;
@@ -789,14 +1170,20 @@ __global__ __launch_bounds__(CTRL_THREADS) void chol_solve_kernel(int n, double*
         rc = chol_solve_lds(n, ld, M, bv, rd);
         for (int e = threadIdx.x; e < n; e += blockDim.x) b[e] = bv[e];
     } else {
-        rc = chol_solve_block_large(n, A, b, sm);
+        // rhs and solution in LDS, then the blocked factorization's scratch
+        double* bv = sm;
+        for (int e = threadIdx.x; e < n; e += blockDim.x) bv[e] = b[e];
+        __syncthreads();
+        rc = chol_solve_blocked(n, A, bv, sm + n);
+        for (int e = threadIdx.x; e < n; e += blockDim.x) b[e] = bv[e];
     }
     if (threadIdx.x == 0) *info = rc;
 }
 
 hipError_t launch_chol_solve(int n, double* A, double* b, int* info, hipStream_t s) {
     size_t lds = sizeof(double) * (rch_fits(n, CTRL_THREADS) ? rch_lds_doubles(n)
-                                   : (size_t)(n <= CHOL_LDS_MAX_N ? (size_t)n * chol_ld(n) + 2 * n : n));
+                                   : (size_t)(n <= CHOL_LDS_MAX_N ? (size_t)n * chol_ld(n) + 2 * n
+                                                                  : (size_t)n + bch_lds_doubles()));
     hipError_t ea = ensure_dynamic_lds((const void*)chol_solve_kernel, lds);
     if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(CTRL_THREADS), lds, s, n, A, b, info);
@@ -859,8 +1246,20 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
     double* ab = st + sl.ab;
     double* gb = st + sl.gb;
     double* H = st + sl.H;
+    double* xprev = st + sl.tmp;  // previous iterate of the accelerated gradient method
     if (threadIdx.x == 0) s_next = 0;
     __syncthreads();
+    // the run's first evaluation opens its first inner solve
+    if (mode == PM_EVAL && st[S_NPASS] == 1.0 && st[S_FO_OUTER] > 0.0) {
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) xprev[k] = xb[k];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            st[S_FO_ON] = 1.0;
+            st[S_FO_PHASE] = 0.0;
+            st[S_FO_T] = 1.0;
+        }
+        __syncthreads();
+    }
 
     if (threadIdx.x == 0) {
         st[S_NPASS] += 1.0;
@@ -921,8 +1320,12 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
         if (s_next) {
             return;
         }
-        // next outer iteration: sigma, proximal center
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) xbar[k] = xb[k];
+        // next outer iteration: sigma, proximal center, inner solver
+        const bool fo = st[S_K] < st[S_FO_OUTER];
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+            xbar[k] = xb[k];
+            if (fo) xprev[k] = xb[k];
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             const double sn = st[S_SIGMA_NEXT];
@@ -930,9 +1333,78 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
             st[S_SIGMA_NEXT] = fmin(sn * st[S_GROWTH], st[S_SIGMA_MAX]);
             st[S_J] = 0.0;
             st[S_HAVE_DIR] = 0.0;
+            st[S_FO_ON] = fo ? 1.0 : 0.0;
+            st[S_FO_PHASE] = 0.0;
+            st[S_FO_T] = 1.0;
+            st[S_FO_STEP] = 0.0;  // re-estimated for the new penalty
         }
         __syncthreads();
         // fall through: the record's evaluation part is at (x_j, w+, sigma_{k+1})
+    } else if (st[S_HAVE_DIR] != 0.0 && st[S_FO_PHASE] != 0.0) {
+        // accelerated gradient method (first-order inner solver for the
+        // early outer iterations, Section 4.1): the trials gave Psi at
+        // y - eta s g (dir = -s g, y = x_base).  Backtracking on the step:
+        // the largest eta with Psi(y + eta dir) <= Psi(y) + eta/2 <g, dir>
+        // (the quadratic upper bound with constant 1 / (eta s)); then
+        // x = y + eta dir, the momentum step y' = x + (t_k - 1) / t_{k+1}
+        // (x - x_prev), restarted (t = 1) when <g(y), x - x_prev> > 0.
+        double pdd = 0.0, pdx = 0.0, pxx = 0.0;
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+            const double dx = xb[k] - xbar[k];
+            pdd += dir[k] * dir[k];
+            pdx += dir[k] * dx;
+            pxx += dx * dx;
+        }
+        double sums[3] = {pdd, pdx, pxx};
+        block_sum_n<3>(sums, scratch);
+        const double dd = sums[0], dxd = sums[1], xx = sums[2];
+        if (threadIdx.x == 0) {
+            const double sg = sigma;
+            const double z0 = red[rl.trial + NT - 1];
+            const double psi0 = xb[0] + 0.5 * sg * z0 - red[rl.ww] / (2.0 * sg) + tau / (2.0 * sg) * xx;
+            const double gd = st[S_GD];
+            const double allow = 8.0 * eps * (fabs(psi0) + 1.0);
+            int acc = -1;
+            for (int l = 0; l < NT - 1; ++l) {
+                const double eta = solver_eta(l);
+                const double dpsi = eta * dir[0] + 0.5 * sg * (red[rl.trial + l] - z0) +
+                                    tau / (2.0 * sg) * (2.0 * eta * dxd + eta * eta * dd);
+                if (dpsi <= 0.5 * eta * gd + allow) {
+                    acc = l;
+                    break;
+                }
+            }
+            // no trial passed: stay at y with a step shorter than every trial
+            const double eta = acc >= 0 ? solver_eta(acc) : 0.0;
+            // the step grows again after a full step, so it tracks the local curvature
+            st[S_FO_STEP] *= acc == 0 ? 2.0 : (acc > 0 ? eta : solver_eta(NT - 2) * 0.5);
+            s_eta = eta;
+            st[S_NFO] += 1.0;
+        }
+        __syncthreads();
+        const double eta = s_eta;
+        // x = y + eta dir; <g(y), x - x_prev> decides the restart
+        double prs = 0.0;
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) prs += gb[k] * (xb[k] + eta * dir[k] - xprev[k]);
+        const double rs = block_sum(prs, scratch);
+        __shared__ double s_beta;
+        if (threadIdx.x == 0) {
+            double t = st[S_FO_T];
+            if (rs > 0.0 || eta == 0.0) t = 1.0;  // restart
+            const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+            s_beta = (t - 1.0) / tn;
+            st[S_FO_T] = tn;
+            st[S_FO_PHASE] = 0.0;
+            st[S_HAVE_DIR] = 0.0;
+        }
+        __syncthreads();
+        const double beta = s_beta;
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+            const double xn = xb[k] + eta * dir[k];
+            xb[k] = xn + beta * (xn - xprev[k]);
+            xprev[k] = xn;
+        }
+        return;  // next pass evaluates at the momentum point
     } else if (st[S_HAVE_DIR] != 0.0) {
         // single-pass Armijo decision along x_base + eta dir
         const double sg = sigma;
@@ -1054,6 +1526,40 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
     }
     __syncthreads();
     if (s_next) return;
+    if (st[S_FO_ON] != 0.0) {
+        // first-order step from y = x_base along -s g (its trials come next)
+        if (threadIdx.x == 0 && !(st[S_FO_STEP] > 0.0)) {
+            // first step: 1 / (a curvature estimate): tau/sigma + sigma (interior + mid/2)
+            st[S_FO_STEP] = 1.0 / (tau / sgm + sgm * (red[rl.ni] + 0.5 * red[rl.nm]) + 1e-300);
+        }
+        __syncthreads();
+        const double step = st[S_FO_STEP];
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = -step * gb[k];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            st[S_GD] = -step * gg;
+            st[S_HAVE_DIR] = 1.0;
+            st[S_FO_PHASE] = 1.0;
+            st[S_LSH] = 0.0;
+            st[S_MODE] = (double)PM_EVAL;
+        }
+        return;
+    }
+    if (st[S_CG] != 0.0) {
+        // matrix-free Newton direction: x = 0, r = -g; the CG launches follow
+        const int cs = cg_stride(n1);
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+            H[k] = 0.0;
+            H[cs + k] = -gb[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            st[S_CG_IT] = 0.0;
+            st[S_CG_DONE] = 0.0;
+            st[S_MODE] = (double)PM_CG;
+        }
+        return;
+    }
     // Newton direction: H dir = -g, H assembled by the contraction.  H is
     // positive definite through its (tau/sigma) I term in exact arithmetic
     // (Section 4); rounding in its assembly can still produce a pivot that is
@@ -1111,9 +1617,13 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
             for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
             __syncthreads();
         } else {
-            for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = -gb[k];
+            // blocked factorization in place (global memory), rhs in LDS
+            double* bv = scratch;
+            for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
             __syncthreads();
-            rc = chol_solve_block_large(n1, H, dir, scratch);
+            rc = chol_solve_blocked(n1, H, bv, lmat);
+            for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
+            __syncthreads();
         }
     }
     if (rc != 0) {
@@ -1138,6 +1648,294 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
     }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-free Newton direction (Section 4.1, large d): preconditioned
+// conjugate gradients on H dir = -g with the Hessian-vector products
+//   H p = tau/sigma p + sigma sum_i P_i p,
+// assembled from the pass's counts and sums (interior balls: the identity;
+// the third case: sigma/2 on H_rr, sigma/2 sum w_i in the r row and column,
+// sum gamma_i on the diagonal) and, for the rank-one parts, from the mid list:
+//   sum_mid coef_i s_i (s_i^T p_c),  s_i recomputed as the pass formed it.
+// Jacobi preconditioner (diagonal of H).  One launch per CG iteration: each
+// block takes its share of the mid list, and the last block to arrive sums
+// the shares in block order (reproducible) and performs the CG update.  The
+// vectors x, r, p and the preconditioner live in the Hessian's place of the
+// state, which this solver does not use.
+// ---------------------------------------------------------------------------
+constexpr int CG_THREADS = 256;
+
+// CMAX: columns per lane (d <= 64 CMAX)
+template <typename T, int CMAX>
+__device__ __forceinline__ void cg_body(const CgArgs& a) {
+    extern __shared__ __align__(16) double csm[];
+    __shared__ int s_last;
+    __shared__ int32_t pref[CG_THREADS * 4 + 1];
+    __shared__ int wtot[CG_THREADS / WAVE];
+    double* st = a.state;
+    if ((int)st[S_MODE] != PM_CG || st[S_CG_DONE] != 0.0) return;
+    const int d = a.d, n1 = d + 1, cs = cg_stride(n1);
+    const StateLayout sl = a.sl;
+    const RecLayout rl = a.rl;
+    const double* red = a.red;
+    double* cx = st + sl.H;       // solution
+    double* cr = cx + cs;         // residual
+    double* cp = cr + cs;         // search direction
+    double* cm = cp + cs;         // preconditioner (diagonal of H)
+    double* ly = csm;             // y (the evaluation point), d
+    double* lp = csm + d;         // p_c (or nothing in the opening pass), d
+    double* lacc = csm + 2 * d;   // block sum, d
+    const double sig = st[S_SIGMA];
+    const T inv = (T)(1.0 / sig);
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        ly[k] = st[sl.xb + 1 + k];
+        lp[k] = cp[1 + k];
+        lacc[k] = 0.0;
+    }
+    // this block's wave segments and the exclusive prefix of their counts
+    const int per = (a.nwaves + gridDim.x - 1) / gridDim.x;
+    const int w0 = blockIdx.x * per, w1 = min(a.nwaves, w0 + per);
+    const int nseg = max(0, w1 - w0);
+    const int lane = lane_id(), wv = threadIdx.x / WAVE;
+    {
+        const int q0 = threadIdx.x * 4;
+        int cnt[4], t = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            cnt[u] = (q0 + u < nseg) ? a.mid_cnt[w0 + q0 + u] : 0;
+            t += cnt[u];
+        }
+        int inc = t;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int y = __shfl_up(inc, o, WAVE);
+            if (lane >= o) inc += y;
+        }
+        if (lane == WAVE - 1) wtot[wv] = inc;
+        __syncthreads();
+        int before = 0;
+        for (int q = 0; q < wv; ++q) before += wtot[q];
+        int run = before + inc - t;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (q0 + u <= nseg) pref[q0 + u] = run;
+            run += cnt[u];
+        }
+        if (threadIdx.x == blockDim.x - 1 && nseg == 4 * (int)blockDim.x) pref[nseg] = run;
+        __syncthreads();
+    }
+    const int total = pref[nseg];
+    const T* C = static_cast<const T*>(a.C);
+    const T* U = static_cast<const T*>(a.U);
+    const T* V = static_cast<const T*>(a.V);
+    // each wave takes every fourth entry: s_i^T p over the row (first read),
+    // then coef_i (s_i^T p) s_i per column (second read, from cache), or
+    // coef_i s_i^2 for the preconditioner
+    double acc[CMAX];
+#pragma unroll
+    for (int q = 0; q < CMAX; ++q) acc[q] = 0.0;
+    auto s_at = [&](int64_t i, bool hv, int k) -> double {
+        const T ek = C[i * d + k] - (T)ly[k];
+        const T vk = hv ? V[i * d + k] : T(0);
+        return (double)(ek + vk * inv);
+    };
+    for (int e = wv; e < total; e += CG_THREADS / WAVE) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pref[mid] <= e)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int64_t pos = (int64_t)(w0 + lo) * a.bw + (e - pref[lo]);
+        const int64_t i = a.mid_idx[pos];
+        const double cf = a.mid_coef[pos];
+        const bool hv = V && U && U[i] != T(0);
+        double f = cf;
+        if (!a.init) {
+            double dot = 0.0;
+#pragma unroll
+            for (int q = 0; q < CMAX; ++q) {
+                const int k = q * WAVE + lane;
+                if (k < d) dot += s_at(i, hv, k) * lp[k];
+            }
+            f = cf * wave_sum(dot);
+        }
+#pragma unroll
+        for (int q = 0; q < CMAX; ++q) {
+            const int k = q * WAVE + lane;
+            if (k < d) {
+                const double sk = s_at(i, hv, k);
+                acc[q] += a.init ? cf * sk * sk : f * sk;
+            }
+        }
+    }
+    // block sum, waves in order
+    for (int w = 0; w < CG_THREADS / WAVE; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int q = 0; q < CMAX; ++q) {
+                const int k = q * WAVE + lane;
+                if (k < d) lacc[k] += acc[q];
+            }
+        }
+        __syncthreads();
+    }
+    double* part = a.part + (size_t)blockIdx.x * d;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) st_shared_dev(part + k, lacc[k]);
+    published();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = arrive(&a.sync[SYNC_CG]) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    // the last block: the rank-one share of every block, in block order
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        double v = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) v += ld_shared_dev(a.part + (size_t)b * d + k);
+        lacc[k] = v;
+    }
+    if (threadIdx.x == 0) a.sync[SYNC_CG] = 0;
+    __syncthreads();
+    const double tau = st[S_TAU];
+    const double hrr = tau / sig + sig * red[rl.ni] + 0.5 * sig * red[rl.nm];
+    const double hdg = tau / sig + sig * red[rl.ni] + red[rl.sg];
+    double* lq = lacc;  // q = H p in place of the rank-one sums (index k = column k)
+    __shared__ double s_q0;
+    if (a.init) {
+        // preconditioner, z = M^-1 r, p = z, r^T z, ||r||^2 (x = 0, r = -g set by the control step)
+        double prz = 0.0, prr = 0.0;
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+            const double m = (k == 0) ? hrr : hdg + lacc[k - 1];
+            cm[k] = m > 0.0 ? m : hdg;
+            const double z = cr[k] / cm[k];
+            cp[k] = z;
+            prz += cr[k] * z;
+            prr += cr[k] * cr[k];
+        }
+        double sums[2] = {prz, prr};
+        block_sum_n<2>(sums, csm + 3 * d);
+        if (threadIdx.x == 0) {
+            st[S_CG_RZ] = sums[0];
+            st[S_CG_B2] = sums[1];
+            if (!(sums[1] > 0.0)) st[S_CG_DONE] = 1.0;
+        }
+        return;
+    }
+    // q = H p
+    double ph = 0.0;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) ph += 0.5 * sig * red[rl.sw + k] * cp[1 + k];
+    const double hrc_p = block_sum(ph, csm + 3 * d);
+    if (threadIdx.x == 0) s_q0 = hrr * cp[0] + hrc_p;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) lq[k] = 0.5 * sig * red[rl.sw + k] * cp[0] + hdg * cp[1 + k] + lacc[k];
+    __syncthreads();
+    if (a.out) {  // the product alone (meb_hess_vec)
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) a.out[k] = (k == 0) ? s_q0 : lq[k - 1];
+        return;
+    }
+    double ppq = 0.0;
+    for (int k = threadIdx.x; k < n1; k += blockDim.x) ppq += cp[k] * (k == 0 ? s_q0 : lq[k - 1]);
+    const double pq = block_sum(ppq, csm + 3 * d);
+    __shared__ double s_alpha;
+    __shared__ int s_stop;
+    if (threadIdx.x == 0) {
+        s_stop = !(pq > 0.0);  // curvature not positive: stop with the current x
+        s_alpha = s_stop ? 0.0 : st[S_CG_RZ] / pq;
+    }
+    __syncthreads();
+    const double alpha = s_alpha;
+    double prr = 0.0, prz = 0.0;
+    for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+        const double qk = (k == 0) ? s_q0 : lq[k - 1];
+        cx[k] += alpha * cp[k];
+        cr[k] -= alpha * qk;
+        prr += cr[k] * cr[k];
+        prz += cr[k] * cr[k] / cm[k];
+    }
+    double sums[2] = {prr, prz};
+    block_sum_n<2>(sums, csm + 3 * d);
+    __shared__ double s_beta;
+    if (threadIdx.x == 0) {
+        const double it = st[S_CG_IT] + 1.0;
+        st[S_CG_IT] = it;
+        st[S_NCG] += 1.0;
+        const double tol = st[S_CG_TOL];
+        if (s_stop || sums[0] <= tol * tol * st[S_CG_B2] || it >= st[S_CG_MAX]) {
+            st[S_CG_DONE] = 1.0;
+            s_beta = -1.0;
+        } else {
+            s_beta = sums[1] / st[S_CG_RZ];
+            st[S_CG_RZ] = sums[1];
+        }
+    }
+    __syncthreads();
+    const double beta = s_beta;
+    if (beta >= 0.0)
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) cp[k] = cr[k] / cm[k] + beta * cp[k];
+}
+
+template <typename T, int CMAX>
+__global__ __launch_bounds__(CG_THREADS) void cg_kernel(CgArgs a) {
+    cg_body<T, CMAX>(a);
+}
+
+template <typename T, int CMAX>
+static hipError_t launch_cg_t(const CgArgs& a, hipStream_t s) {
+    const size_t lds = sizeof(double) * (3 * (size_t)a.d + 3 * (CG_THREADS / WAVE) + 8);
+    const hipError_t ea = ensure_dynamic_lds((const void*)cg_kernel<T, CMAX>, lds);
+    if (ea != hipSuccess) return ea;
+    hipLaunchKernelGGL((cg_kernel<T, CMAX>), dim3(CG_BLOCKS), dim3(CG_THREADS), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_cg_c(const CgArgs& a, hipStream_t s) {
+    if (a.d <= 4 * WAVE) return launch_cg_t<T, 4>(a, s);
+    if (a.d <= 8 * WAVE) return launch_cg_t<T, 8>(a, s);
+    if (a.d <= 16 * WAVE) return launch_cg_t<T, 16>(a, s);
+    if (a.d <= 32 * WAVE) return launch_cg_t<T, 32>(a, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_cg_iter(const CgArgs& a, hipStream_t s) {
+    return a.dtype == 0 ? launch_cg_c<double>(a, s) : launch_cg_c<float>(a, s);
+}
+
+// The Newton direction from the CG solution (x, or the preconditioned
+// steepest descent direction -M^-1 g if x is not a descent direction), and
+// the line search that follows.
+__global__ __launch_bounds__(256) void cg_finish_kernel(double* st, StateLayout sl, int* flag) {
+    __shared__ double scratch[256 / WAVE * 2 + 8];
+    if ((int)st[S_MODE] == PM_CG) {
+        const int n1 = sl.n1, cs = cg_stride(n1);
+        const double* cx = st + sl.H;
+        const double* cm = cx + 3 * cs;
+        const double* gb = st + sl.gb;
+        double* dir = st + sl.dir;
+        double p = 0.0;
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) p += gb[k] * cx[k];
+        const double gd = block_sum(p, scratch);
+        const bool desc = gd < 0.0;
+        double p2 = 0.0;
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+            dir[k] = desc ? cx[k] : -gb[k] / cm[k];
+            p2 += gb[k] * dir[k];
+        }
+        const double gd2 = block_sum(p2, scratch);
+        if (threadIdx.x == 0) {
+            st[S_GD] = gd2;
+            st[S_HAVE_DIR] = 1.0;
+            st[S_LSH] = 0.0;
+            st[S_MODE] = (double)PM_EVAL;
+        }
+    }
+    if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
+}
+
+hipError_t launch_cg_finish(double* state, StateLayout sl, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(cg_finish_kernel, dim3(1), dim3(256), 0, s, state, sl, flag);
+    return hipGetLastError();
+}
+
 // `flag` (nullable, typically host-mapped) receives the state's mode after
 // the step, so a host can learn that the run has ended without a copy.
 __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, StateLayout sl, RecLayout rl,
@@ -1152,6 +1950,8 @@ size_t control_lds_bytes(int n1) {
         lds += sizeof(double) * rch_lds_doubles(n1);
     else if (n1 <= CTRL_CHOL_LDS_MAX_N)
         lds += sizeof(double) * (size_t)n1 * chol_ld(n1);
+    else
+        lds += sizeof(double) * (size_t)bch_lds_doubles();
     return lds;
 }
 
@@ -1174,10 +1974,11 @@ __global__ __launch_bounds__(256) void syrk_batch_kernel(const BatchItem* tab, T
     const BatchItem& it = tab[L.slot[k]];
     const int b = blockIdx.x - L.off[k];
     const int npairs = it.sa.ntile * (it.sa.ntile + 1) / 2;
+    __shared__ __align__(16) unsigned char smem[SYRK_SMEM];
     if (it.sa.dtype == 0)
-        syrk_body<double>(it.sa, b % npairs, b / npairs, npairs);
+        syrk_dispatch<double>(it.sa, b % npairs, b / npairs, npairs, smem);
     else
-        syrk_body<float>(it.sa, b % npairs, b / npairs, npairs);
+        syrk_dispatch<float>(it.sa, b % npairs, b / npairs, npairs, smem);
 }
 
 __global__ __launch_bounds__(CTRL_THREADS) void control_batch_kernel(const BatchItem* tab, TickList L) {
@@ -1316,13 +2117,19 @@ static ScanLanes scan_lanes(int d, int dtype) {
 // Distances are accumulated in FP64 (FP32 rows are widened exactly).  Each
 // wave streams its own rows with the next group's loads issued before the
 // current group is used.
+// Hits go to seg: by default into the wave's own segment seg[wbeg ..]
+// (concatenated afterwards by scan_copy); with a placement (pl.offs) straight
+// to their final positions seg[pl.offs[wave] + k], those below pl.cap, after
+// a counting pass has filled pl.offs -- and the kernel returns at once if
+// *pl.gate (that pass's total) is zero.  seg may be NULL (count only).
 template <typename T, int VEC, int NLMAX, int MODE>
 __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T* R, int64_t m, int d, int G, int nl,
                                                             const double* xdev, double r, double thr,
                                                             double* slack, float* C32, float* R32, ScanCfg cfg,
                                                             double* wmax, int64_t* warg, int64_t* wcnt,
-                                                            int64_t* seg) {
+                                                            int64_t* seg, ScanPlace pl) {
     extern __shared__ double lx[];
+    if (pl.gate && *pl.gate == 0) return;
     for (int k = threadIdx.x; k < d; k += SCAN_THREADS) lx[k] = xdev ? xdev[k] : 0.0;
     __syncthreads();
     const int lane = lane_id();
@@ -1330,6 +2137,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T*
     const int64_t gw = (int64_t)blockIdx.x * SCAN_WPB + wid;
     const int gi = lane / G, gl = lane % G, bpw = WAVE / G;
     const int64_t wbeg = gw * cfg.bw, wend = min(m, wbeg + cfg.bw);
+    const int64_t obase = pl.offs ? pl.offs[gw] : wbeg;
+    const int64_t ocap = pl.offs ? pl.cap : INT64_MAX;
     int col[NLMAX];
     bool own[NLMAX];
 #pragma unroll
@@ -1365,7 +2174,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T*
                 acc += e * e;
                 o.v[q] = (float)e;
             }
-            if (MODE == 2 && act && own[j]) store_vec<float, VEC>(C32 + i * d + col[j], o);
+            if (MODE == 2 && C32 && act && own[j]) store_vec<float, VEC>(C32 + i * d + col[j], o);
         }
         const double dist = sqrt(group_sum<double>(acc, G));
         const double ri = act ? (double)L.r : 0.0;
@@ -1377,6 +2186,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T*
             if (slack && act && gl == 0) slack[i] = val;
         } else {
             val = ri + dist - r;
+            // the preparation flags a negative radius or a non-finite value
+            // (including NaN, which the maximum below would skip) as +inf
+            if (MODE == 2 && !(ri >= 0.0 && val < INFINITY)) val = INFINITY;
             hit = (MODE == 0) && act && val > thr;
             if (MODE == 2 && R32 && act && gl == 0) R32[i] = (float)ri;
             if (act && (val > best || (val == best && i < barg))) {
@@ -1386,7 +2198,10 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(const T* C, const T*
         }
         if (MODE != 2) {
             const unsigned long long bal = __ballot(hit && gl == 0);
-            if (hit && gl == 0) seg[wbeg + count + __popcll(bal & ((1ull << lane) - 1ull))] = i;
+            if (seg && hit && gl == 0) {
+                const int64_t q = obase + count + __popcll(bal & ((1ull << lane) - 1ull));
+                if (q < ocap) seg[q] = i;
+            }
             count += __popcll(bal);
         }
     };
@@ -1486,18 +2301,20 @@ __global__ __launch_bounds__(256) void scan_copy(const int64_t* seg, const int64
 template <typename T, int MODE, int VEC, int NLMAX>
 static hipError_t launch_scan_v(const void* C, const void* R, int64_t m, int d, const ScanLanes& l, const double* x,
                                 double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c,
-                                double* wmax, int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s) {
+                                double* wmax, int64_t* warg, int64_t* wcnt, int64_t* seg, const ScanPlace& pl,
+                                hipStream_t s) {
     hipLaunchKernelGGL((scan_kernel<T, VEC, NLMAX, MODE>), dim3(c.blocks), dim3(SCAN_THREADS), sizeof(double) * d, s,
                        (const T*)C, (const T*)R, m, d, l.G, l.nl, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt,
-                       seg);
+                       seg, pl);
     return hipGetLastError();
 }
 
 template <typename T, int MODE, int VEC>
 static hipError_t launch_scan_n(const void* C, const void* R, int64_t m, int d, const ScanLanes& l, const double* x,
                                 double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c,
-                                double* wmax, int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s) {
-#define MEB_SCAN_ARGS C, R, m, d, l, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, s
+                                double* wmax, int64_t* warg, int64_t* wcnt, int64_t* seg, const ScanPlace& pl,
+                                hipStream_t s) {
+#define MEB_SCAN_ARGS C, R, m, d, l, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, pl, s
     if (l.nlmax == 2) return launch_scan_v<T, MODE, VEC, 2>(MEB_SCAN_ARGS);
     if (l.nlmax == 4) return launch_scan_v<T, MODE, VEC, 4>(MEB_SCAN_ARGS);
     if (l.nlmax == 8) return launch_scan_v<T, MODE, VEC, 8>(MEB_SCAN_ARGS);
@@ -1508,7 +2325,8 @@ static hipError_t launch_scan_n(const void* C, const void* R, int64_t m, int d, 
 template <int MODE>
 static hipError_t launch_scan_t(const void* C, const void* R, int64_t m, int d, int dtype, const double* x,
                                 double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c,
-                                double* wmax, int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s) {
+                                double* wmax, int64_t* warg, int64_t* wcnt, int64_t* seg, const ScanPlace& pl,
+                                hipStream_t s) {
     const ScanLanes l = scan_lanes(d, dtype);
     if (dtype == 0) {
         if (l.vec == 2) return launch_scan_n<double, MODE, 2>(MEB_SCAN_ARGS);
@@ -1523,10 +2341,12 @@ static hipError_t launch_scan_t(const void* C, const void* R, int64_t m, int d, 
 
 hipError_t launch_scan(int mode, const void* C, const void* R, int64_t m, int d, int dtype, const double* x,
                        double r, double thr, double* slack, float* C32, float* R32, const ScanCfg& c, double* wmax,
-                       int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s) {
-    if (mode == 0) return launch_scan_t<0>(C, R, m, d, dtype, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, s);
-    if (mode == 1) return launch_scan_t<1>(C, R, m, d, dtype, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, s);
-    return launch_scan_t<2>(C, R, m, d, 0, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, s);
+                       int64_t* warg, int64_t* wcnt, int64_t* seg, hipStream_t s, const ScanPlace& pl) {
+    if (mode == 0)
+        return launch_scan_t<0>(C, R, m, d, dtype, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, pl, s);
+    if (mode == 1)
+        return launch_scan_t<1>(C, R, m, d, dtype, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, pl, s);
+    return launch_scan_t<2>(C, R, m, d, 0, x, r, thr, slack, C32, R32, c, wmax, warg, wcnt, seg, pl, s);
 }
 
 hipError_t launch_scan_finalize(const int64_t* wcnt, const double* wmax, const int64_t* warg, int nw, int64_t* offs,
@@ -1634,6 +2454,19 @@ hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+__global__ void widen_f32_kernel(const float* src, double* dst, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+        dst[e] = (double)src[e];
+}
+
+hipError_t launch_widen_f32(const float* src, double* dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(widen_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 // The evaluation pass of ripALM (single-instance launches): the kernel
 // instances for every (precision, load width, loads per lane, trials per
 // lane) and the launch configuration for a shape.
+#include <stdlib.h>
+
 #include "meb_device.h"
 
 namespace meb {
@@ -48,13 +50,34 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     // configuration selects).  A deeper ring (more bytes in flight per wave),
     // where the copy counter allows one, is taken when the LDS it needs does
     // not lower that count, i.e. when registers bound the occupancy anyway.
+    // ring depth forced for tuning sweeps (MEB_PASS_STAGES = 4, 8 or 16)
+    static const int forced_stages = [] {
+        const char* e = getenv("MEB_PASS_STAGES");
+        const int v = e ? atoi(e) : 0;
+        return (v == 4 || v == 8 || v == 16) ? v : 0;
+    }();
     auto resident_waves = [&]() -> int64_t {
         c.stages = DMA_MIN_STAGES;
         int per_cu = pass_blocks_per_cu(dtype, c, d);
-        if (c.dma) {
+        if (c.dma && forced_stages > DMA_MIN_STAGES && forced_stages <= dma_max_stages(c.vec * esize)) {
             PassConfig deep = c;
-            deep.stages = DMA_MAX_STAGES;
-            if (pass_blocks_per_cu(dtype, deep, d) >= per_cu) c.stages = DMA_MAX_STAGES;
+            deep.stages = forced_stages;
+            const int n = pass_blocks_per_cu(dtype, deep, d);
+            if (n >= 1) {
+                c.stages = forced_stages;
+                per_cu = n;
+            }
+        } else if (c.dma) {
+            // the deepest power-of-two ring the copy counter allows that
+            // keeps the occupancy
+            for (int st = dma_max_stages(c.vec * esize); st > DMA_MIN_STAGES; st >>= 1) {
+                PassConfig deep = c;
+                deep.stages = st;
+                if (pass_blocks_per_cu(dtype, deep, d) >= per_cu) {
+                    c.stages = st;
+                    break;
+                }
+            }
         }
         if (per_cu < 1) per_cu = 1;
         int64_t mw = (int64_t)num_cu * per_cu * WPB;
@@ -105,6 +128,10 @@ struct Occupancy {
     template <typename T, int VEC, int NLMAX, int TRL>
     hipError_t go() {
         const size_t lds = pass_lds_bytes<T, VEC, NLMAX>(d, stages);
+        if (lds > LDS_PER_CU) {  // this ring depth does not fit at all
+            n = 0;
+            return hipSuccess;
+        }
         const void* fn = (const void*)pass_kernel<T, VEC, NLMAX, TRL>;
         const hipError_t ea = ensure_dynamic_lds(fn, lds);
         if (ea != hipSuccess) return ea;
@@ -114,7 +141,7 @@ struct Occupancy {
         const int regs = at.numRegs > 0 ? (at.numRegs + 7) / 8 * 8 : 128;
         const int by_vgpr = 512 / regs;
         const size_t per_block = lds + at.sharedSizeBytes;
-        const int by_lds = per_block > 0 ? (int)((160 * 1024) / per_block) : 8;
+        const int by_lds = per_block > 0 ? (int)(LDS_PER_CU / per_block) : 8;
         n = by_vgpr < by_lds ? by_vgpr : by_lds;
         if (n > 8) n = 8;
         return hipSuccess;

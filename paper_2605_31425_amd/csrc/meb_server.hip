@@ -32,7 +32,6 @@
 
 namespace meb {
 
-int check_common(const void* C, int64_t m, int32_t d, int32_t dtype);
 int check_solve_options(const meb_options* o);
 
 // ---------------------------------------------------------------------------
@@ -146,6 +145,7 @@ struct Slot {
     uint64_t ev_seq = 0;      // enqueue order of that event
     bool waiting = false;
     bool in_run = false;  // its table entry is stepped by ticks
+    int lane = 0;         // the lane (stream) its work runs on
     int err = 0;
     std::string msg;
 };
@@ -161,9 +161,16 @@ struct Tick {
 
 using namespace meb;
 
+// Requests run in one of two lanes, each with its own stream and its own
+// ticks: a tick steps every job of its lane that is inside a ripALM run, so
+// its duration is set by the lane's largest pass.  Small requests (m d below
+// LANE_SPLIT elements) do not wait for the passes of large ones.
+constexpr int NLANES = 2;
+constexpr double LANE_SPLIT = 8e6;
+
 struct meb_server {
     int dev = 0;
-    hipStream_t s = nullptr;
+    hipStream_t ls[NLANES] = {nullptr, nullptr};
     char* pool = nullptr;
     size_t pool_bytes = 0;
     char* pool_jobs = nullptr;  // after the item table
@@ -178,8 +185,9 @@ struct meb_server {
     int* dflag = nullptr;
     double* pinslab = nullptr;  // per-slot job staging
     size_t pin_stride = 0;
-    std::deque<Tick> ticks;
+    std::deque<Tick> ticks[NLANES];
     std::vector<hipEvent_t> tick_events;
+    int64_t lane_ticks[NLANES] = {0, 0};
     uint64_t seq = 0;
     int64_t n_ticks = 0;
     double tick_items = 0;
@@ -204,8 +212,9 @@ struct meb_server {
     int advance(int k);
     int upload_item(int k);
     void complete(int k, int rc);
-    int tick();
-    int retire_tick();
+    int tick(int lane);
+    int retire_tick(int lane);
+    hipStream_t stream_of(int k) const { return ls[slots[k].lane]; }
 };
 
 meb_server::~meb_server() {
@@ -215,7 +224,8 @@ meb_server::~meb_server() {
     if (htab) (void)hipHostFree(htab);
     if (hflag) (void)hipHostFree(hflag);
     if (pinslab) (void)hipHostFree(pinslab);
-    if (s) (void)hipStreamDestroy(s);
+    for (auto st : ls)
+        if (st) (void)hipStreamDestroy(st);
 }
 
 // Admits what fits; returns the slots started.  Called with `mu` held.
@@ -242,6 +252,7 @@ int meb_server::admit_locked(std::vector<int>& started) {
         sl.req = pending[id];
         pending.erase(id);
         sl.off = off;
+        sl.lane = (double)sl.req.m * sl.req.d >= LANE_SPLIT ? 1 : 0;
         sl.t_admit = now_ms();
         sl.waiting = false;
         sl.in_run = false;
@@ -259,8 +270,9 @@ int meb_server::admit_locked(std::vector<int>& started) {
 int meb_server::start_slot(int k) {
     Slot& sl = slots[k];
     sl.job.reset(new Job());
-    CHK(sl.job->init(sl.req.C, sl.req.R, sl.req.m, sl.req.d, &o, pool_jobs + sl.off, sl.req.bytes,
+    CHK(sl.job->init(sl.req.C, sl.req.R, sl.req.m, sl.req.d, MEB_F64, &o, pool_jobs + sl.off, sl.req.bytes,
                      pinslab + (size_t)k * pin_stride, nullptr, nullptr));
+    hipStream_t s = stream_of(k);
     CHK(sl.job->start(s));
     HIPCHK(hipEventRecord(sl.ev, s));
     sl.ev_seq = ++seq;
@@ -275,7 +287,7 @@ int meb_server::upload_item(int k) {
     Job& j = *sl.job;
     htab[k] = j.e->item(j.pa, dflag + k);
     hflag[k] = PM_EVAL;
-    HIPCHK(hipMemcpyAsync(dtab + k, htab + k, sizeof(BatchItem), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dtab + k, htab + k, sizeof(BatchItem), hipMemcpyHostToDevice, stream_of(k)));
     sl.in_run = true;
     return MEB_OK;
 }
@@ -284,6 +296,7 @@ int meb_server::upload_item(int k) {
 int meb_server::advance(int k) {
     Slot& sl = slots[k];
     Job& j = *sl.job;
+    hipStream_t s = stream_of(k);
     sl.waiting = false;
     CHK(j.on_ready(s));
     if (j.done()) return MEB_OK;
@@ -332,28 +345,31 @@ void meb_server::complete(int k, int rc) {
     cv_done.notify_all();
 }
 
-// One solver step for every job inside a run.
-int meb_server::tick() {
+// One solver step for every job of the lane inside a run.
+int meb_server::tick(int lane) {
     std::vector<int> list;
     for (int k = 0; k < max_active; ++k)
-        if (slots[k].used && slots[k].in_run) list.push_back(k);
+        if (slots[k].used && slots[k].in_run && slots[k].lane == lane) list.push_back(k);
     if (list.empty()) return 0;
+    hipStream_t s = ls[lane];
     HIPCHK(launch_tick(dtab, htab, list.data(), (int)list.size(), s));
     for (int k : list) slots[k].job->steps += 1;
     Tick t;
-    t.ev = tick_events[n_ticks % tick_events.size()];
+    // each lane cycles through events of its own (more than it keeps queued)
+    t.ev = tick_events[lane * (TICKS_IN_FLIGHT + 1) + lane_ticks[lane]++ % (TICKS_IN_FLIGHT + 1)];
     HIPCHK(hipEventRecord(t.ev, s));
     t.slots.swap(list);
     tick_items += (double)t.slots.size();
     ++n_ticks;
-    ticks.push_back(std::move(t));
+    ticks[lane].push_back(std::move(t));
     return 1;
 }
 
-// Waits for the oldest tick and ends the runs it finished.
-int meb_server::retire_tick() {
-    Tick t = std::move(ticks.front());
-    ticks.pop_front();
+// Waits for the lane's oldest tick and ends the runs it finished.
+int meb_server::retire_tick(int lane) {
+    Tick t = std::move(ticks[lane].front());
+    ticks[lane].pop_front();
+    hipStream_t s = ls[lane];
     HIPCHK(hipEventSynchronize(t.ev));
     for (int k : t.slots) {
         Slot& sl = slots[k];
@@ -411,20 +427,50 @@ void meb_server::loop() {
             int rc = q == hipSuccess ? advance(k) : fail(MEB_ERR_HIP, hipGetErrorString(q));
             if (rc < 0 || (sl.job && sl.job->done())) complete(k, rc);
         }
-        const int launched = tick();
-        if (launched < 0) {
+        // each lane keeps TICKS_IN_FLIGHT ticks queued; a lane's oldest
+        // tick is retired when it has completed, or waited for when the lane
+        // is full (or idle with ticks left) and nothing else progressed
+        bool bad = false;
+        int full[NLANES];
+        for (int lane = 0; lane < NLANES && !bad; ++lane) {
+            full[lane] = 0;
+            if ((int)ticks[lane].size() < TICKS_IN_FLIGHT) {
+                const int launched = tick(lane);
+                if (launched < 0) {
+                    bad = true;
+                    break;
+                }
+                progressed = progressed || launched > 0;
+                if (launched == 0 && !ticks[lane].empty()) full[lane] = 1;
+            }
+            if ((int)ticks[lane].size() >= TICKS_IN_FLIGHT) full[lane] = 1;
+            while (!ticks[lane].empty() && hipEventQuery(ticks[lane].front().ev) == hipSuccess) {
+                if (retire_tick(lane) < 0) {
+                    bad = true;
+                    break;
+                }
+                progressed = true;
+                full[lane] = 0;
+            }
+        }
+        if (!bad && !progressed) {
+            // both lanes waiting on the device: block on the lane whose
+            // oldest tick was enqueued first
+            int w = -1;
+            for (int lane = 0; lane < NLANES; ++lane)
+                if (full[lane] && !ticks[lane].empty()) {
+                    w = lane;
+                    break;
+                }
+            if (w >= 0) {
+                if (retire_tick(w) < 0) bad = true;
+                progressed = true;
+            }
+        }
+        if (bad) {
             std::lock_guard<std::mutex> g(mu);
             fatal = last_error_text();
             break;
-        }
-        progressed = progressed || launched > 0;
-        if ((int)ticks.size() >= TICKS_IN_FLIGHT || (launched == 0 && !ticks.empty())) {
-            if (retire_tick() < 0) {
-                std::lock_guard<std::mutex> g(mu);
-                fatal = last_error_text();
-                break;
-            }
-            progressed = true;
         }
         if (!progressed) {
             // only readbacks outstanding: wait for the earliest enqueued one
@@ -435,7 +481,7 @@ void meb_server::loop() {
         }
     }
     // fail whatever is left (only after a fatal error)
-    (void)hipStreamSynchronize(s);
+    for (auto st : ls) (void)hipStreamSynchronize(st);
     for (int k = 0; k < max_active; ++k)
         if (slots[k].used) complete(k, fail(MEB_ERR_HIP, fatal.empty() ? "server stopped" : fatal));
     std::lock_guard<std::mutex> g(mu);
@@ -472,6 +518,7 @@ int meb_server_create(void* pool, size_t pool_bytes, const meb_options* opts, in
     const meb_options* o = opts ? opts : &def;
     CHK(check_solve_options(o));
     if (o->profile) return fail(MEB_ERR_ARG, "per-pass profiling is not available in the server");
+    if (o->newton != MEB_NEWTON_DENSE) return fail(MEB_ERR_ARG, "the server solves Newton systems densely");
     std::unique_ptr<meb_server> sv(new meb_server());
     HIPCHK(hipGetDevice(&sv->dev));
     sv->o = *o;
@@ -486,7 +533,7 @@ int meb_server_create(void* pool, size_t pool_bytes, const meb_options* opts, in
     sv->adm.reset(pool_bytes - tab_bytes, max_active);
     sv->slots.resize(max_active);
     for (auto& sl : sv->slots) HIPCHK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
-    sv->tick_events.resize(TICKS_IN_FLIGHT + 1);
+    sv->tick_events.resize(NLANES * (TICKS_IN_FLIGHT + 1));
     for (auto& e : sv->tick_events) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(hipHostMalloc((void**)&sv->htab, sizeof(BatchItem) * (size_t)max_active, hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&sv->hflag, sizeof(int) * (size_t)max_active,
@@ -495,7 +542,7 @@ int meb_server_create(void* pool, size_t pool_bytes, const meb_options* opts, in
     sv->pin_stride = (JobPin::doubles(max_d) + 31) & ~(size_t)31;
     HIPCHK(hipHostMalloc((void**)&sv->pinslab, sizeof(double) * sv->pin_stride * (size_t)max_active,
                          hipHostMallocDefault));
-    HIPCHK(hipStreamCreateWithFlags(&sv->s, hipStreamNonBlocking));
+    for (auto& st : sv->ls) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     sv->th = std::thread([p = sv.get()] { p->loop(); });
     *out = sv.release();
     return MEB_OK;
@@ -507,7 +554,7 @@ int meb_server_submit(meb_server* sv, const void* C, const void* R, int64_t m, i
     CHK(check_common(C, m, d, dtype));
     if (dtype != MEB_F64) return fail(MEB_ERR_ARG, "the server needs FP64 input");
     if (d > sv->max_d) return fail(MEB_ERR_ARG, "d exceeds the server's max_d");
-    const size_t bytes = solve_ws_bytes(m, d, &sv->o);
+    const size_t bytes = solve_ws_bytes(m, d, MEB_F64, &sv->o);
     Request r;
     r.tag = tag;
     r.C = C;

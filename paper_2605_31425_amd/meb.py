@@ -16,15 +16,20 @@ LIB_PATH = os.path.join(_HERE, "libmeb.so")
 
 MEB_OK = 0
 MEB_WARN_MAXITER = 1
+MEB_ERR_ARG, MEB_ERR_HIP, MEB_ERR_WORKSPACE, MEB_ERR_NUMERIC, MEB_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 MEB_F64 = 0
 MEB_F32 = 1
 MEB_MODE_FP64 = 0
 MEB_MODE_MIXED = 1
+MEB_HESS_AUTO, MEB_HESS_F64, MEB_HESS_MFMA_F64, MEB_HESS_MFMA_F32, MEB_HESS_MFMA_BF16 = 0, 1, 2, 3, 4
+_HESS = {"auto": 0, "f64": 1, "mfma_f64": 2, "mfma_f32": 3, "mfma_bf16": 4}
 WANT_PSI, WANT_GRAD, WANT_HESS, WANT_MULT, WANT_DMULT, WANT_KKT = 1, 2, 4, 8, 16, 32
 WANT_ALL = 63
 
 EXPORTS = ["meb_default_options", "meb_last_error", "meb_workspace_size", "meb_eval_workspace_size", "meb_solve",
-           "meb_al_eval", "meb_screen", "meb_check_feasible", "meb_prepare_f32", "meb_chol_workspace_size",
+           "meb_al_eval", "meb_hess_vec", "meb_screen", "meb_check_feasible",
+           "meb_prepare_f32",
+           "meb_chol_workspace_size",
            "meb_chol_solve", "meb_server_create", "meb_server_submit", "meb_server_poll", "meb_server_info",
            "meb_server_destroy", "meb_sched_simulate"]
 
@@ -35,7 +40,9 @@ class Options(ctypes.Structure):
                 ("tol_kkt_low", ctypes.c_double), ("tol_red", ctypes.c_double), ("eps_feas_rel", ctypes.c_double),
                 ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32), ("max_ls", ctypes.c_int32),
                 ("max_reinsert", ctypes.c_int32), ("mode", ctypes.c_int32), ("stall_outer", ctypes.c_int32),
-                ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32), ("hess", ctypes.c_int32),
+                ("first_order_outer", ctypes.c_int32), ("newton", ctypes.c_int32),
+                ("cg_max_iter", ctypes.c_int32), ("cg_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -46,7 +53,8 @@ class Stats(ctypes.Structure):
                 ("pass_ms", ctypes.c_double * 2), ("pass_bytes", ctypes.c_double * 2),
                 ("pass_launches", ctypes.c_int32 * 2), ("reserved", ctypes.c_int32),
                 ("mid_rows", ctypes.c_double * 2), ("mid_rows_max", ctypes.c_double * 2),
-                ("newton_shifted", ctypes.c_int32 * 2), ("inner_breaks", ctypes.c_int32 * 2)]
+                ("newton_shifted", ctypes.c_int32 * 2), ("inner_breaks", ctypes.c_int32 * 2),
+                ("first_order_steps", ctypes.c_int32 * 2), ("cg_iterations", ctypes.c_int32 * 2)]
 
     def as_dict(self):
         return dict(outer=list(self.outer), inner=list(self.inner), passes=list(self.passes), kkt=list(self.kkt),
@@ -55,7 +63,8 @@ class Stats(ctypes.Structure):
                     ms_phase=list(self.ms_phase), pass_ms=list(self.pass_ms), pass_bytes=list(self.pass_bytes),
                     pass_launches=list(self.pass_launches), mid_rows=list(self.mid_rows),
                     mid_rows_max=list(self.mid_rows_max), newton_shifted=list(self.newton_shifted),
-                    inner_breaks=list(self.inner_breaks))
+                    inner_breaks=list(self.inner_breaks), first_order_steps=list(self.first_order_steps),
+                    cg_iterations=list(self.cg_iterations))
 
 
 class ServerResult(ctypes.Structure):
@@ -73,7 +82,9 @@ class ServerStats(ctypes.Structure):
 
 
 class MebError(RuntimeError):
-    pass
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
 
 
 _vp = ctypes.c_void_p
@@ -100,6 +111,8 @@ def _load():
     L.meb_check_feasible.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _dp,
                                      ctypes.c_double, _dp, _i64p, _vp, ctypes.c_int64, _i64p, _vp, ctypes.c_size_t,
                                      _vp]
+    L.meb_hess_vec.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _dp,
+                               ctypes.c_double, ctypes.c_double, _dp, _dp, _vp, ctypes.c_size_t, _vp]
     L.meb_prepare_f32.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _dp, _vp, _vp, _dp, _vp, ctypes.c_size_t,
                                   _vp]
     L.meb_chol_workspace_size.argtypes = [ctypes.c_int32, _szp]
@@ -123,7 +136,7 @@ lib = _load()
 
 def _check(rc):
     if rc < 0:
-        raise MebError(f"libmeb error {rc}: {lib.meb_last_error().decode()}")
+        raise MebError(f"libmeb error {rc}: {lib.meb_last_error().decode()}", rc)
     return rc
 
 
@@ -133,6 +146,10 @@ def options(**kw):
     for k, v in kw.items():
         if k == "mode" and isinstance(v, str):
             v = {"fp64": MEB_MODE_FP64, "mixed": MEB_MODE_MIXED}[v]
+        if k == "hess" and isinstance(v, str):
+            v = _HESS[v]
+        if k == "newton" and isinstance(v, str):
+            v = {"dense": 0, "cg": 1}[v]
         setattr(o, k, v)
     return o
 
@@ -239,6 +256,21 @@ def check_feasible(C, R, r, c, eps, viol_cap=None):
                                   ctypes.byref(am), _ptr(viol) if cap > 0 else None, cap, ctypes.byref(nv), _ptr(ws),
                                   ws.numel(), _stream()))
     return dmax.value, am.value, viol[:min(nv.value, cap)], nv.value
+
+
+def hess_vec(C, R, U, V, x, sigma, tau, q):
+    """meb_hess_vec: the generalized Hessian at x times q, without forming H."""
+    m, d = C.shape
+    dt = _dtype_code(C)
+    nb = ctypes.c_size_t()
+    _check(lib.meb_eval_workspace_size(m, d, dt, ctypes.byref(nb)))
+    ws = _workspace(nb.value, C.device)
+    xh, xp = _host(x)
+    qh, qp = _host(q)
+    out = np.empty(d + 1)
+    _check(lib.meb_hess_vec(_ptr(C), _ptr(R), _ptr(U), _ptr(V), m, d, dt, xp, float(sigma), float(tau), qp,
+                            out.ctypes.data_as(_dp), _ptr(ws), ws.numel(), _stream()))
+    return out
 
 
 def prepare_f32(C, R, origin=None):

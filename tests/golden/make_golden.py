@@ -46,6 +46,32 @@ def make(name):
     print(name, r, st["r_fixed"], st["kkt"], f"{el:.1f}s", flush=True)
 
 
+# The instances of the paper's experiments (Section 5, "Test instances"):
+# the Figure 2 / Table 1 grid and the Figure 3 high-dimensional shapes up to
+# the dimensions this build supports.
+LCG_SHAPES = [(d, m) for d in (20, 30, 40, 50) for m in (1000, 5000, 10000, 50000, 100000)] + \
+             [(d, m) for d in (100, 500, 1000) for m in (1000, 5000)]
+
+
+def make_lcg():
+    out = dict(description="LCG instances of Section 5 (psi_0 = 7, psi_{j+1} = (445 psi_j + 1) mod 4096, "
+                           "values psi_j / 40.96 as r_1, c_1, r_2, c_2, ...)",
+               oracle_tol=1e-12, instances=[])
+    for d, m in LCG_SHAPES:
+        C, R = inputs.lcg_instance(m, d)
+        t = time.time()
+        r, c, st = oracle.ripalm(C, R, tol=1e-12)
+        el = time.time() - t
+        out["instances"].append(dict(d=d, m=m, r_fixed=st["r_fixed"], rbar=r, kkt=st["kkt"], outer=st["outer"],
+                                     inner=st["inner"], oracle_seconds=el, c=c.tolist() if d <= 50 else None))
+        print("lcg", d, m, st["r_fixed"], st["kkt"], f"{el:.1f}s", flush=True)
+    with open(os.path.join(HERE, "oracle_lcg.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(WORKLOADS)):
-        make(n)
+    for n in (sys.argv[1:] or list(WORKLOADS) + ["lcg"]):
+        if n == "lcg":
+            make_lcg()
+        else:
+            make(n)

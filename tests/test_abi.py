@@ -47,7 +47,8 @@ def test_options_defaults_without_gpu():
     sys.path.insert(0, ROOT)
     from paper_2605_31425_amd import meb
     o = meb.options()
-    assert o.rho == 0.9 and o.tol_kkt == 1e-8 and o.tol_kkt_low == 1e-2 and o.mode == meb.MEB_MODE_MIXED
+    assert o.rho == 0.9 and o.tol_kkt == 1e-9 and o.tol_kkt_low == 1e-2 and o.mode == meb.MEB_MODE_MIXED
+    assert o.hess == meb.MEB_HESS_AUTO and o.newton == 0 and o.cg_max_iter == 20 and o.first_order_outer == 0
     n = ctypes.c_size_t()
     assert meb.lib.meb_workspace_size(1000, 10, 0, ctypes.byref(o), ctypes.byref(n)) == 0
     assert n.value > 1000 * 10 * 8

@@ -71,3 +71,16 @@ def test_golden_radius_bracket(name):
     gap = (g["r_fixed"] - lb) / g["r_fixed"]
     print(f"{name}: r_out {g['r_fixed']:.17g} lower bound {lb:.17g} relative gap {gap:.2e}")
     assert gap <= 1e-10
+
+
+@pytest.mark.parametrize("d,m", [(20, 1000), (30, 5000), (40, 1000), (50, 100000)])
+def test_lcg_golden_radius_bracket(d, m):
+    # the paper's LCG instances (Section 5): the stored oracle radius is
+    # bracketed the same way
+    g = {(e["d"], e["m"]): e for e in json.load(open(os.path.join(HERE, "golden", "oracle_lcg.json")))["instances"]}
+    e = g[(d, m)]
+    C, R = inputs.lcg_instance(m, d)
+    lb, reach = certificate(C, R, np.asarray(e["c"]), e["r_fixed"])
+    assert reach == pytest.approx(e["r_fixed"], rel=1e-15, abs=0)
+    assert lb <= e["r_fixed"]
+    assert (e["r_fixed"] - lb) / e["r_fixed"] <= 1e-10, (e["r_fixed"] - lb) / e["r_fixed"]

@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import oracle
-from tests.gpu_common import cone_multipliers, dev, gpu, near_point
+from tests.gpu_common import case_allowance, cone_multipliers, dev, gpu, hess_scale, mult_scale, near_point
 
 pytestmark = gpu
 
@@ -46,17 +46,20 @@ def test_al_eval_parity(m, d, dtype):
             V.astype(np.float32).astype(np.float64)
         R = None if R is None else R.astype(np.float32).astype(np.float64)
     tol = 1e-12 if dtype == "f64" else 1e-5
+    # the FP64-accumulating contraction (the matrix-core forms have tests of their own)
     out = meb.al_eval(dev(C, tdt), dev(R, tdt), dev(U, tdt), dev(V, tdt), x, xbar, sigma, tau, direction=direction,
-                      etas=etas)
+                      etas=etas, want=meb.WANT_ALL | (meb.MEB_HESS_F64 << 8))
     y = x + direction
     ref = oracle.al_eval(C, R, U, V, y, xbar, sigma, tau)
     # scales: sums of magnitudes of the terms
     Up, Vp = ref["U"], ref["V"]
     sg = 1.0 + np.concatenate([[np.abs(Up).sum()], np.abs(Vp).sum(0)]) + tau / sigma * np.abs(y - xbar)
     assert np.all(np.abs(out["g"] - ref["g"]) <= tol * sg), np.abs(out["g"] - ref["g"]).max()
-    nact = ref["counts"][0] + ref["counts"][2]
-    sH = tau / sigma + sigma * max(nact, 1)
-    assert np.abs(out["H"] - ref["H"]).max() <= tol * sH
+    # H per component against the sum of magnitudes of its terms (plus, for
+    # balls on a case boundary to working precision, either case's element)
+    sH = hess_scale(C, R, U, V, y, sigma, tau)
+    aH = case_allowance(C, R, U, V, y, sigma, 10 * tol)
+    assert np.all(np.abs(out["H"] - ref["H"]) <= tol * sH + aH), (np.abs(out["H"] - ref["H"]) / sH).max()
     spsi = abs(y[0]) + sigma / 2 * (np.sum((Up / sigma) ** 2) + np.sum((Vp / sigma) ** 2)) + \
         (np.sum(U ** 2) + np.sum(V ** 2)) / (2 * sigma) + tau / (2 * sigma) * np.sum((y - xbar) ** 2) + 1.0
     assert abs(out["psi"] - ref["psi"]) <= tol * spsi
@@ -67,8 +70,10 @@ def test_al_eval_parity(m, d, dtype):
     assert abs(out["dmult"] - ref["dmult"]) <= tol * sdm
     Un, Vn = out["U"].double().cpu().numpy(), out["V"].double().cpu().numpy()
     sw = np.abs(Up).max() + 1
-    assert np.abs(Un - Up).max() <= tol * sw * 10
-    assert np.abs(Vn - Vp).max() <= tol * sw * 10
+    # updated multipliers per ball against the magnitude of their terms
+    su = mult_scale(C, R, U, V, y, sigma) + 1e-300
+    assert np.all(np.abs(Un - Up) <= tol * su), (np.abs(Un - Up) / su).max()
+    assert np.all(np.abs(Vn - Vp) <= tol * su[:, None]), (np.abs(Vn - Vp) / su[:, None]).max()
     k_ref, parts = oracle.kkt_max(C, R, Up, Vp, y)
     scale_k = [1 + np.abs(Up).sum(), 1 + np.abs(Vp).sum(), 1 + np.abs(y).max() + np.abs(C).max(), 1 + sw,
                (1 + np.abs(y).max() + np.abs(C).max()) * sw]
@@ -193,3 +198,119 @@ def test_al_eval_deterministic_bitwise():
     a = meb.al_eval(dev(C), dev(R), dev(U), dev(V), x, x, 2.0, 1.0)
     b = meb.al_eval(dev(C), dev(R), dev(U), dev(V), x, x, 2.0, 1.0)
     assert a["psi"] == b["psi"] and np.array_equal(a["g"], b["g"]) and np.array_equal(a["H"], b["H"])
+
+
+# ---------------------------------------------------------------------------
+# The rank-one Hessian contraction in each arithmetic (MEB_HESS_*), against
+# the oracle per component, relative to the sum of magnitudes of the terms:
+# FP64 inputs (vector FMAs or FP64 matrix cores) 1e-12; FP32 inputs with
+# FP32 matrix-core accumulation 1e-5; BF16 inputs (8 significant bits, two
+# roundings per product) with FP32 accumulation 1.5e-2.
+# ---------------------------------------------------------------------------
+HESS_CASES = [("f64", "f64", 1e-12), ("f64", "mfma_f64", 1e-12), ("f32", "f64", 1e-5), ("f32", "mfma_f32", 1e-5),
+              ("f32", "mfma_bf16", 1.5e-2)]
+
+
+@pytest.mark.parametrize("m,d", [(4001, 5), (3001, 64), (2500, 100), (1201, 129), (700, 300), (301, 1001)])
+@pytest.mark.parametrize("dtype,hess,tol", HESS_CASES)
+def test_hessian_contraction_arithmetics(m, d, dtype, hess, tol):
+    from paper_2605_31425_amd import meb
+    print(f"hess m={m} d={d} {dtype} {hess}", flush=True)
+    rng, C, R = _inst(7 * m + d, m, d)
+    U, V = cone_multipliers(rng, m, d)
+    x = near_point(rng, C, R)
+    xbar = x + rng.normal(size=d + 1) * 0.01
+    sigma, tau = 2.0, 0.9
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        C, R, U, V = (a.astype(np.float32).astype(np.float64) for a in (C, R, U, V))
+    code = meb._HESS[hess]
+    out = meb.al_eval(dev(C, tdt), dev(R, tdt), dev(U, tdt), dev(V, tdt), x, xbar, sigma, tau,
+                      want=meb.WANT_HESS | (code << 8))
+    ref = oracle.al_eval(C, R, U, V, x, xbar, sigma, tau)
+    assert ref["counts"][2] > 0  # balls in the third projection case exist
+    sH = hess_scale(C, R, U, V, x, sigma, tau)
+    aH = case_allowance(C, R, U, V, x, sigma, 1e-5 if dtype == "f32" else 1e-12)
+    err = np.maximum(np.abs(out["H"] - ref["H"]) - aH, 0.0) / sH
+    assert err.max() <= tol, (err.max(), np.unravel_index(err.argmax(), err.shape))
+    # symmetric to rounding (the two triangles of a diagonal tile multiply the
+    # coefficient into different factors)
+    assert np.all(np.abs(out["H"] - out["H"].T) <= 2 * tol * sH)
+
+
+# ---------------------------------------------------------------------------
+# Full-size evaluation passes: shapes at which every wave streams many batches
+# through its LDS ring (the ring wraps, full 64-ball batches, the FP32 partial
+# sums flushed every 64 balls, the radii and multipliers copied a batch
+# ahead), checked against the oracle's evaluator to the same bars.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,d", [(200_000, 100), (2_000_000, 5), (300_001, 36)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_al_eval_full_size(m, d, dtype):
+    from paper_2605_31425_amd import meb
+    print(f"al_eval full m={m} d={d} {dtype}", flush=True)
+    rng = np.random.default_rng(m + d)
+    C = rng.uniform(-1, 1, size=(m, d))
+    R = rng.uniform(0, 0.1, m)
+    # multipliers on about 1% of the balls (as late in a run)
+    U, V = cone_multipliers(rng, m, d, frac=0.01)
+    x = near_point(rng, C, R)
+    xbar = x + rng.normal(size=d + 1) * 0.01
+    direction = rng.normal(size=d + 1) * 0.02
+    sigma, tau = 3.0, 0.7
+    etas = [1.0, 0.5, 0.25, 0.0]
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        C, R, U, V = (a.astype(np.float32).astype(np.float64) for a in (C, R, U, V))
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    out = meb.al_eval(dev(C, tdt), dev(R, tdt), dev(U, tdt), dev(V, tdt), x, xbar, sigma, tau, direction=direction,
+                      etas=etas, want=meb.WANT_ALL | (meb.MEB_HESS_F64 << 8))
+    y = x + direction
+    ref = oracle.al_eval(C, R, U, V, y, xbar, sigma, tau)
+    Up, Vp = ref["U"], ref["V"]
+    sg = 1.0 + np.concatenate([[np.abs(Up).sum()], np.abs(Vp).sum(0)]) + tau / sigma * np.abs(y - xbar)
+    assert np.all(np.abs(out["g"] - ref["g"]) <= tol * sg), np.abs(out["g"] - ref["g"]).max()
+    sH = hess_scale(C, R, U, V, y, sigma, tau)
+    aH = case_allowance(C, R, U, V, y, sigma, 10 * tol)
+    assert np.all(np.abs(out["H"] - ref["H"]) <= tol * sH + aH), (np.abs(out["H"] - ref["H"]) / sH).max()
+    spsi = abs(y[0]) + sigma / 2 * (np.sum((Up / sigma) ** 2) + np.sum((Vp / sigma) ** 2)) + \
+        (np.sum(U ** 2) + np.sum(V ** 2)) / (2 * sigma) + tau / (2 * sigma) * np.sum((y - xbar) ** 2) + 1.0
+    assert abs(out["psi"] - ref["psi"]) <= tol * spsi
+    for eta, pv in zip(etas, out["psi_trial"]):
+        rt = oracle.al_eval(C, R, U, V, x + eta * direction, xbar, sigma, tau, want_h=False)
+        assert abs(pv - rt["psi"]) <= 10 * tol * spsi, (eta, pv, rt["psi"])
+    sdm = np.sum(Up ** 2) + np.sum(Vp ** 2) + np.sum(U ** 2) + np.sum(V ** 2) + 1e-300
+    assert abs(out["dmult"] - ref["dmult"]) <= tol * sdm
+    su = mult_scale(C, R, U, V, y, sigma) + 1e-300
+    Un, Vn = out["U"].double().cpu().numpy(), out["V"].double().cpu().numpy()
+    assert np.all(np.abs(Un - Up) <= tol * su), (np.abs(Un - Up) / su).max()
+    assert np.all(np.abs(Vn - Vp) <= tol * su[:, None]), (np.abs(Vn - Vp) / su[:, None]).max()
+
+
+# ---------------------------------------------------------------------------
+# The matrix-free Hessian-vector product (meb_hess_vec, the product the CG
+# Newton solver iterates with) against the oracle's H times q, per component
+# relative to the sum of magnitudes of the terms (|H| |q| with the scale of
+# each entry of H).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,d", [(4001, 5), (3001, 64), (2500, 100), (700, 300), (301, 1001), (200_000, 100)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_hess_vec_parity(m, d, dtype):
+    from paper_2605_31425_amd import meb
+    print(f"hess_vec m={m} d={d} {dtype}", flush=True)
+    rng, C, R = _inst(11 * m + d, m, d)
+    U, V = cone_multipliers(rng, m, d, frac=0.3)
+    x = near_point(rng, C, R)
+    q = rng.normal(size=d + 1)
+    sigma, tau = 2.5, 0.8
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        C, R, U, V = (a.astype(np.float32).astype(np.float64) for a in (C, R, U, V))
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    out = meb.hess_vec(dev(C, tdt), dev(R, tdt), dev(U, tdt), dev(V, tdt), x, sigma, tau, q)
+    ref = oracle.al_eval(C, R, U, V, x, x, sigma, tau)
+    Hq = ref["H"] @ q
+    sc = hess_scale(C, R, U, V, x, sigma, tau) @ np.abs(q)
+    al = case_allowance(C, R, U, V, x, sigma, 10 * tol) @ np.abs(q)
+    err = np.abs(out - Hq)
+    assert np.all(err <= tol * sc + al), (err / sc).max()
