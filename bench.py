@@ -145,6 +145,8 @@ def other_workloads(names, log):
             row[f"{mode}_radius_relerr_vs_oracle"] = abs(r - g["r_fixed"]) / g["r_fixed"] if g else None
             row[f"{mode}_passes"] = st["passes"]
             row[f"{mode}_newton_steps"] = st["inner"]
+            row[f"{mode}_ms_phase"] = [round(x, 3) for x in st["ms_phase"]]
+            row[f"{mode}_mid_rows_max"] = st["mid_rows_max"]
             if mode == "mixed":
                 row["kept_for_fp64"] = st["n_red"]
                 row["reinsert_rounds"] = st["reinsert_rounds"]

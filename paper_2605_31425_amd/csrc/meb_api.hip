@@ -178,7 +178,10 @@ int Engine::step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0,
         return MEB_OK;
     }
     if (a.want_mid) HIPCHK(launch_syrk(syrk_args(a.C, U, V), s));
-    if (control) HIPCHK(launch_control(state, sl, rl, red, flag, s));
+    if (control) {
+        HIPCHK(launch_control(state, sl, rl, red, nullptr, s));
+        HIPCHK(launch_newton(state, sl, flag, s));
+    }
     return MEB_OK;
 }
 

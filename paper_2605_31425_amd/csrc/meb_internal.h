@@ -72,6 +72,9 @@ enum StateSlot : int {
     S_CG_RZ,         // r^T z of the current CG iteration
     S_CG_B2,         // ||b||^2 of the current system
     S_NCG,           // CG iterations in total
+    S_SHIFT_TRY,     // raises of the Newton system's diagonal tried for the current direction
+    S_SHIFT_MU0,     // first raise mu of the current direction
+    S_SHIFT_MU,      // raise in effect
     S_NSCALAR = 64
 };
 
@@ -154,11 +157,13 @@ struct RecLayout {
 // V row is written).
 constexpr int ACT_NC = 7;
 
-static_assert(S_NCG < S_NSCALAR, "state scalars fit their slots");
+static_assert(S_SHIFT_MU < S_NSCALAR, "state scalars fit their slots");
 
 // Pass modes.  PM_CG: a Newton direction is being computed by conjugate
 // gradients (set by the control step, cleared by the CG finish step).
-enum PassMode : int { PM_EVAL = 0, PM_MULT = 1, PM_DONE = 2, PM_CG = 3 };
+// PM_SOLVE: the control step asks the Newton kernel of the step for a
+// direction (cleared by it).
+enum PassMode : int { PM_EVAL = 0, PM_MULT = 1, PM_DONE = 2, PM_CG = 3, PM_SOLVE = 4 };
 
 // Arguments of the matrix-free Newton solve (conjugate gradients with
 // Hessian-vector products over the mid list of the last pass).
@@ -308,6 +313,7 @@ hipError_t launch_pass_group(const BatchItem* dtab, const TickList& L, int block
 hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* slots, int n, hipStream_t s);
 int pass_variant(int dtype, const PassConfig& cfg);
 size_t control_lds_bytes(int n1);
+size_t newton_lds_bytes(int n1);
 
 // ----------------------------------------------------------------------------
 // Launchers (meb_kernels.hip).  All return hipError_t of the launch.
@@ -332,6 +338,9 @@ hipError_t launch_syrk(const SyrkArgs& a, hipStream_t s);
 hipError_t launch_cg_iter(const CgArgs& a, hipStream_t s);
 // the direction from a finished CG solve; `flag` as for the control step
 hipError_t launch_cg_finish(double* state, StateLayout sl, int* flag, hipStream_t s);
+// the Newton solve of a step (nothing unless the control step asked for one);
+// `flag` (nullable) receives the state's mode after it
+hipError_t launch_newton(double* state, StateLayout sl, int* flag, hipStream_t s);
 int syrk_ksplit(int d);
 hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag_host_mapped,
                           hipStream_t s);

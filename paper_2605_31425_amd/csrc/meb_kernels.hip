@@ -55,7 +55,7 @@ __device__ __forceinline__ bool syrk_prologue(const SyrkArgs& a, int bx, int by,
     __shared__ int wtot[256 / WAVE];
     double* st = a.state;
     const int mode = (int)st[S_MODE];
-    if (mode == PM_DONE) return false;
+    if (mode != PM_EVAL && mode != PM_MULT) return false;  // done, or a Newton system being re-solved
     const RecLayout rl = a.rl;
     const double* red = a.red;
     c.have_dir = (mode == PM_EVAL) && st[S_HAVE_DIR] != 0.0;
@@ -1147,6 +1147,10 @@ constexpr int CTRL_THREADS = 1024;
 // the control kernel also keeps CTRL_THREADS doubles of scratch in LDS
 constexpr int CTRL_CHOL_LDS_MAX_N = 132;  // 1024 + 132 x 133 doubles < 160 KiB
 constexpr int CTRL_SHIFT_TRIES = 8;       // raises of the diagonal before an inner solve gives up
+// systems above what registers and LDS hold take the blocked factorization
+__host__ __device__ inline bool newton_large(int n1) {
+    return !(n1 >= 1 && n1 <= RCH_MAX_N) && n1 > CTRL_CHOL_LDS_MAX_N;
+}
 // LDS scratch of the control step: two n1-vectors and the wave sums of a
 // block reduction after them, and at least one double per thread
 __host__ __device__ inline int ctrl_scratch_doubles(int n1) {
@@ -1229,12 +1233,11 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 
 __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayout rl, const double* red) {
     extern __shared__ __align__(16) double sm[];
-    double* scratch = sm;                            // ctrl_scratch_doubles(n1)
-    double* lmat = sm + ctrl_scratch_doubles(sl.n1);  // Cholesky matrix when it fits
-    __shared__ int s_next;                   // 0 = continue to EVAL_AT_BASE, 1 = return
+    double* scratch = sm;  // ctrl_scratch_doubles(n1)
+    __shared__ int s_next;  // 0 = continue to EVAL_AT_BASE, 1 = return
     __shared__ double s_eta;
     const int mode = (int)st[S_MODE];
-    if (mode == PM_DONE) return;
+    if (mode != PM_EVAL && mode != PM_MULT) return;  // done, or a Newton system being re-solved
     const int n1 = sl.n1, d = n1 - 1;
     const double L = st[S_L];
     const double sigma = st[S_SIGMA];
@@ -1560,92 +1563,8 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
         }
         return;
     }
-    // Newton direction: H dir = -g, H assembled by the contraction.  H is
-    // positive definite through its (tau/sigma) I term in exact arithmetic
-    // (Section 4); rounding in its assembly can still produce a pivot that is
-    // not positive.  Breakdown guard: the diagonal is raised by
-    // mu = max(tau/sigma, 4 eps mean_k H_kk), then 16 mu, 256 mu, ... (at
-    // most CTRL_SHIFT_TRIES raises) and the system solved again -- a shifted
-    // system still gives a descent direction for the line search; if no shift
-    // succeeds, the inner solve ends at the current iterate.
-    const bool large = !rch_fits(n1, blockDim.x) && n1 > CTRL_CHOL_LDS_MAX_N;
-    double* hdiag = scratch + n1;  // the large path factorizes H in place: its diagonal is kept here
-    if (large) {
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) hdiag[k] = H[k * n1 + k];
-        __syncthreads();
-    }
-    int rc = 1;
-    double mu0 = 0.0, mu = 0.0;
-    for (int attempt = 0; attempt <= CTRL_SHIFT_TRIES && rc != 0; ++attempt) {
-        if (attempt == 1) {
-            double ptr = 0.0;
-            for (int k = threadIdx.x; k < n1; k += blockDim.x) ptr += large ? hdiag[k] : H[k * n1 + k];
-            const double tr = block_sum(ptr, scratch + 2 * n1);
-            mu0 = fmax(tau / sgm, 4.0 * eps * fabs(tr) / n1);
-        }
-        if (attempt > 0) {
-            const double mu_new = mu0 * (double)(1u << (4 * (attempt - 1)));
-            if (large) {
-                // restore the lower triangle from the untouched upper one
-                for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) {
-                    const int i = e / n1, j = e % n1;
-                    if (i > j) H[e] = H[j * n1 + i];
-                    if (i == j) H[e] = hdiag[i] + mu_new;
-                }
-            } else {
-                for (int k = threadIdx.x; k < n1; k += blockDim.x) H[k * n1 + k] += mu_new - mu;
-            }
-            mu = mu_new;
-            __syncthreads();
-        }
-        if (rch_fits(n1, blockDim.x)) {
-            double* bv = scratch;
-            for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
-            __syncthreads();
-            rc = chol_solve_regs(n1, H, bv, bv, lmat);
-            for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
-            __syncthreads();
-        } else if (n1 <= CTRL_CHOL_LDS_MAX_N) {
-            // LDS: scratch = [rd (n1) | rhs (n1)], lmat = H with an odd leading dimension
-            const int ld = chol_ld(n1);
-            double* rd = scratch;
-            double* bv = scratch + n1;
-            for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) lmat[(e / n1) * ld + e % n1] = H[e];
-            for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
-            __syncthreads();
-            rc = chol_solve_lds(n1, ld, lmat, bv, rd);
-            for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
-            __syncthreads();
-        } else {
-            // blocked factorization in place (global memory), rhs in LDS
-            double* bv = scratch;
-            for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
-            __syncthreads();
-            rc = chol_solve_blocked(n1, H, bv, lmat);
-            for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
-            __syncthreads();
-        }
-    }
-    if (rc != 0) {
-        // no shift helped: end the inner solve here (multiplier update next)
-        if (threadIdx.x == 0) {
-            st[S_NBREAK] += 1.0;
-            st[S_MODE] = (double)PM_MULT;
-            st[S_HAVE_DIR] = 0.0;
-            st[S_FLOOR] = 0.0;
-        }
-        return;
-    }
-    if (threadIdx.x == 0 && mu > 0.0) st[S_NSHIFT] += 1.0;
-    double pgd = 0.0;
-    for (int k = threadIdx.x; k < n1; k += blockDim.x) pgd += gb[k] * dir[k];
-    const double gd = block_sum(pgd, scratch);
-    if (threadIdx.x == 0) {
-        st[S_GD] = gd;
-        st[S_HAVE_DIR] = 1.0;
-        st[S_LSH] = 0.0;
-        st[S_MODE] = (double)PM_EVAL;
-    }
+    // the Newton system H dir = -g is solved by the next kernel of the step
+    if (threadIdx.x == 0) st[S_MODE] = (double)PM_SOLVE;
 }
 
 // ---------------------------------------------------------------------------
@@ -1936,6 +1855,149 @@ hipError_t launch_cg_finish(double* state, StateLayout sl, int* flag, hipStream_
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Newton step of the semismooth Newton method (Algorithm 2): H dir = -g in
+// FP64 with the H the contraction assembled and the g the control step left
+// in the state, then the Armijo search that follows.  Its own kernel (after
+// the control step, which sets PM_SOLVE when a direction is needed): the
+// factorizations keep their matrices in registers, and the control logic
+// beside them would force spills.
+// ---------------------------------------------------------------------------
+// LARGE: the instance of the blocked factorization (n > CTRL_CHOL_LDS_MAX_N);
+// otherwise the register and LDS factorizations.  Separate instances keep the
+// register-resident factorization free of the blocked one's register needs.
+template <bool LARGE>
+__device__ __forceinline__ void newton_body(double* st, StateLayout sl) {
+    extern __shared__ __align__(16) double sm[];
+    if ((int)st[S_MODE] != PM_SOLVE) return;
+    if (LARGE != newton_large(sl.n1)) return;
+    double* scratch = sm;                            // ctrl_scratch_doubles(n1)
+    double* lmat = sm + ctrl_scratch_doubles(sl.n1);  // Cholesky matrix when it fits
+    const int n1 = sl.n1;
+    const double tau = st[S_TAU];
+    const double eps = st[S_EPS];
+    const double sgm = st[S_SIGMA];
+    double* dir = st + sl.dir;
+    double* gb = st + sl.gb;
+    double* H = st + sl.H;
+    // Newton direction: H dir = -g, H assembled by the contraction.  H is
+    // positive definite through its (tau/sigma) I term in exact arithmetic
+    // (Section 4); rounding in its assembly can still produce a pivot that is
+    // not positive.  Breakdown guard: the diagonal is raised by
+    // mu = max(tau/sigma, 4 eps mean_k H_kk), then 16 mu, 256 mu, ... (at
+    // most CTRL_SHIFT_TRIES raises) and the system solved again -- a shifted
+    // system still gives a descent direction for the line search; if no shift
+    // succeeds, the inner solve ends at the current iterate.
+    // One attempt per launch: when a pivot is not positive, the step ends
+    // with the mode still PM_SOLVE, the next step's pass, contraction and
+    // control step do nothing, and its Newton launch tries the next raise
+    // (a loop here would keep the register-resident factorization's state
+    // live across attempts and spill).
+    constexpr bool large = LARGE;
+    // the large path factorizes H in place (lower triangle); the diagonal of
+    // the assembled H is kept in the state's spare vector (the accelerated
+    // gradient method's previous iterate, unused while Newton steps run)
+    double* hdiag = st + sl.tmp;
+    const int attempt = (int)st[S_SHIFT_TRY];
+    if (large && attempt == 0) {
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) hdiag[k] = H[(size_t)k * n1 + k];
+        __syncthreads();
+    }
+    double mu = 0.0;
+    if (attempt > 0) {
+        if (attempt == 1) {
+            double ptr = 0.0;
+            for (int k = threadIdx.x; k < n1; k += blockDim.x) ptr += large ? hdiag[k] : H[(size_t)k * n1 + k];
+            const double tr = block_sum(ptr, scratch + 2 * n1);
+            if (threadIdx.x == 0) st[S_SHIFT_MU0] = fmax(tau / sgm, 4.0 * eps * fabs(tr) / n1);
+            __syncthreads();
+        }
+        const double mu_prev = st[S_SHIFT_MU];
+        mu = st[S_SHIFT_MU0] * (double)(1u << (4 * (attempt - 1)));
+        if (large) {
+            // restore the lower triangle from the untouched upper one, and the
+            // diagonal (kept before the first attempt) raised by mu
+            for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) {
+                const int i = e / n1, j = e % n1;
+                if (i > j) H[e] = H[(size_t)j * n1 + i];
+                if (i == j) H[e] = hdiag[i] + mu;
+            }
+        } else {
+            for (int k = threadIdx.x; k < n1; k += blockDim.x) H[(size_t)k * n1 + k] += mu - mu_prev;
+        }
+        __syncthreads();
+    }
+    int rc = 0;
+    if constexpr (LARGE) {
+        // blocked factorization in place (global memory), rhs in LDS
+        double* bv = scratch;
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
+        __syncthreads();
+        rc = chol_solve_blocked(n1, H, bv, lmat);
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
+        __syncthreads();
+    } else if (rch_fits(n1, blockDim.x)) {
+        double* bv = scratch;
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
+        __syncthreads();
+        rc = chol_solve_regs(n1, H, bv, bv, lmat);
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
+        __syncthreads();
+    } else {
+        // LDS: scratch = [rd (n1) | rhs (n1)], lmat = H with an odd leading dimension
+        const int ld = chol_ld(n1);
+        double* rd = scratch;
+        double* bv = scratch + n1;
+        for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) lmat[(e / n1) * ld + e % n1] = H[e];
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
+        __syncthreads();
+        rc = chol_solve_lds(n1, ld, lmat, bv, rd);
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
+        __syncthreads();
+    }
+    if (rc != 0) {
+        if (threadIdx.x == 0) {
+            if (attempt < CTRL_SHIFT_TRIES) {
+                // the next step's Newton launch tries a larger raise
+                st[S_SHIFT_TRY] = (double)(attempt + 1);
+                st[S_SHIFT_MU] = mu;
+            } else {
+                // no raise helped: end the inner solve here (multiplier update next)
+                st[S_NBREAK] += 1.0;
+                st[S_MODE] = (double)PM_MULT;
+                st[S_HAVE_DIR] = 0.0;
+                st[S_FLOOR] = 0.0;
+                st[S_SHIFT_TRY] = 0.0;
+                st[S_SHIFT_MU] = 0.0;
+            }
+        }
+        return;
+    }
+    if (threadIdx.x == 0) {
+        st[S_SHIFT_TRY] = 0.0;
+        st[S_SHIFT_MU] = 0.0;
+    }
+    if (threadIdx.x == 0 && mu > 0.0) st[S_NSHIFT] += 1.0;
+    double pgd = 0.0;
+    for (int k = threadIdx.x; k < n1; k += blockDim.x) pgd += gb[k] * dir[k];
+    const double gd = block_sum(pgd, scratch);
+    if (threadIdx.x == 0) {
+        st[S_GD] = gd;
+        st[S_HAVE_DIR] = 1.0;
+        st[S_LSH] = 0.0;
+        st[S_MODE] = (double)PM_EVAL;
+    }
+}
+
+// `flag` (nullable, typically host-mapped) receives the state's mode after
+// the step.
+template <bool LARGE>
+__global__ __launch_bounds__(CTRL_THREADS) void newton_kernel(double* st, StateLayout sl, int* flag) {
+    newton_body<LARGE>(st, sl);
+    if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
+}
+
 // `flag` (nullable, typically host-mapped) receives the state's mode after
 // the step, so a host can learn that the run has ended without a copy.
 __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, StateLayout sl, RecLayout rl,
@@ -1944,7 +2006,9 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
     if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
 }
 
-size_t control_lds_bytes(int n1) {
+size_t control_lds_bytes(int n1) { return sizeof(double) * (size_t)ctrl_scratch_doubles(n1); }
+
+size_t newton_lds_bytes(int n1) {
     size_t lds = sizeof(double) * (size_t)ctrl_scratch_doubles(n1);
     if (rch_fits(n1, CTRL_THREADS))
         lds += sizeof(double) * rch_lds_doubles(n1);
@@ -1953,6 +2017,19 @@ size_t control_lds_bytes(int n1) {
     else
         lds += sizeof(double) * (size_t)bch_lds_doubles();
     return lds;
+}
+
+hipError_t launch_newton(double* state, StateLayout sl, int* flag, hipStream_t s) {
+    const size_t lds = newton_lds_bytes(sl.n1);
+    const bool big = newton_large(sl.n1);
+    const void* fn = big ? (const void*)newton_kernel<true> : (const void*)newton_kernel<false>;
+    hipError_t ea = ensure_dynamic_lds(fn, lds);
+    if (ea != hipSuccess) return ea;
+    if (big)
+        hipLaunchKernelGGL(newton_kernel<true>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag);
+    else
+        hipLaunchKernelGGL(newton_kernel<false>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag);
+    return hipGetLastError();
 }
 
 hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag, hipStream_t s) {
@@ -1985,7 +2062,15 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_batch_kernel(const Batch
     const BatchItem& it = tab[L.slot[blockIdx.x]];
     double* st = const_cast<double*>(it.pa.state);
     control_body(st, it.pa.sl, it.pa.rl, it.pa.red);
-    if (threadIdx.x == 0 && it.flag) *it.flag = (int)st[S_MODE];
+}
+
+template <bool LARGE>
+__global__ __launch_bounds__(CTRL_THREADS) void newton_batch_kernel(const BatchItem* tab, TickList L) {
+    const BatchItem& it = tab[L.slot[blockIdx.x]];
+    double* st = const_cast<double*>(it.pa.state);
+    newton_body<LARGE>(st, it.pa.sl);
+    // the flag after the last kernel of the item's step
+    if (threadIdx.x == 0 && it.flag && (LARGE || !newton_large(it.pa.sl.n1))) *it.flag = (int)st[S_MODE];
 }
 
 namespace {
@@ -2054,8 +2139,30 @@ hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* 
         const hipError_t ea = ensure_dynamic_lds((const void*)control_batch_kernel, lds);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(control_batch_kernel, dim3(cn), dim3(CTRL_THREADS), lds, s, dtab, L);
-        const hipError_t e = hipGetLastError();
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        // the Newton solves: the small systems' instance over every item, then
+        // the large systems' instance (items of the other kind return)
+        size_t nlds = 0;
+        bool any_large = false;
+        for (int k = 0; k < cn; ++k) {
+            const int n1 = htab[sl[k]].pa.sl.n1;
+            const size_t b = newton_lds_bytes(n1);
+            if (b > nlds) nlds = b;
+            any_large = any_large || newton_large(n1);
+        }
+        const hipError_t eb = ensure_dynamic_lds((const void*)newton_batch_kernel<false>, nlds);
+        if (eb != hipSuccess) return eb;
+        hipLaunchKernelGGL(newton_batch_kernel<false>, dim3(cn), dim3(CTRL_THREADS), nlds, s, dtab, L);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (any_large) {
+            const hipError_t ec = ensure_dynamic_lds((const void*)newton_batch_kernel<true>, nlds);
+            if (ec != hipSuccess) return ec;
+            hipLaunchKernelGGL(newton_batch_kernel<true>, dim3(cn), dim3(CTRL_THREADS), nlds, s, dtab, L);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
