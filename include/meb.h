@@ -273,6 +273,23 @@ int meb_check_feasible(const void* C, const void* R, int64_t m, int32_t d, int32
                        const double* c, double eps, double* delta_max, int64_t* argmax, int64_t* viol_idx,
                        int64_t viol_cap, int64_t* n_viol, void* ws, size_t ws_bytes, void* stream);
 
+/* meb_check_feasible without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops that forbid
+ * allocation).  Same arguments, results and error behaviour as
+ * meb_check_feasible, minus ws / ws_bytes.  Its scratch (about 540 KB: the
+ * center c, per-wave maxima and counts, their prefix) is a fixed array inside
+ * the library, one copy per device, held until the process ends; the call
+ * allocates nothing.  It returns MEB_ERR_UNSUPPORTED on a device whose scan
+ * needs more than 16384 wave slots (more than 512 compute units).  When some
+ * ball is violated and viol_cap > 0 the data are read twice (a counting pass,
+ * then a pass that writes each index to its final place).  All calls on one
+ * device share the scratch: calls that overlap in time on one device (from
+ * several host threads or streams) race and give undefined results.
+ * Returns after synchronizing the stream. */
+int meb_check_feasible_noalloc(const void* C, const void* R, int64_t m, int32_t d, int32_t dtype, double r,
+                               const double* c, double eps, double* delta_max, int64_t* argmax, int64_t* viol_idx,
+                               int64_t viol_cap, int64_t* n_viol, void* stream);
+
 /* Precision preparation for the screening run: C32[i] = float(C[i] - origin)
  * (row-wise, origin host d, nullable = 0), R32[i] = float(R[i]) (R32 unused
  * if R is NULL), rounded to nearest.  *L_out (host, nullable) receives

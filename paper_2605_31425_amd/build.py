@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libmeb.so")
-SOURCES = ["meb_pass.hip", "meb_pass_eval.hip", "meb_pass_batch.hip", "meb_kernels.hip", "meb_api.hip", "meb_server.hip"]
+SOURCES = ["meb_pass.hip", "meb_pass_eval.hip", "meb_pass_batch.hip", "meb_kernels.hip", "meb_api.hip", "meb_server.hip",
+           "meb_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC, "-pthread"]

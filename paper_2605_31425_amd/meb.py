@@ -27,7 +27,7 @@ WANT_PSI, WANT_GRAD, WANT_HESS, WANT_MULT, WANT_DMULT, WANT_KKT = 1, 2, 4, 8, 16
 WANT_ALL = 63
 
 EXPORTS = ["meb_default_options", "meb_last_error", "meb_workspace_size", "meb_eval_workspace_size", "meb_solve",
-           "meb_al_eval", "meb_hess_vec", "meb_screen", "meb_check_feasible",
+           "meb_al_eval", "meb_hess_vec", "meb_screen", "meb_check_feasible", "meb_check_feasible_noalloc",
            "meb_prepare_f32",
            "meb_chol_workspace_size",
            "meb_chol_solve", "meb_server_create", "meb_server_submit", "meb_server_poll", "meb_server_info",
@@ -113,6 +113,9 @@ def _load():
                                      _vp]
     L.meb_hess_vec.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _dp,
                                ctypes.c_double, ctypes.c_double, _dp, _dp, _vp, ctypes.c_size_t, _vp]
+    L.meb_check_feasible_noalloc.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_double, _dp, ctypes.c_double, _dp, _i64p, _vp, ctypes.c_int64,
+                                             _i64p, _vp]
     L.meb_prepare_f32.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _dp, _vp, _vp, _dp, _vp, ctypes.c_size_t,
                                   _vp]
     L.meb_chol_workspace_size.argtypes = [ctypes.c_int32, _szp]
@@ -271,6 +274,23 @@ def hess_vec(C, R, U, V, x, sigma, tau, q):
     _check(lib.meb_hess_vec(_ptr(C), _ptr(R), _ptr(U), _ptr(V), m, d, dt, xp, float(sigma), float(tau), qp,
                             out.ctypes.data_as(_dp), _ptr(ws), ws.numel(), _stream()))
     return out
+
+
+def check_feasible_noalloc(C, R, r, c, eps, viol_idx=None):
+    """meb_check_feasible_noalloc: like check_feasible, with the library's
+    fixed scratch instead of a workspace.  viol_idx (device int64 tensor,
+    nullable) receives the first viol_idx.numel() violated indices."""
+    m, d = C.shape
+    dt = _dtype_code(C)
+    cap = 0 if viol_idx is None else viol_idx.numel()
+    dmax = ctypes.c_double()
+    am = ctypes.c_int64()
+    nv = ctypes.c_int64()
+    ch, cp = _host(c)
+    _check(lib.meb_check_feasible_noalloc(_ptr(C), _ptr(R), m, d, dt, float(r), cp, float(eps), ctypes.byref(dmax),
+                                          ctypes.byref(am), _ptr(viol_idx) if cap > 0 else None, cap,
+                                          ctypes.byref(nv), _stream()))
+    return dmax.value, am.value, nv.value
 
 
 def prepare_f32(C, R, origin=None):
