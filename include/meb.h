@@ -176,6 +176,10 @@ int meb_default_options(meb_options* opts);
  * next call on the same thread. */
 const char* meb_last_error(void);
 
+/* SHA-256 (hex) over the library's sources, fixed when it was built; lets a
+ * caller recognise a library built from other sources.  Static storage. */
+const char* meb_source_hash(void);
+
 /* Device workspace (bytes) that meb_solve needs for an instance of this
  * shape and options.  Returns MEB_ERR_ARG for m < 1, d < 1, d > MEB_MAX_D. */
 int meb_workspace_size(int64_t m, int32_t d, int32_t dtype, const meb_options* opts, size_t* bytes);

@@ -4,6 +4,7 @@ Every HIP translation unit is compiled with packed-FP32 instruction
 selection disabled; the host pass of hipcc warns that it does not know that
 target feature, which is harmless.
 """
+import hashlib
 import os
 import subprocess
 import sys
@@ -20,8 +21,22 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-u
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC, "-pthread"]
 
 
-def _compile(src, obj):
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def source_hash():
+    """SHA-256 over the library's sources (csrc/ and include/meb.h), names
+    and contents; compiled into libmeb.so and returned by meb_source_hash(),
+    so that a library built from other sources can be recognised."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    for path in [os.path.join(CSRC, f) for f in files] + [os.path.join(INCLUDE, "meb.h")]:
+        h.update(os.path.basename(path).encode() + b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
+def _compile(src, obj, defs=()):
+    cmd = [HIPCC, *FLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -33,8 +48,9 @@ def build(verbose=False):
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in SOURCES]
+    defs = [f'-DMEB_SOURCE_HASH="{source_hash()}"']
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        logs = list(ex.map(_compile, SOURCES, objs))
+        logs = list(ex.map(lambda so: _compile(so[0], so[1], defs), zip(SOURCES, objs)))
     if verbose:
         for l in logs:
             if l.strip():

@@ -64,10 +64,40 @@ void Engine::setup(int64_t m_, int d_, int dtype_) {
     pc = choose_pass_config(m, d, dtype, device_cus());
     sl = StateLayout::make(d);
     rl = RecLayout::make(d);
-    ksplit = syrk_ksplit(d);
+    ksplit = syrk_ksplit(m, d, pc.nwaves);
+    rec_cap = pc.nwaves;
+    list_cap = (int64_t)pc.nwaves * pc.bw;
+    ks_cap = ksplit;
     mm = SYRK_VEC;
     // a line-search pass skips the contraction above this many rows
     skip_k = std::max(4096.0, 16.0 * d);
+}
+
+// For n <= m the configuration takes one step per wave while n fits the
+// resident waves, and more steps per wave beyond (fewer waves than at the
+// threshold), so the wave count peaks at the larger instance's resident
+// waves; a wave's range is bw(n) <= bw at the smaller instance's resident
+// waves, and the lists hold at most n + WPB bw(n) entries.
+void Engine::reserve_subsets() {
+    const int64_t bpw = WAVE / pc.G;
+    const int64_t wmax = ((int64_t)pc.fill_max + WPB - 1) / WPB * WPB;
+    rec_cap = std::max<int64_t>(rec_cap, wmax);
+    const int64_t steps = (m + bpw - 1) / bpw;
+    const int64_t fmin = std::max(1, pc.fill_min);
+    const int64_t bw_max = (steps + fmin - 1) / fmin * bpw;
+    list_cap = std::max<int64_t>(list_cap, m + (int64_t)WPB * bw_max);
+    ks_cap = std::max(ks_cap, syrk_ksplit(m, d, (int)rec_cap));
+}
+
+bool Engine::resize_within(int64_t n) {
+    const int64_t rc = rec_cap, lc = list_cap;
+    const int kc = ks_cap;
+    setup(n, d, dtype);
+    if (rec_cap > rc || list_cap > lc || ksplit > kc) return false;
+    rec_cap = rc;
+    list_cap = lc;
+    ks_cap = kc;
+    return true;
 }
 
 PassArgs Engine::args(const void* C, const void* R, void* U, void* V) const {
@@ -254,7 +284,10 @@ int enq_prepare(const double* C, const double* R, int64_t m, int d, const double
 // ---------------------------------------------------------------------------
 void SolveWs::setup(int64_t m, int d, const meb_options* o) {
     e64.setup(m, d, MEB_F64);
-    if (o->mode == MEB_MODE_MIXED) e32.setup(m, d, MEB_F32);
+    if (o->mode == MEB_MODE_MIXED) {
+        e32.setup(m, d, MEB_F32);
+        e64.reserve_subsets();  // the FP64 run then takes the reduced set
+    }
     scan.setup(m, d);
 }
 
@@ -532,10 +565,10 @@ int Job::start_fp64_reduced(hipStream_t s) {
     // size inside the same region (the carving grows with m)
     Engine& eng = w.e64;
     char* region = (char*)eng.state;
-    const size_t region_bytes = engine_bytes(m, d, MEB_F64);
-    if (engine_bytes(n_red, d, MEB_F64) > region_bytes) return fail(MEB_ERR_WORKSPACE, "reduced engine does not fit");
-    eng.setup(n_red, d, MEB_F64);
-    Arena sub{region, region_bytes, 0};
+    Sizer full;
+    eng.carve(full);
+    if (!eng.resize_within(n_red)) return fail(MEB_ERR_WORKSPACE, "reduced engine does not fit");
+    Arena sub{region, full.off, 0};
     eng.carve(sub);
     return begin_run(1, eng, w.Cred, R ? (const void*)w.Rred : nullptr, w.U64, w.V64, xw.data(), sigma_w, o.tol_kkt,
                      EPS64, s);
@@ -909,6 +942,11 @@ int meb_default_options(meb_options* o) {
 
 const char* meb_last_error(void) { return last_error_text(); }
 
+#ifndef MEB_SOURCE_HASH
+#define MEB_SOURCE_HASH "unknown"
+#endif
+const char* meb_source_hash(void) { return MEB_SOURCE_HASH; }
+
 int meb_workspace_size(int64_t m, int32_t d, int32_t dtype, const meb_options* opts, size_t* bytes) {
     if (!bytes) return fail(MEB_ERR_ARG, "bytes is NULL");
     if (m < 1 || d < 1 || d > MEB_MAX_D) return fail(MEB_ERR_ARG, "bad shape");
@@ -1131,7 +1169,8 @@ int meb_prepare_f32(const double* C, const double* R, int64_t m, int32_t d, cons
 
 int meb_chol_workspace_size(int32_t n, size_t* bytes) {
     if (n < 1 || n > MEB_MAX_D + 1 || !bytes) return fail(MEB_ERR_ARG, "bad size");
-    *bytes = al(sizeof(double) * (size_t)n * n) + al(sizeof(int) * 4) + ALIGN;
+    *bytes = al(sizeof(double) * (size_t)n * n) + al(sizeof(int) * 4) + al(sizeof(double) * (size_t)n) +
+             al(sizeof(double) * MCHOL_NB * MCHOL_NB) + al(sizeof(double)) + ALIGN;
     return MEB_OK;
 }
 
@@ -1146,7 +1185,14 @@ int meb_chol_solve(int32_t n, const double* H, const double* b, double* y, void*
     int* info = ar.take<int>(4);
     HIPCHK(hipMemcpyAsync(A, H, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
     if (y != b) HIPCHK(hipMemcpyAsync(y, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    HIPCHK(launch_chol_solve(n, A, y, info, s));
+    if (n >= MCHOL_MIN_N) {
+        double* yw = ar.take<double>(n);
+        double* ldw = ar.take<double>(MCHOL_NB * MCHOL_NB);
+        double* badw = ar.take<double>(1);
+        HIPCHK(launch_chol_solve_mwg(n, A, y, yw, ldw, badw, info, s));
+    } else {
+        HIPCHK(launch_chol_solve(n, A, y, info, s));
+    }
     int hinfo = 0;
     HIPCHK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

@@ -28,10 +28,6 @@
 
 namespace meb {
 
-constexpr int WAVE = 64;
-constexpr int PASS_THREADS = 256;
-constexpr int WPB = PASS_THREADS / WAVE;
-
 // ---------------------------------------------------------------------------
 // small device helpers
 // ---------------------------------------------------------------------------

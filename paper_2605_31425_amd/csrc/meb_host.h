@@ -90,6 +90,11 @@ struct Engine {
     StateLayout sl{};
     RecLayout rl{};
     int ksplit = 0;
+    // capacities the carving provides: block records, mid / active list
+    // entries, contraction blocks per tile pair (those of m unless raised by
+    // reserve_subsets)
+    int64_t rec_cap = 0, list_cap = 0;
+    int ks_cap = 0;
     int mm = 0;         // contraction arithmetic (SYRK_*), chosen per run
     int cg_iters = 0;   // > 0: matrix-free Newton directions with this many CG launches per step
     double* state = nullptr;
@@ -105,18 +110,23 @@ struct Engine {
     double skip_k = INFINITY;
 
     void setup(int64_t m_, int d_, int dtype_);
+    // raise the capacities so that setup(n) for any n <= m fits the same carving
+    void reserve_subsets();
+    // setup(n) inside the carving of this engine (n <= its m after
+    // reserve_subsets); false if it does not fit
+    bool resize_within(int64_t n);
     template <typename A>
     void carve(A& a) {
         state = a.template take<double>(sl.len);
-        rec = a.template take<double>((size_t)pc.nwaves * rl.len);
+        rec = a.template take<double>((size_t)rec_cap * rl.len);
         red = a.template take<double>((size_t)(SYNC_GROUPS + 1) * rl.len);
-        const size_t cap = (size_t)pc.nwaves * (size_t)pc.bw;
+        const size_t cap = (size_t)list_cap;
         mid_idx = a.template take<int32_t>(cap);
         mid_coef = a.template take<double>(cap);
         mid_cnt = a.template take<int32_t>(pc.nwaves);
         act_idx = a.template take<int32_t>(cap);
         act_coef = a.template take<double>(cap * ACT_NC);
-        syrk = a.template take<double>(syrk_partial_doubles(d, ksplit));
+        syrk = a.template take<double>(syrk_partial_doubles(d, ks_cap));
         sync = a.template take<int>(SYNC_LEN);
     }
     PassArgs args(const void* C, const void* R, void* U, void* V) const;

@@ -75,8 +75,18 @@ enum StateSlot : int {
     S_SHIFT_TRY,     // raises of the Newton system's diagonal tried for the current direction
     S_SHIFT_MU0,     // first raise mu of the current direction
     S_SHIFT_MU,      // raise in effect
+    S_CHOL_BAD,      // 1 when the multi-workgroup factorization met a pivot that is not positive
     S_NSCALAR = 64
 };
+
+constexpr int WAVE = 64;           // lanes per wavefront
+constexpr int PASS_THREADS = 256;  // threads per evaluation-pass block
+constexpr int WPB = PASS_THREADS / WAVE;
+
+// panel width of the blocked Cholesky factorizations, and the system size
+// from which a single-instance Newton step factors across many workgroups
+constexpr int MCHOL_NB = 32;
+constexpr int MCHOL_MIN_N = 320;
 
 struct StateLayout {
     int n1;      // d + 1
@@ -86,6 +96,8 @@ struct StateLayout {
     int ab;      // auxiliary sequence (alpha, beta)
     int gb;      // gradient at xb
     int tmp;     // previous iterate of the accelerated gradient method
+    int yv;      // forward substitution L y = -g of the multi-workgroup factorization
+    int ldiag;   // its current diagonal factor block (MCHOL_NB^2)
     int H;       // (d+1)^2 Hessian / Cholesky factor
     int len;
     static StateLayout make(int d) {
@@ -99,6 +111,8 @@ struct StateLayout {
         s.ab = vec(s.n1);
         s.gb = vec(s.n1);
         s.tmp = vec(s.n1);
+        s.yv = vec(s.n1);
+        s.ldiag = vec(MCHOL_NB * MCHOL_NB);
         s.H = vec(s.n1 * s.n1);
         s.len = o;
         return s;
@@ -157,7 +171,7 @@ struct RecLayout {
 // V row is written).
 constexpr int ACT_NC = 7;
 
-static_assert(S_SHIFT_MU < S_NSCALAR, "state scalars fit their slots");
+static_assert(S_CHOL_BAD < S_NSCALAR, "state scalars fit their slots");
 
 // Pass modes.  PM_CG: a Newton direction is being computed by conjugate
 // gradients (set by the control step, cleared by the CG finish step).
@@ -204,6 +218,7 @@ struct PassConfig {
     int dma;      // rows stream through the waves' LDS rings
     int stages;   // ring blocks per wave (DMA_MIN_STAGES or DMA_MAX_STAGES)
     int spec;     // the instance specialized for this group width may be used
+    int fill_min, fill_max;  // resident waves of the two instances (smaller, larger)
 };
 
 PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu);
@@ -263,7 +278,7 @@ struct SyrkArgs {
     int64_t bw;
     double* out;         // ksplit x pairs x T x T partial blocks
     int* sync;           // tile-pair counters (at SYNC_SYRK)
-    int ksplit;
+    int ksplit;          // blocks per tile pair in the launch (a pass uses a prefix of them)
     int tile;
     int ntile;           // tiles per dimension
     double skip_k;       // in a line-search pass, skip when K exceeds this
@@ -341,7 +356,7 @@ hipError_t launch_cg_finish(double* state, StateLayout sl, int* flag, hipStream_
 // the Newton solve of a step (nothing unless the control step asked for one);
 // `flag` (nullable) receives the state's mode after it
 hipError_t launch_newton(double* state, StateLayout sl, int* flag, hipStream_t s);
-int syrk_ksplit(int d);
+int syrk_ksplit(int64_t m, int d, int nwaves);
 hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag_host_mapped,
                           hipStream_t s);
 // g of a single evaluation, and a copy of the H assembled in the state
@@ -378,6 +393,10 @@ hipError_t launch_scatter_mult(const double* Ured, const double* Vred, const int
 hipError_t launch_dense_mult(const void* U, const void* V, int dtype, int64_t m, int d, double* U_out,
                              double* V_out, hipStream_t s);
 hipError_t launch_chol_solve(int n, double* A, double* b, int* info, hipStream_t s);
+// the multi-workgroup factorization (n >= MCHOL_MIN_N): b (device) holds the
+// solution on return; yw n, ldw MCHOL_NB^2 and badw 1 doubles of scratch
+hipError_t launch_chol_solve_mwg(int n, double* A, double* b, double* yw, double* ldw, double* badw, int* info,
+                                 hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 // dst[k] = (double)src[k] (exact), k < n
 hipError_t launch_widen_f32(const float* src, double* dst, int64_t n, hipStream_t s);

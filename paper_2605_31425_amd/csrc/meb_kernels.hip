@@ -4,6 +4,11 @@
 // decision, relative stopping test, multiplier bookkeeping, FP64 Cholesky
 // solve), the screening and feasibility scans, the precision-preparation
 // and gather kernels, and the multi-instance step of the server.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+
 #include "meb_device.h"
 
 namespace meb {
@@ -23,8 +28,15 @@ namespace meb {
 // ---------------------------------------------------------------------------
 
 constexpr int SYRK_KB = 32;     // mid balls staged per step
-constexpr int SYRK_KSPLIT = 8;  // blocks along the mid list per tile pair
 constexpr int SYRK_SEGS = 1024; // most wave segments one block walks
+// Blocks along the mid list per tile pair: the launch provides up to
+// SyrkArgs::ksplit of them (enough for about SYRK_BLOCKS blocks in all when
+// d is small), and each pass uses one per SYRK_ROWS mid rows, at least
+// SYRK_KSPLIT_MIN; the others return at once.
+constexpr int SYRK_KSPLIT_MIN = 8;
+constexpr int SYRK_KSPLIT_MAX = 1024;
+constexpr int SYRK_BLOCKS = 2048;
+constexpr int SYRK_ROWS = 1024;
 constexpr int SYRK_MT = 64;     // tile width of the matrix-core contraction
 // row stride (elements) of its staged rows: k padded by 16 bytes
 template <int MI>
@@ -32,9 +44,14 @@ __host__ __device__ constexpr int syrk_ldk() {
     return SYRK_KB + (MI == 0 ? 2 : (MI == 1 ? 4 : 8));
 }
 
-int syrk_ksplit(int d) {
-    (void)d;
-    return SYRK_KSPLIT;
+int syrk_ksplit(int64_t m, int d, int nwaves) {
+    const int64_t nt = (d + 31) / 32;  // pairs of the 32-wide tiling (the 64-wide one has fewer)
+    const int64_t pairs = nt * (nt + 1) / 2;
+    int64_t ks = std::max<int64_t>(1, SYRK_BLOCKS / pairs);
+    ks = std::min<int64_t>(ks, (m + SYRK_ROWS - 1) / SYRK_ROWS);
+    ks = std::min<int64_t>(ks, nwaves);
+    ks = std::max<int64_t>(ks, SYRK_KSPLIT_MIN);
+    return (int)std::min<int64_t>(ks, SYRK_KSPLIT_MAX);
 }
 
 // LDS of one contraction block (both arithmetics carve it)
@@ -44,6 +61,7 @@ constexpr size_t SYRK_SMEM = 44 * 1024;
 // exclusive prefix of its wave segments' counts in LDS) and the penalty.
 struct SyrkCtx {
     int I, J;       // tile row / column (I <= J)
+    int ks;         // blocks along the mid list in this pass
     int w0, nseg;   // this block's wave segments
     int total;      // mid entries in them
     double sig;
@@ -65,6 +83,10 @@ __device__ __forceinline__ bool syrk_prologue(const SyrkArgs& a, int bx, int by,
     const bool skip = (c.have_dir && K > a.skip_k) || (mode == PM_EVAL && st[S_FO_ON] != 0.0);
     if (bx == 0 && by == 0 && threadIdx.x == 0) st[S_HSKIP] = skip ? 1.0 : 0.0;
     if (skip) return false;
+    // every block derives the same split from K
+    const double want = ceil(K / (double)SYRK_ROWS);
+    c.ks = want >= (double)a.ksplit ? a.ksplit : max((int)want, SYRK_KSPLIT_MIN);
+    if (by >= c.ks) return false;
     c.sig = (mode == PM_MULT) ? st[S_SIGMA_NEXT] : st[S_SIGMA];
     int p = bx, I = 0;
     while (p >= a.ntile - I) {
@@ -73,7 +95,7 @@ __device__ __forceinline__ bool syrk_prologue(const SyrkArgs& a, int bx, int by,
     }
     c.I = I;
     c.J = I + p;
-    const int per = (a.nwaves + a.ksplit - 1) / a.ksplit;
+    const int per = (a.nwaves + c.ks - 1) / c.ks;
     c.w0 = by * per;
     const int w1 = min(a.nwaves, c.w0 + per);
     c.nseg = max(0, w1 - c.w0);
@@ -137,14 +159,14 @@ __device__ __forceinline__ T syrk_s(const SyrkArgs& a, const T* C, const T* U, c
     return ek + vk * inv;
 }
 
-// The last of the ksplit blocks of a tile pair sums their partial tiles in
+// The last of the c.ks blocks of a tile pair sums their partial tiles in
 // order and writes its part of H (tile pair 0 also the r row and column).
 __device__ __forceinline__ void syrk_finish(const SyrkArgs& a, const SyrkCtx& c, int bx, int npairs) {
     __shared__ int s_last;
     const int T = a.tile;
     published();
     __syncthreads();
-    if (threadIdx.x == 0) s_last = arrive(&a.sync[SYNC_SYRK + bx]) == a.ksplit - 1;
+    if (threadIdx.x == 0) s_last = arrive(&a.sync[SYNC_SYRK + bx]) == c.ks - 1;
     __syncthreads();
     if (!s_last) return;
     double* st = a.state;
@@ -155,17 +177,23 @@ __device__ __forceinline__ void syrk_finish(const SyrkArgs& a, const SyrkCtx& c,
     const double base = tau / c.sig + c.sig * red[rl.ni];
     const int n1 = d + 1;
     double* H = st + a.sl.H;
-    for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
-        const int r = e / T, cc = e % T;
+    // only the entries of the tile that lie inside d x d
+    const int rows = min(T, d - c.I * T), cols = min(T, d - c.J * T);
+    const size_t stride = (size_t)npairs * T * T;
+    for (int e2 = threadIdx.x; e2 < rows * cols; e2 += blockDim.x) {
+        const int r = e2 / cols, cc = e2 % cols;
         const int k = c.I * T + r, l = c.J * T + cc;
-        if (k >= d || l >= d) continue;
-        double part[SYRK_KSPLIT];
-#pragma unroll
-        for (int ks = 0; ks < SYRK_KSPLIT; ++ks)
-            part[ks] = ks < a.ksplit ? ld_shared_dev(a.out + ((size_t)ks * npairs + bx) * T * T + e) : 0.0;
+        const double* src = a.out + (size_t)bx * T * T + r * T + cc;
         double v = 0.0;
+        int ks = 0;
+        for (; ks + 8 <= c.ks; ks += 8) {
+            double part[8];
 #pragma unroll
-        for (int ks = 0; ks < SYRK_KSPLIT; ++ks) v += part[ks];
+            for (int u = 0; u < 8; ++u) part[u] = ld_shared_dev(src + (size_t)(ks + u) * stride);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v += part[u];
+        }
+        for (; ks < c.ks; ++ks) v += ld_shared_dev(src + (size_t)ks * stride);
         if (k == l) v += base + red[rl.sg];
         H[(1 + k) * n1 + 1 + l] = v;
         if (c.I != c.J) H[(1 + l) * n1 + 1 + k] = v;
@@ -429,7 +457,9 @@ __global__ __launch_bounds__(256) void syrk_kernel(SyrkArgs a) {
 
 hipError_t launch_syrk(const SyrkArgs& a, hipStream_t s) {
     const int pairs = a.ntile * (a.ntile + 1) / 2;
-    if ((a.nwaves + a.ksplit - 1) / a.ksplit > SYRK_SEGS || pairs > SYNC_LEN - SYNC_SYRK) return hipErrorInvalidValue;
+    if ((a.nwaves + SYRK_KSPLIT_MIN - 1) / SYRK_KSPLIT_MIN > SYRK_SEGS || a.ksplit < SYRK_KSPLIT_MIN ||
+        a.ksplit > SYRK_KSPLIT_MAX || pairs > SYNC_LEN - SYNC_SYRK)
+        return hipErrorInvalidValue;
     if (a.tile != syrk_tile_of(a.mm)) return hipErrorInvalidValue;
     dim3 grid(pairs, a.ksplit);
     if (a.dtype == 0)
@@ -933,24 +963,24 @@ __device__ __forceinline__ int chol_solve_regs(int n, const double* H, const dou
 __host__ __device__ inline int chol_ld(int n) { return n | 1; }
 
 // ---------------------------------------------------------------------------
-// Blocked Cholesky solve for n above what LDS holds (one workgroup of 16
-// waves, the matrix in global memory, where it stays in L2).  Right-looking
-// in panels of BCH_NB columns:
-//   1. wave 0 factors the diagonal block in registers (lane r holds row r);
-//      the right-hand side rides along as one more row (lane BCH_NB), so the
-//      forward substitution L y = b happens inside the factorization;
-//   2. every thread takes rows below the block: x L_D^T = a by substitution
-//      against L_D in LDS, stores the panel row and updates its entry of b
-//      with the row's share of the forward substitution;
+// Blocked Cholesky solve for n above what LDS holds, the matrix in global
+// memory (where it stays in L2).  Right-looking in panels of BCH_NB columns:
+//   1. one wave factors the diagonal block in registers (lane r holds row
+//      r); the right-hand side rides along as one more row (lane BCH_NB), so
+//      the forward substitution L y = b happens inside the factorization;
+//   2. every row below the block solves x L_D^T = a by substitution against
+//      L_D in LDS, stores the panel row and subtracts the row's share of the
+//      forward substitution from its entry of b;
 //   3. the trailing lower triangle takes the rank-BCH_NB update
 //      A_ij -= sum_k L_ik L_jk in 32 x 32 tiles, one tile per wave at a time,
 //      on FP64 matrix cores (16 x 16 x 4 blocks).
 // Then the back substitution L^T x = y runs block by block from the bottom.
 // Only the lower triangle is written; the upper triangle keeps A (the
-// breakdown guard restores the lower triangle from it).  b (LDS, n) holds
-// the solution on return.  Returns -1 if a pivot is not positive.
+// breakdown guard restores the lower triangle from it).  Two drivers: one
+// workgroup of 16 waves (chol_solve_blocked), or one launch per phase across
+// many workgroups (the mchol kernels below) for the largest systems.
 // ---------------------------------------------------------------------------
-constexpr int BCH_NB = 32;
+constexpr int BCH_NB = MCHOL_NB;
 constexpr int BCH_LD = BCH_NB + 2;  // LDS row stride of L_D (doubles, 16-byte rows)
 __host__ __device__ constexpr int bch_lds_doubles() { return BCH_NB * BCH_LD + BCH_NB; }
 
@@ -963,151 +993,144 @@ __device__ __forceinline__ bch_d4 mfma_f64_16x16x4(double a, double b, bch_d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ int chol_solve_blocked(int n, double* M, double* b, double* lw) {
-    __shared__ int s_bad;
-    double* lrow = lw;                      // L_D row-major, BCH_NB x BCH_LD
-    double* dinv = lw + BCH_NB * BCH_LD;    // 1 / L_D(j, j)
+// Step 1 for the block at kb (nb columns), by one whole wave: lane r < nb
+// loads row r of the block from M, lane BCH_NB the right-hand side bsrc[0,
+// nb).  On return a[] holds this lane's row of L_D (zero above the
+// diagonal), or y_D on the right-hand-side lane; L_D is also in lrow
+// (row-major, BCH_LD stride) and 1 / L_D(j, j) in dinv.  Returns true (on
+// every lane) if a pivot was not positive.
+__device__ __forceinline__ bool bch_diag(int n, int kb, int nb, const double* M, const double* bsrc, double* lrow,
+                                         double* dinv, double (&a)[BCH_NB]) {
+    const int lane = lane_id();
+    const bool is_row = lane < nb;
+    const bool is_rhs = lane == BCH_NB;
+#pragma unroll
+    for (int c = 0; c < BCH_NB; ++c) {
+        double v = 0.0;
+        if (is_row && c <= lane) v = M[(size_t)(kb + lane) * n + kb + c];
+        if (is_rhs && c < nb) v = bsrc[c];
+        a[c] = v;
+    }
+    bool bad = false;
+    double dv = 0.0;
+#pragma unroll
+    for (int j = 0; j < BCH_NB; ++j) {
+        if (j < nb) {
+            const double piv = readlane_f64(a[j], j);
+            bad = bad || !(piv > 0.0);
+            const double inv = rsqrt_f64(piv > 0.0 ? piv : 1.0);
+            // column j of L: lanes below the pivot scale, the pivot lane
+            // takes sqrt(piv); the rhs lane gets y_j
+            a[j] = (lane == j) ? piv * inv : a[j] * inv;
+            if (lane == j) dv = inv;
+            // broadcast column j through LDS: lrow(r, j) = L(r, j), read back
+            // by every lane of the wave
+            if (is_row) lrow[lane * BCH_LD + j] = a[j];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int c = j + 1; c < BCH_NB; ++c) {
+                if (c < nb) {
+                    const double lcj = lrow[c * BCH_LD + j];
+                    a[c] = fma(-a[j], lcj, a[c]);
+                }
+            }
+        }
+    }
+    if (is_row) {
+#pragma unroll
+        for (int c = 0; c < BCH_NB; ++c) {
+            if (c > lane) a[c] = 0.0;
+            lrow[lane * BCH_LD + c] = a[c];
+        }
+        dinv[lane] = dv;
+    }
+    return bad;
+}
+
+// Step 2 for one row below the block: row[0, nb) <- x with x L_D^T = row;
+// returns the row's share sum_c x_c y_c of the forward substitution.
+__device__ __forceinline__ double bch_row(double* row, int nb, const double* lrow, const double* dinv,
+                                          const double* yd) {
+    double x[BCH_NB];
+#pragma unroll
+    for (int c = 0; c < BCH_NB; ++c) x[c] = c < nb ? row[c] : 0.0;
+#pragma unroll
+    for (int j = 0; j < BCH_NB; ++j) {
+        if (j < nb) {
+            double sacc = x[j];
+#pragma unroll
+            for (int c = 0; c < j; ++c) sacc = fma(-x[c], lrow[j * BCH_LD + c], sacc);
+            x[j] = sacc * dinv[j];
+        }
+    }
+    double by = 0.0;
+#pragma unroll
+    for (int c = 0; c < BCH_NB; ++c) {
+        if (c < nb) {
+            row[c] = x[c];
+            by = fma(x[c], yd[c], by);
+        }
+    }
+    return by;
+}
+
+// lower-triangle tile t of T x T tiles (row-major over TI >= TJ)
+__device__ __forceinline__ void bch_tile_of(int t, int& TI, int& TJ) {
+    TI = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (TI * (TI + 1) / 2 > t) --TI;
+    while ((TI + 1) * (TI + 2) / 2 <= t) ++TI;
+    TJ = t - TI * (TI + 1) / 2;
+}
+
+// Step 3 for one 32 x 32 tile of the trailing matrix at (i0, j0), by one
+// whole wave: A_ij -= sum_{k < nb} L(i, kb + k) L(j, kb + k), lower part.
+__device__ __forceinline__ void bch_tile(int n, double* M, int kb, int nb, int i0, int j0) {
+    const int lane = lane_id(), g = lane / 16, l16 = lane % 16;
+    bch_d4 acc[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[p][q] = bch_d4{0.0, 0.0, 0.0, 0.0};
+    // lane group g covers k in [8 g, 8 g + 8): 8 products of 4 k each, in
+    // two halves (fewer operands live at once)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        double av[2][4], bv[2][4];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int ri = i0 + 16 * p + l16, rj = j0 + 16 * p + l16;
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) {
+                const int k = 8 * g + 4 * h + s2;
+                av[p][s2] = (ri < n && k < nb) ? M[(size_t)ri * n + kb + k] : 0.0;
+                bv[p][s2] = (rj < n && k < nb) ? M[(size_t)rj * n + kb + k] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) acc[p][q] = mfma_f64_16x16x4(av[p][s2], bv[q][s2], acc[p][q]);
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = i0 + 16 * p + 4 * e + g, j = j0 + 16 * q + l16;
+                if (i < n && j <= i) M[(size_t)i * n + j] -= acc[p][q][e];
+            }
+}
+
+// Back substitution L^T x = y by one workgroup, blocks from the bottom; b
+// (LDS, n) holds y on entry and x on return.
+__device__ __forceinline__ void bch_back(int n, const double* M, double* b) {
     const int tid = threadIdx.x, lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    const int nw = blockDim.x / WAVE;
-    if (tid == 0) s_bad = 0;
-    __syncthreads();
-    for (int kb = 0; kb < n; kb += BCH_NB) {
-        const int nb = min(BCH_NB, n - kb);
-        // ---- 1. diagonal block (wave 0)
-        if (w == 0) {
-            // lane r < nb: row r of the block; lane BCH_NB: the right-hand side
-            const bool is_row = lane < nb;
-            const bool is_rhs = lane == BCH_NB;
-            double a[BCH_NB];
-#pragma unroll
-            for (int c = 0; c < BCH_NB; ++c) {
-                double v = 0.0;
-                if (is_row && c <= lane) v = M[(size_t)(kb + lane) * n + kb + c];
-                if (is_rhs && c < nb) v = b[kb + c];
-                a[c] = v;
-            }
-            bool bad = false;
-            double dv = 0.0;
-#pragma unroll
-            for (int j = 0; j < BCH_NB; ++j) {
-                if (j < nb) {
-                    const double piv = readlane_f64(a[j], j);
-                    bad = bad || !(piv > 0.0);
-                    const double inv = rsqrt_f64(piv > 0.0 ? piv : 1.0);
-                    // column j of L: lanes below the pivot scale, the pivot
-                    // lane takes sqrt(piv); the rhs lane gets y_j
-                    a[j] = (lane == j) ? piv * inv : a[j] * inv;
-                    if (lane == j) dv = inv;
-                    // broadcast column j through LDS: lrow(r, j) = L(r, j),
-                    // read back by every lane of the wave
-                    if (is_row) lrow[lane * BCH_LD + j] = a[j];
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-                    for (int c = j + 1; c < BCH_NB; ++c) {
-                        if (c < nb) {
-                            const double lcj = lrow[c * BCH_LD + j];
-                            a[c] = fma(-a[j], lcj, a[c]);
-                        }
-                    }
-                }
-            }
-            // L_D in LDS (rows, lower part; zero above), 1 / pivots; y to b
-            if (is_row) {
-#pragma unroll
-                for (int c = 0; c < BCH_NB; ++c) lrow[lane * BCH_LD + c] = (c <= lane) ? a[c] : 0.0;
-                dinv[lane] = dv;
-#pragma unroll
-                for (int c = 0; c < BCH_NB; ++c)
-                    if (c <= lane) M[(size_t)(kb + lane) * n + kb + c] = a[c];
-            }
-            if (is_rhs) {
-#pragma unroll
-                for (int c = 0; c < BCH_NB; ++c)
-                    if (c < nb) b[kb + c] = a[c];
-            }
-            if (bad && lane == 0) s_bad = 1;
-        }
-        __syncthreads();
-        if (s_bad) return -1;
-        // ---- 2. panel rows below the block and their share of L y = b
-        for (int i = kb + nb + tid; i < n; i += blockDim.x) {
-            double x[BCH_NB];
-            double* row = M + (size_t)i * n + kb;
-#pragma unroll
-            for (int c = 0; c < BCH_NB; ++c) x[c] = c < nb ? row[c] : 0.0;
-#pragma unroll
-            for (int j = 0; j < BCH_NB; ++j) {
-                if (j < nb) {
-                    double sacc = x[j];
-#pragma unroll
-                    for (int c = 0; c < j; ++c) sacc = fma(-x[c], lrow[j * BCH_LD + c], sacc);
-                    x[j] = sacc * dinv[j];
-                }
-            }
-            double by = 0.0;
-#pragma unroll
-            for (int c = 0; c < BCH_NB; ++c) {
-                if (c < nb) {
-                    row[c] = x[c];
-                    by = fma(x[c], b[kb + c], by);
-                }
-            }
-            b[i] -= by;
-        }
-        __syncthreads();
-        // ---- 3. trailing update, 32 x 32 tiles of the lower triangle
-        const int t0 = kb + nb;
-        if (t0 < n) {
-            const int T = (n - t0 + 31) / 32;
-            const int ntiles = T * (T + 1) / 2;
-            const int g = lane / 16, l16 = lane % 16;
-            for (int t = w; t < ntiles; t += nw) {
-                // tile (TI, TJ), TJ <= TI, from the linear index
-                int TI = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-                while (TI * (TI + 1) / 2 > t) --TI;
-                while ((TI + 1) * (TI + 2) / 2 <= t) ++TI;
-                const int TJ = t - TI * (TI + 1) / 2;
-                const int i0 = t0 + 32 * TI, j0 = t0 + 32 * TJ;
-                bch_d4 acc[2][2];
-#pragma unroll
-                for (int p = 0; p < 2; ++p)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) acc[p][q] = bch_d4{0.0, 0.0, 0.0, 0.0};
-                // lane group g covers k in [8 g, 8 g + 8): 8 products of 4 k each
-                double av[2][8], bv[2][8];
-#pragma unroll
-                for (int p = 0; p < 2; ++p) {
-                    const int ri = i0 + 16 * p + l16, rj = j0 + 16 * p + l16;
-#pragma unroll
-                    for (int s2 = 0; s2 < 8; ++s2) {
-                        const int k = 8 * g + s2;
-                        av[p][s2] = (ri < n && k < nb) ? M[(size_t)ri * n + kb + k] : 0.0;
-                        bv[p][s2] = (rj < n && k < nb) ? M[(size_t)rj * n + kb + k] : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-                    for (int p = 0; p < 2; ++p)
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) acc[p][q] = mfma_f64_16x16x4(av[p][s2], bv[q][s2], acc[p][q]);
-#pragma unroll
-                for (int p = 0; p < 2; ++p)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int i = i0 + 16 * p + 4 * e + g, j = j0 + 16 * q + l16;
-                            if (i < n && j <= i) M[(size_t)i * n + j] -= acc[p][q][e];
-                        }
-            }
-        }
-        __syncthreads();
-    }
-    // ---- back substitution L^T x = y, blocks from the bottom
     const int nblk = (n + BCH_NB - 1) / BCH_NB;
     for (int bk = nblk - 1; bk >= 0; --bk) {
         const int kb = bk * BCH_NB, nb = min(BCH_NB, n - kb);
@@ -1139,7 +1162,199 @@ __device__ __forceinline__ int chol_solve_blocked(int n, double* M, double* b, d
         }
         __syncthreads();
     }
+}
+
+// One workgroup of 16 waves: M (global, n x n) factored in place, b (LDS, n)
+// holds the solution on return.  lw: bch_lds_doubles() of LDS.  Returns -1 if
+// a pivot is not positive.
+__device__ __forceinline__ int chol_solve_blocked(int n, double* M, double* b, double* lw) {
+    __shared__ int s_bad;
+    double* lrow = lw;                      // L_D row-major, BCH_NB x BCH_LD
+    double* dinv = lw + BCH_NB * BCH_LD;    // 1 / L_D(j, j)
+    const int tid = threadIdx.x, lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int nw = blockDim.x / WAVE;
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    for (int kb = 0; kb < n; kb += BCH_NB) {
+        const int nb = min(BCH_NB, n - kb);
+        // ---- 1. diagonal block (wave 0); L_D to M, y_D to b
+        if (w == 0) {
+            double a[BCH_NB];
+            const bool bad = bch_diag(n, kb, nb, M, b + kb, lrow, dinv, a);
+            if (lane < nb) {
+#pragma unroll
+                for (int c = 0; c < BCH_NB; ++c)
+                    if (c <= lane) M[(size_t)(kb + lane) * n + kb + c] = a[c];
+            }
+            if (lane == BCH_NB) {
+#pragma unroll
+                for (int c = 0; c < BCH_NB; ++c)
+                    if (c < nb) b[kb + c] = a[c];
+            }
+            if (bad && lane == 0) s_bad = 1;
+        }
+        __syncthreads();
+        if (s_bad) return -1;
+        // ---- 2. panel rows below the block and their share of L y = b
+        for (int i = kb + nb + tid; i < n; i += blockDim.x) b[i] -= bch_row(M + (size_t)i * n + kb, nb, lrow, dinv, b + kb);
+        __syncthreads();
+        // ---- 3. trailing update, 32 x 32 tiles of the lower triangle
+        const int t0 = kb + nb;
+        if (t0 < n) {
+            const int T = (n - t0 + 31) / 32;
+            const int ntiles = T * (T + 1) / 2;
+            for (int t = w; t < ntiles; t += nw) {
+                int TI, TJ;
+                bch_tile_of(t, TI, TJ);
+                bch_tile(n, M, kb, nb, t0 + 32 * TI, t0 + 32 * TJ);
+            }
+        }
+        __syncthreads();
+    }
+    bch_back(n, M, b);
     return 0;
+}
+
+// ---------------------------------------------------------------------------
+// The same factorization across many workgroups: one launch per phase, so
+// that the launches themselves order the phases (no grid-wide barrier):
+//   panel kb  one-wave workgroups, one row below the block per lane; every
+//             workgroup factors the diagonal block itself (the same
+//             arithmetic on the same data, so the same L_D and y_D in each)
+//             and subtracts its rows' shares of the forward substitution
+//             from b; workgroup 0 keeps L_D and y_D aside (the diagonal block
+//             of M is still being read by the others);
+//   update kb four tiles of the trailing lower triangle per workgroup, one
+//             per wave; workgroup 0 also stores L_D into the diagonal block;
+//   back      one workgroup: L^T x = y.
+// With `gate`, every launch does nothing unless *gate holds PM_SOLVE (the
+// solver state's mode); a pivot that is not positive sets *bad to 1, after
+// which the launches do nothing.
+// ---------------------------------------------------------------------------
+struct MChol {
+    int n;
+    double* M;           // n x n, row-major; lower triangle overwritten by L
+    double* b;           // right-hand side, reduced by the panels' forward updates
+    double* y;           // L y = b, block by block
+    double* x;           // solution (may alias b or y)
+    double* ld;          // BCH_NB x BCH_NB: L_D of the current panel
+    double* bad;         // 0 / 1, cleared by the caller
+    const double* gate;  // nullable
+};
+
+__device__ __forceinline__ bool mchol_live(const MChol& a) {
+    return (!a.gate || (int)*a.gate == PM_SOLVE) && *a.bad == 0.0;
+}
+
+constexpr int MCHOL_UPDATE_WAVES = 4;
+
+__global__ __launch_bounds__(WAVE) void mchol_panel_kernel(MChol a, int kb) {
+    __shared__ double lw[bch_lds_doubles() + BCH_NB];
+    if (!mchol_live(a)) return;
+    double* lrow = lw;
+    double* dinv = lw + BCH_NB * BCH_LD;
+    double* yd = dinv + BCH_NB;
+    const int n = a.n, nb = min(BCH_NB, n - kb), lane = threadIdx.x;
+    double r[BCH_NB];
+    const bool bad = bch_diag(n, kb, nb, a.M, a.b + kb, lrow, dinv, r);
+    if (bad) {
+        if (blockIdx.x == 0 && lane == 0) *a.bad = 1.0;
+        return;
+    }
+    if (lane == BCH_NB) {
+#pragma unroll
+        for (int c = 0; c < BCH_NB; ++c) yd[c] = r[c];
+    }
+    if (blockIdx.x == 0) {
+        if (lane < BCH_NB) {
+#pragma unroll
+            for (int c = 0; c < BCH_NB; ++c) a.ld[lane * BCH_NB + c] = r[c];
+        }
+        if (lane == BCH_NB) {
+#pragma unroll
+            for (int c = 0; c < BCH_NB; ++c)
+                if (c < nb) a.y[kb + c] = r[c];
+        }
+    }
+    __syncthreads();
+    const int i = kb + nb + blockIdx.x * WAVE + lane;
+    if (i < n) a.b[i] -= bch_row(a.M + (size_t)i * n + kb, nb, lrow, dinv, yd);
+}
+
+__global__ __launch_bounds__(WAVE * MCHOL_UPDATE_WAVES) void mchol_update_kernel(MChol a, int kb) {
+    if (!mchol_live(a)) return;
+    const int n = a.n, nb = min(BCH_NB, n - kb);
+    if (blockIdx.x == 0) {
+        for (int e = threadIdx.x; e < BCH_NB * BCH_NB; e += blockDim.x) {
+            const int r = e / BCH_NB, c = e % BCH_NB;
+            if (r < nb && c <= r) a.M[(size_t)(kb + r) * n + kb + c] = a.ld[e];
+        }
+    }
+    const int t0 = kb + nb;
+    if (t0 >= n) return;
+    const int T = (n - t0 + 31) / 32;
+    const int t = blockIdx.x * MCHOL_UPDATE_WAVES + (int)__builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    if (t >= T * (T + 1) / 2) return;
+    int TI, TJ;
+    bch_tile_of(t, TI, TJ);
+    bch_tile(n, a.M, kb, nb, t0 + 32 * TI, t0 + 32 * TJ);
+}
+
+// back substitution of the multi-workgroup factorization: x from y, by one
+// workgroup (n doubles of dynamic LDS)
+__device__ __forceinline__ void mchol_back(const MChol& a, double* bl) {
+    const int n = a.n;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) bl[k] = a.y[k];
+    __syncthreads();
+    bch_back(n, a.M, bl);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) a.x[k] = bl[k];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void mchol_back_kernel(MChol a, int* info) {
+    extern __shared__ __align__(16) double sm[];
+    const bool live = mchol_live(a);
+    if (live) mchol_back(a, sm);
+    if (threadIdx.x == 0 && info) *info = live ? 0 : -1;
+}
+
+// the panel and update launches of one factorization
+hipError_t launch_mchol_factor(const MChol& a, hipStream_t s) {
+    const int n = a.n;
+    for (int kb = 0; kb < n; kb += BCH_NB) {
+        const int nb = std::min(BCH_NB, n - kb);
+        const int rows = n - kb - nb;
+        hipLaunchKernelGGL(mchol_panel_kernel, dim3(std::max(1, (rows + WAVE - 1) / WAVE)), dim3(WAVE), 0, s, a, kb);
+        const int T = (rows + 31) / 32;
+        const int tiles = T * (T + 1) / 2;
+        hipLaunchKernelGGL(mchol_update_kernel,
+                           dim3(std::max(1, (tiles + MCHOL_UPDATE_WAVES - 1) / MCHOL_UPDATE_WAVES)),
+                           dim3(WAVE * MCHOL_UPDATE_WAVES), 0, s, a, kb);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_solve_mwg(int n, double* A, double* b, double* yw, double* ldw, double* badw, int* info,
+                                 hipStream_t s) {
+    MChol a;
+    a.n = n;
+    a.M = A;
+    a.b = b;
+    a.y = yw;
+    a.x = b;
+    a.ld = ldw;
+    a.bad = badw;
+    a.gate = nullptr;
+    hipError_t e = hipMemsetAsync(badw, 0, sizeof(double), s);
+    if (e != hipSuccess) return e;
+    e = launch_mchol_factor(a, s);
+    if (e != hipSuccess) return e;
+    const size_t lds = sizeof(double) * (size_t)n;
+    e = ensure_dynamic_lds((const void*)mchol_back_kernel, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mchol_back_kernel, dim3(1), dim3(1024), lds, s, a, info);
+    return hipGetLastError();
 }
 
 constexpr int CHOL_LDS_MAX_N = 140;  // 140 x 141 doubles + vectors < 160 KiB
@@ -1150,6 +1365,21 @@ constexpr int CTRL_SHIFT_TRIES = 8;       // raises of the diagonal before an in
 // systems above what registers and LDS hold take the blocked factorization
 __host__ __device__ inline bool newton_large(int n1) {
     return !(n1 >= 1 && n1 <= RCH_MAX_N) && n1 > CTRL_CHOL_LDS_MAX_N;
+}
+// Factorizations of the small systems (n1 <= CTRL_CHOL_LDS_MAX_N): LDL^T in
+// registers, Cholesky in LDS, or the blocked factorization on a copy in LDS
+enum : int { NSMALL_REGS = 1, NSMALL_LDS = 2, NSMALL_BLOCKED = 3 };
+constexpr int NSMALL_BLOCKED_MAX_N = 132;  // CTRL_THREADS + n^2 + blocked scratch doubles < 160 KiB
+__host__ __device__ inline int newton_small_kind(int n1, int force) {
+    if (force == NSMALL_BLOCKED && n1 <= NSMALL_BLOCKED_MAX_N) return NSMALL_BLOCKED;
+    if (force == NSMALL_LDS && n1 <= CTRL_CHOL_LDS_MAX_N) return NSMALL_LDS;
+    return (n1 >= 1 && n1 <= RCH_MAX_N) ? NSMALL_REGS : NSMALL_LDS;
+}
+// kernel instances of the one-workgroup Newton step
+enum : int { NK_SMALL = 0, NK_SBLOCK = 1, NK_LARGE = 2 };
+__host__ __device__ inline int newton_kind(int n1, int force) {
+    if (newton_large(n1)) return NK_LARGE;
+    return newton_small_kind(n1, force) == NSMALL_BLOCKED ? NK_SBLOCK : NK_SMALL;
 }
 // LDS scratch of the control step: two n1-vectors and the wave sums of a
 // block reduction after them, and at least one double per thread
@@ -1867,37 +2097,14 @@ hipError_t launch_cg_finish(double* state, StateLayout sl, int* flag, hipStream_
 // LARGE: the instance of the blocked factorization (n > CTRL_CHOL_LDS_MAX_N);
 // otherwise the register and LDS factorizations.  Separate instances keep the
 // register-resident factorization free of the blocked one's register needs.
-template <bool LARGE>
-__device__ __forceinline__ void newton_body(double* st, StateLayout sl) {
-    extern __shared__ __align__(16) double sm[];
-    if ((int)st[S_MODE] != PM_SOLVE) return;
-    if (LARGE != newton_large(sl.n1)) return;
-    double* scratch = sm;                            // ctrl_scratch_doubles(n1)
-    double* lmat = sm + ctrl_scratch_doubles(sl.n1);  // Cholesky matrix when it fits
+// Breakdown guard, before a factorization attempt: the raise mu of this
+// attempt (0 on the first), with the lower triangle of H restored from the
+// untouched upper one and the diagonal raised when the factorization is in
+// place (`large`; the diagonal of the assembled H kept in hdiag before the
+// first attempt), or the diagonal raised by the change of mu otherwise.
+__device__ __forceinline__ double newton_shift(double* st, StateLayout sl, bool large, double* scratch) {
     const int n1 = sl.n1;
-    const double tau = st[S_TAU];
-    const double eps = st[S_EPS];
-    const double sgm = st[S_SIGMA];
-    double* dir = st + sl.dir;
-    double* gb = st + sl.gb;
     double* H = st + sl.H;
-    // Newton direction: H dir = -g, H assembled by the contraction.  H is
-    // positive definite through its (tau/sigma) I term in exact arithmetic
-    // (Section 4); rounding in its assembly can still produce a pivot that is
-    // not positive.  Breakdown guard: the diagonal is raised by
-    // mu = max(tau/sigma, 4 eps mean_k H_kk), then 16 mu, 256 mu, ... (at
-    // most CTRL_SHIFT_TRIES raises) and the system solved again -- a shifted
-    // system still gives a descent direction for the line search; if no shift
-    // succeeds, the inner solve ends at the current iterate.
-    // One attempt per launch: when a pivot is not positive, the step ends
-    // with the mode still PM_SOLVE, the next step's pass, contraction and
-    // control step do nothing, and its Newton launch tries the next raise
-    // (a loop here would keep the register-resident factorization's state
-    // live across attempts and spill).
-    constexpr bool large = LARGE;
-    // the large path factorizes H in place (lower triangle); the diagonal of
-    // the assembled H is kept in the state's spare vector (the accelerated
-    // gradient method's previous iterate, unused while Newton steps run)
     double* hdiag = st + sl.tmp;
     const int attempt = (int)st[S_SHIFT_TRY];
     if (large && attempt == 0) {
@@ -1909,15 +2116,13 @@ __device__ __forceinline__ void newton_body(double* st, StateLayout sl) {
         if (attempt == 1) {
             double ptr = 0.0;
             for (int k = threadIdx.x; k < n1; k += blockDim.x) ptr += large ? hdiag[k] : H[(size_t)k * n1 + k];
-            const double tr = block_sum(ptr, scratch + 2 * n1);
-            if (threadIdx.x == 0) st[S_SHIFT_MU0] = fmax(tau / sgm, 4.0 * eps * fabs(tr) / n1);
+            const double tr = block_sum(ptr, scratch);
+            if (threadIdx.x == 0) st[S_SHIFT_MU0] = fmax(st[S_TAU] / st[S_SIGMA], 4.0 * st[S_EPS] * fabs(tr) / n1);
             __syncthreads();
         }
         const double mu_prev = st[S_SHIFT_MU];
         mu = st[S_SHIFT_MU0] * (double)(1u << (4 * (attempt - 1)));
         if (large) {
-            // restore the lower triangle from the untouched upper one, and the
-            // diagonal (kept before the first attempt) raised by mu
             for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) {
                 const int i = e / n1, j = e % n1;
                 if (i > j) H[e] = H[(size_t)j * n1 + i];
@@ -1928,6 +2133,82 @@ __device__ __forceinline__ void newton_body(double* st, StateLayout sl) {
         }
         __syncthreads();
     }
+    return mu;
+}
+
+// After a factorization attempt: on failure (rc != 0) the next step's Newton
+// launch tries the next raise, or, after the last, the inner solve ends at
+// its iterate; on success dir holds the direction and the line search
+// starts.
+__device__ __forceinline__ void newton_finish(double* st, StateLayout sl, int rc, double mu, double* scratch) {
+    const int n1 = sl.n1;
+    if (rc != 0) {
+        if (threadIdx.x == 0) {
+            const int attempt = (int)st[S_SHIFT_TRY];
+            if (attempt < CTRL_SHIFT_TRIES) {
+                st[S_SHIFT_TRY] = (double)(attempt + 1);
+                st[S_SHIFT_MU] = mu;
+            } else {
+                // no raise helped: end the inner solve here (multiplier update next)
+                st[S_NBREAK] += 1.0;
+                st[S_MODE] = (double)PM_MULT;
+                st[S_HAVE_DIR] = 0.0;
+                st[S_FLOOR] = 0.0;
+                st[S_SHIFT_TRY] = 0.0;
+                st[S_SHIFT_MU] = 0.0;
+            }
+        }
+        return;
+    }
+    const double* dir = st + sl.dir;
+    const double* gb = st + sl.gb;
+    double pgd = 0.0;
+    for (int k = threadIdx.x; k < n1; k += blockDim.x) pgd += gb[k] * dir[k];
+    const double gd = block_sum(pgd, scratch);
+    if (threadIdx.x == 0) {
+        st[S_SHIFT_TRY] = 0.0;
+        st[S_SHIFT_MU] = 0.0;
+        if (mu > 0.0) st[S_NSHIFT] += 1.0;
+        st[S_GD] = gd;
+        st[S_HAVE_DIR] = 1.0;
+        st[S_LSH] = 0.0;
+        st[S_MODE] = (double)PM_EVAL;
+    }
+}
+
+// NK: the instance (newton_kind): the register and LDS factorizations, the
+// blocked factorization on a copy in LDS, or the one-workgroup blocked
+// factorization in global memory (n > CTRL_CHOL_LDS_MAX_N).  Separate
+// instances keep the register-resident factorization free of the blocked
+// one's register needs.
+//
+// Newton direction: H dir = -g, H assembled by the contraction.  H is
+// positive definite through its (tau/sigma) I term in exact arithmetic
+// (Section 4); rounding in its assembly can still produce a pivot that is not
+// positive.  Breakdown guard: the diagonal is raised by
+// mu = max(tau/sigma, 4 eps mean_k H_kk), then 16 mu, 256 mu, ... (at most
+// CTRL_SHIFT_TRIES raises) and the system solved again -- a shifted system
+// still gives a descent direction for the line search; if no shift succeeds,
+// the inner solve ends at the current iterate.  One attempt per launch: when a
+// pivot is not positive, the step ends with the mode still PM_SOLVE, the next
+// step's pass, contraction and control step do nothing, and its Newton launch
+// tries the next raise (a loop here would keep the register-resident
+// factorization's state live across attempts and spill).
+template <int NK>
+__device__ __forceinline__ void newton_body(double* st, StateLayout sl, int force) {
+    extern __shared__ __align__(16) double sm[];
+    if ((int)st[S_MODE] != PM_SOLVE) return;
+    if (newton_kind(sl.n1, force) != NK) return;
+    constexpr bool LARGE = NK == NK_LARGE;
+    double* scratch = sm;                            // ctrl_scratch_doubles(n1)
+    double* lmat = sm + ctrl_scratch_doubles(sl.n1);  // Cholesky matrix when it fits
+    const int n1 = sl.n1;
+    const int kind = LARGE ? 0 : newton_small_kind(n1, force);
+    double* dir = st + sl.dir;
+    const double* gb = st + sl.gb;
+    double* H = st + sl.H;
+    // the large path factorizes H in place (lower triangle)
+    const double mu = newton_shift(st, sl, LARGE, scratch + 2 * n1);
     int rc = 0;
     if constexpr (LARGE) {
         // blocked factorization in place (global memory), rhs in LDS
@@ -1937,7 +2218,17 @@ __device__ __forceinline__ void newton_body(double* st, StateLayout sl) {
         rc = chol_solve_blocked(n1, H, bv, lmat);
         for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
         __syncthreads();
-    } else if (rch_fits(n1, blockDim.x)) {
+    } else if (NK == NK_SBLOCK) {
+        // the blocked factorization on a copy of H in LDS (row stride n1)
+        double* bv = scratch;
+        double* lw = lmat + (size_t)n1 * n1;
+        for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) lmat[e] = H[e];
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
+        __syncthreads();
+        rc = chol_solve_blocked(n1, lmat, bv, lw);
+        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
+        __syncthreads();
+    } else if (kind == NSMALL_REGS) {
         double* bv = scratch;
         for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
         __syncthreads();
@@ -1956,45 +2247,54 @@ __device__ __forceinline__ void newton_body(double* st, StateLayout sl) {
         for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
         __syncthreads();
     }
-    if (rc != 0) {
-        if (threadIdx.x == 0) {
-            if (attempt < CTRL_SHIFT_TRIES) {
-                // the next step's Newton launch tries a larger raise
-                st[S_SHIFT_TRY] = (double)(attempt + 1);
-                st[S_SHIFT_MU] = mu;
-            } else {
-                // no raise helped: end the inner solve here (multiplier update next)
-                st[S_NBREAK] += 1.0;
-                st[S_MODE] = (double)PM_MULT;
-                st[S_HAVE_DIR] = 0.0;
-                st[S_FLOOR] = 0.0;
-                st[S_SHIFT_TRY] = 0.0;
-                st[S_SHIFT_MU] = 0.0;
-            }
-        }
-        return;
+    newton_finish(st, sl, rc, mu, scratch);
+}
+
+// The Newton step with the multi-workgroup factorization (systems of at
+// least MCHOL_MIN_N unknowns, single-instance runs): newton_pre_kernel
+// (breakdown guard, b = -g in dir, the failure flag cleared), the panel and
+// update launches (gated on the mode), then newton_post_kernel (back
+// substitution into dir and the bookkeeping of newton_finish).
+__host__ __device__ inline MChol newton_mchol(double* st, StateLayout sl) {
+    MChol a;
+    a.n = sl.n1;
+    a.M = st + sl.H;
+    a.b = st + sl.dir;
+    a.y = st + sl.yv;
+    a.x = st + sl.dir;
+    a.ld = st + sl.ldiag;
+    a.bad = st + S_CHOL_BAD;
+    a.gate = st + S_MODE;
+    return a;
+}
+
+__global__ __launch_bounds__(CTRL_THREADS) void newton_pre_kernel(double* st, StateLayout sl) {
+    extern __shared__ __align__(16) double sm[];
+    if ((int)st[S_MODE] != PM_SOLVE) return;
+    newton_shift(st, sl, true, sm);
+    const int n1 = sl.n1;
+    for (int k = threadIdx.x; k < n1; k += blockDim.x) st[sl.dir + k] = -st[sl.gb + k];
+    if (threadIdx.x == 0) st[S_CHOL_BAD] = 0.0;
+}
+
+__global__ __launch_bounds__(CTRL_THREADS) void newton_post_kernel(double* st, StateLayout sl, int* flag) {
+    extern __shared__ __align__(16) double sm[];
+    if ((int)st[S_MODE] == PM_SOLVE) {
+        const MChol a = newton_mchol(st, sl);
+        const int rc = st[S_CHOL_BAD] != 0.0 ? -1 : 0;
+        if (rc == 0) mchol_back(a, sm);
+        const int attempt = (int)st[S_SHIFT_TRY];
+        const double mu = attempt > 0 ? st[S_SHIFT_MU0] * (double)(1u << (4 * (attempt - 1))) : 0.0;
+        newton_finish(st, sl, rc, mu, sm + sl.n1);
     }
-    if (threadIdx.x == 0) {
-        st[S_SHIFT_TRY] = 0.0;
-        st[S_SHIFT_MU] = 0.0;
-    }
-    if (threadIdx.x == 0 && mu > 0.0) st[S_NSHIFT] += 1.0;
-    double pgd = 0.0;
-    for (int k = threadIdx.x; k < n1; k += blockDim.x) pgd += gb[k] * dir[k];
-    const double gd = block_sum(pgd, scratch);
-    if (threadIdx.x == 0) {
-        st[S_GD] = gd;
-        st[S_HAVE_DIR] = 1.0;
-        st[S_LSH] = 0.0;
-        st[S_MODE] = (double)PM_EVAL;
-    }
+    if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
 }
 
 // `flag` (nullable, typically host-mapped) receives the state's mode after
 // the step.
-template <bool LARGE>
-__global__ __launch_bounds__(CTRL_THREADS) void newton_kernel(double* st, StateLayout sl, int* flag) {
-    newton_body<LARGE>(st, sl);
+template <int NK>
+__global__ __launch_bounds__(CTRL_THREADS) void newton_kernel(double* st, StateLayout sl, int* flag, int force) {
+    newton_body<NK>(st, sl, force);
     if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
 }
 
@@ -2008,27 +2308,57 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
 
 size_t control_lds_bytes(int n1) { return sizeof(double) * (size_t)ctrl_scratch_doubles(n1); }
 
+// tuning override of the small systems' factorization (MEB_NEWTON_SMALL =
+// regs, lds or blocked; otherwise chosen by size)
+int newton_small_force() {
+    static const int v = [] {
+        const char* e = getenv("MEB_NEWTON_SMALL");
+        if (!e) return 0;
+        if (!strcmp(e, "regs")) return (int)NSMALL_REGS;
+        if (!strcmp(e, "lds")) return (int)NSMALL_LDS;
+        if (!strcmp(e, "blocked")) return (int)NSMALL_BLOCKED;
+        return 0;
+    }();
+    return v;
+}
+
 size_t newton_lds_bytes(int n1) {
     size_t lds = sizeof(double) * (size_t)ctrl_scratch_doubles(n1);
-    if (rch_fits(n1, CTRL_THREADS))
-        lds += sizeof(double) * rch_lds_doubles(n1);
-    else if (n1 <= CTRL_CHOL_LDS_MAX_N)
-        lds += sizeof(double) * (size_t)n1 * chol_ld(n1);
-    else
-        lds += sizeof(double) * (size_t)bch_lds_doubles();
-    return lds;
+    if (newton_large(n1)) return lds + sizeof(double) * (size_t)bch_lds_doubles();
+    switch (newton_small_kind(n1, newton_small_force())) {
+        case NSMALL_REGS: return lds + sizeof(double) * rch_lds_doubles(n1);
+        case NSMALL_BLOCKED: return lds + sizeof(double) * ((size_t)n1 * n1 + bch_lds_doubles());
+        default: return lds + sizeof(double) * (size_t)n1 * chol_ld(n1);
+    }
 }
 
 hipError_t launch_newton(double* state, StateLayout sl, int* flag, hipStream_t s) {
+    if (sl.n1 >= MCHOL_MIN_N) {
+        // LDS: the back substitution's vector, then block-sum scratch
+        const size_t lds = sizeof(double) * ((size_t)sl.n1 + CTRL_THREADS);
+        hipError_t ea = ensure_dynamic_lds((const void*)newton_post_kernel, lds);
+        if (ea != hipSuccess) return ea;
+        hipLaunchKernelGGL(newton_pre_kernel, dim3(1), dim3(CTRL_THREADS), sizeof(double) * CTRL_THREADS, s, state,
+                           sl);
+        ea = launch_mchol_factor(newton_mchol(state, sl), s);
+        if (ea != hipSuccess) return ea;
+        hipLaunchKernelGGL(newton_post_kernel, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag);
+        return hipGetLastError();
+    }
     const size_t lds = newton_lds_bytes(sl.n1);
-    const bool big = newton_large(sl.n1);
-    const void* fn = big ? (const void*)newton_kernel<true> : (const void*)newton_kernel<false>;
+    const int force = newton_small_force();
+    const int nk = newton_kind(sl.n1, force);
+    const void* fn = nk == NK_LARGE    ? (const void*)newton_kernel<NK_LARGE>
+                     : nk == NK_SBLOCK ? (const void*)newton_kernel<NK_SBLOCK>
+                                       : (const void*)newton_kernel<NK_SMALL>;
     hipError_t ea = ensure_dynamic_lds(fn, lds);
     if (ea != hipSuccess) return ea;
-    if (big)
-        hipLaunchKernelGGL(newton_kernel<true>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag);
+    if (nk == NK_LARGE)
+        hipLaunchKernelGGL(newton_kernel<NK_LARGE>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag, force);
+    else if (nk == NK_SBLOCK)
+        hipLaunchKernelGGL(newton_kernel<NK_SBLOCK>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag, force);
     else
-        hipLaunchKernelGGL(newton_kernel<false>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag);
+        hipLaunchKernelGGL(newton_kernel<NK_SMALL>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag, force);
     return hipGetLastError();
 }
 
@@ -2064,13 +2394,13 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_batch_kernel(const Batch
     control_body(st, it.pa.sl, it.pa.rl, it.pa.red);
 }
 
-template <bool LARGE>
-__global__ __launch_bounds__(CTRL_THREADS) void newton_batch_kernel(const BatchItem* tab, TickList L) {
+template <int NK>
+__global__ __launch_bounds__(CTRL_THREADS) void newton_batch_kernel(const BatchItem* tab, TickList L, int force) {
     const BatchItem& it = tab[L.slot[blockIdx.x]];
     double* st = const_cast<double*>(it.pa.state);
-    newton_body<LARGE>(st, it.pa.sl);
-    // the flag after the last kernel of the item's step
-    if (threadIdx.x == 0 && it.flag && (LARGE || !newton_large(it.pa.sl.n1))) *it.flag = (int)st[S_MODE];
+    newton_body<NK>(st, it.pa.sl, force);
+    // the flag after the item's own Newton instance
+    if (threadIdx.x == 0 && it.flag && newton_kind(it.pa.sl.n1, force) == NK) *it.flag = (int)st[S_MODE];
 }
 
 namespace {
@@ -2141,25 +2471,30 @@ hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* 
         hipLaunchKernelGGL(control_batch_kernel, dim3(cn), dim3(CTRL_THREADS), lds, s, dtab, L);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        // the Newton solves: the small systems' instance over every item, then
-        // the large systems' instance (items of the other kind return)
-        size_t nlds = 0;
-        bool any_large = false;
+        // the Newton solves: one launch per instance that some item needs
+        // (items of the other kinds return)
+        const int force = newton_small_force();
+        size_t nlds[3] = {0, 0, 0};
         for (int k = 0; k < cn; ++k) {
             const int n1 = htab[sl[k]].pa.sl.n1;
-            const size_t b = newton_lds_bytes(n1);
-            if (b > nlds) nlds = b;
-            any_large = any_large || newton_large(n1);
+            const int nk = newton_kind(n1, force);
+            nlds[nk] = std::max(nlds[nk], newton_lds_bytes(n1));
         }
-        const hipError_t eb = ensure_dynamic_lds((const void*)newton_batch_kernel<false>, nlds);
-        if (eb != hipSuccess) return eb;
-        hipLaunchKernelGGL(newton_batch_kernel<false>, dim3(cn), dim3(CTRL_THREADS), nlds, s, dtab, L);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        if (any_large) {
-            const hipError_t ec = ensure_dynamic_lds((const void*)newton_batch_kernel<true>, nlds);
-            if (ec != hipSuccess) return ec;
-            hipLaunchKernelGGL(newton_batch_kernel<true>, dim3(cn), dim3(CTRL_THREADS), nlds, s, dtab, L);
+        const void* fns[3] = {(const void*)newton_batch_kernel<NK_SMALL>, (const void*)newton_batch_kernel<NK_SBLOCK>,
+                              (const void*)newton_batch_kernel<NK_LARGE>};
+        for (int nk = 0; nk < 3; ++nk) {
+            if (nlds[nk] == 0) continue;
+            const hipError_t eb = ensure_dynamic_lds(fns[nk], nlds[nk]);
+            if (eb != hipSuccess) return eb;
+            if (nk == NK_SMALL)
+                hipLaunchKernelGGL(newton_batch_kernel<NK_SMALL>, dim3(cn), dim3(CTRL_THREADS), nlds[nk], s, dtab, L,
+                                   force);
+            else if (nk == NK_SBLOCK)
+                hipLaunchKernelGGL(newton_batch_kernel<NK_SBLOCK>, dim3(cn), dim3(CTRL_THREADS), nlds[nk], s, dtab,
+                                   L, force);
+            else
+                hipLaunchKernelGGL(newton_batch_kernel<NK_LARGE>, dim3(cn), dim3(CTRL_THREADS), nlds[nk], s, dtab, L,
+                                   force);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

@@ -96,6 +96,8 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     const int stages_generic = c.stages;
     c.spec = 1;
     int64_t max_waves = resident_waves();
+    c.fill_min = (int)(max_waves < mw_generic ? max_waves : mw_generic);
+    c.fill_max = (int)(max_waves < mw_generic ? mw_generic : max_waves);
     if (max_waves < mw_generic && steps > 8 * mw_generic) {
         c.spec = 0;
         c.stages = stages_generic;

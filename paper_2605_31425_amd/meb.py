@@ -26,7 +26,7 @@ _HESS = {"auto": 0, "f64": 1, "mfma_f64": 2, "mfma_f32": 3, "mfma_bf16": 4}
 WANT_PSI, WANT_GRAD, WANT_HESS, WANT_MULT, WANT_DMULT, WANT_KKT = 1, 2, 4, 8, 16, 32
 WANT_ALL = 63
 
-EXPORTS = ["meb_default_options", "meb_last_error", "meb_workspace_size", "meb_eval_workspace_size", "meb_solve",
+EXPORTS = ["meb_default_options", "meb_last_error", "meb_source_hash", "meb_workspace_size", "meb_eval_workspace_size", "meb_solve",
            "meb_al_eval", "meb_hess_vec", "meb_screen", "meb_check_feasible", "meb_check_feasible_noalloc",
            "meb_prepare_f32",
            "meb_chol_workspace_size",
@@ -99,6 +99,7 @@ def _load():
     L = ctypes.CDLL(LIB_PATH)
     L.meb_default_options.argtypes = [ctypes.POINTER(Options)]
     L.meb_last_error.restype = ctypes.c_char_p
+    L.meb_source_hash.restype = ctypes.c_char_p
     L.meb_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Options), _szp]
     L.meb_eval_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _szp]
     L.meb_solve.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Options), _vp,
@@ -135,6 +136,11 @@ def _load():
 
 
 lib = _load()
+
+
+def source_hash():
+    """The source hash compiled into the loaded libmeb.so."""
+    return lib.meb_source_hash().decode()
 
 
 def _check(rc):

@@ -54,3 +54,13 @@ def test_options_defaults_without_gpu():
     assert n.value > 1000 * 10 * 8
     assert meb.lib.meb_workspace_size(0, 10, 0, ctypes.byref(o), ctypes.byref(n)) < 0
     assert meb.lib.meb_last_error().decode() != ""
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmeb.so not built")
+def test_library_was_built_from_these_sources():
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2605_31425_amd import build
+    lib = ctypes.CDLL(LIB)
+    lib.meb_source_hash.restype = ctypes.c_char_p
+    assert lib.meb_source_hash().decode() == build.source_hash(), "libmeb.so is stale: rebuild it"

@@ -143,7 +143,8 @@ def test_prepare_f32_bit_exact(m, d):
     assert abs(L - rL) <= 1e-14 * rL
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 11, 63, 64, 65, 101, 127, 128, 141, 300])
+# n >= 320: the factorization across many workgroups (one launch per phase)
+@pytest.mark.parametrize("n", [1, 2, 3, 11, 63, 64, 65, 101, 127, 128, 141, 300, 320, 353, 1001, 1025])
 def test_chol_solve_parity(n):
     from paper_2605_31425_amd import meb
     rng = np.random.default_rng(n)
@@ -157,7 +158,7 @@ def test_chol_solve_parity(n):
         meb.chol_solve(dev(-np.eye(n)), dev(b))
 
 
-@pytest.mark.parametrize("n", [5, 64, 101, 127])
+@pytest.mark.parametrize("n", [5, 64, 101, 127, 400])
 def test_chol_solve_ill_conditioned_backward_error(n):
     # condition number 1e10, like the Hessians late in a run: compare the
     # backward error (residual), which a stable solve keeps near eps
@@ -172,7 +173,7 @@ def test_chol_solve_ill_conditioned_backward_error(n):
     assert res <= 64 * n * np.finfo(float).eps * np.abs(A).max() * np.abs(y).max()
 
 
-@pytest.mark.parametrize("n", [2, 40, 101, 127])
+@pytest.mark.parametrize("n", [2, 40, 101, 127, 333, 700])
 def test_chol_solve_detects_late_negative_pivot(n):
     # positive diagonal, one negative eigenvalue: the failure shows only in a
     # later pivot

@@ -197,3 +197,29 @@ def test_newton_cg_solver_matches_oracle(mode, seed, m, d):
     assert st["rc"] == 0, st
     assert sum(st["cg_iterations"]) > 0
     _check(C, R, r, c, st_ref["r_fixed"])
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("seed,m,d", [(54, 2000, 400), (55, 1500, 700)])
+def test_dense_newton_large_d_matches_oracle(mode, seed, m, d):
+    # Newton systems of d + 1 >= 320 unknowns: the Cholesky factorization
+    # across many workgroups, one launch per panel phase
+    from paper_2605_31425_amd import meb
+    print(f"dense newton {mode} m={m} d={d}", flush=True)
+    C, R, r_ref = _large_d_instance(seed, m, d)
+    r, c, st = meb.solve(dev(C), dev(R), mode=mode)
+    assert st["rc"] == 0, st
+    _check(C, R, r, c, r_ref)
+
+
+_large_d = {}
+
+
+def _large_d_instance(seed, m, d):
+    # the oracle's answer, computed once for both modes
+    if seed not in _large_d:
+        rng = np.random.default_rng(seed)
+        C = rng.normal(size=(m, d))
+        R = rng.uniform(0, 0.1, m)
+        _large_d[seed] = (C, R, oracle.ripalm(C, R, tol=1e-12)[2]["r_fixed"])
+    return _large_d[seed]
