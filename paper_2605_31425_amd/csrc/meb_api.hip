@@ -84,7 +84,7 @@ void Engine::reserve_subsets() {
     rec_cap = std::max<int64_t>(rec_cap, wmax);
     const int64_t steps = (m + bpw - 1) / bpw;
     const int64_t fmin = std::max(1, pc.fill_min);
-    const int64_t bw_max = (steps + fmin - 1) / fmin * bpw;
+    const int64_t bw_max = std::max<int64_t>((steps + fmin - 1) / fmin, pass_min_steps()) * bpw;
     list_cap = std::max<int64_t>(list_cap, m + (int64_t)WPB * bw_max);
     ks_cap = std::max(ks_cap, syrk_ksplit(m, d, (int)rec_cap));
 }

@@ -201,6 +201,10 @@ template <typename T, int VEC>
 __host__ __device__ constexpr int dma_loads() {
     return DMA_BLK / (WAVE * dma_width<T, VEC>());
 }
+// rows of four parts per lane are read two steps per round
+#ifndef PASS_ROUND2_NL4
+#define PASS_ROUND2_NL4 1
+#endif
 constexpr int DMA_MIN_STAGES = 4;  // blocks per ring: the layout's minimum
 // and maximum.  A wave's outstanding vector-memory operations are counted in
 // six bits (at most 63), and the waits above count every copy in flight:
@@ -1205,8 +1209,23 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                     ensure(end);
                     RowVec<T, VEC> c[NB][NLMAX];
                     T u[NB];
-                    static_assert(NB == 1 || NLMAX == 2, "rounds of several steps read two parts per row");
-                    if constexpr (NB == 4) {
+                    static_assert(NB == 1 || NLMAX == 2 || (NLMAX == 4 && NB == 2),
+                                  "rounds of several steps read eight parts at most");
+                    if constexpr (NB == 2 && NLMAX == 4) {
+                        uint32_t ra[8];
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) ra[4 * t + j] = row_addr(s + t, j);
+                        typename LdsWord<VEC * sizeof(T)>::type w[8];
+                        lds_read8<VEC * sizeof(T)>(ra, w);
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) __builtin_memcpy(&c[t][j], &w[4 * t + j], sizeof(c[t][j]));
+                        u[0] = U ? lds_load1<T>(u_addr_of(s)) : T(0);
+                        u[1] = U ? lds_load1<T>(u_addr_of(s + 1)) : T(0);
+                    } else if constexpr (NB == 4) {
                         uint32_t ra[8];
 #pragma unroll
                         for (int t = 0; t < 4; ++t) {
@@ -1259,6 +1278,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
                     if ((S & 3) == 0 && 4 * step_bytes <= (stages - 1) * DMA_BLK) {
                         for (; s + 4 <= s1; s += 4) round(s, std::integral_constant<int, 4>());
                     } else if ((S & 1) == 0 && 2 * step_bytes <= (stages - 1) * DMA_BLK) {
+                        for (; s + 2 <= s1; s += 2) round(s, std::integral_constant<int, 2>());
+                    }
+                } else if constexpr (NLMAX == 4 && PASS_ROUND2_NL4) {
+                    if ((S & 1) == 0 && 2 * step_bytes <= (stages - 1) * DMA_BLK) {
                         for (; s + 2 <= s1; s += 2) round(s, std::integral_constant<int, 2>());
                     }
                 }

@@ -222,6 +222,7 @@ struct PassConfig {
 };
 
 PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu);
+int pass_min_steps();
 
 // Arguments of the evaluation pass.
 struct PassArgs {

@@ -4,9 +4,6 @@
 // decision, relative stopping test, multiplier bookkeeping, FP64 Cholesky
 // solve), the screening and feasibility scans, the precision-preparation
 // and gather kernels, and the multi-instance step of the server.
-#include <stdlib.h>
-#include <string.h>
-
 #include <algorithm>
 
 #include "meb_device.h"
@@ -999,49 +996,55 @@ __device__ __forceinline__ bch_d4 mfma_f64_16x16x4(double a, double b, bch_d4 c)
 // diagonal), or y_D on the right-hand-side lane; L_D is also in lrow
 // (row-major, BCH_LD stride) and 1 / L_D(j, j) in dinv.  Returns true (on
 // every lane) if a pivot was not positive.
+template <bool ALLSTEPS>
 __device__ __forceinline__ bool bch_diag(int n, int kb, int nb, const double* M, const double* bsrc, double* lrow,
                                          double* dinv, double (&a)[BCH_NB]) {
     const int lane = lane_id();
     const bool is_row = lane < nb;
     const bool is_rhs = lane == BCH_NB;
+    // every lane loads from a valid address (its row, the right-hand side, or
+    // row 0 of the block) and keeps what it needs: loads under a condition
+    // would be issued one at a time
+    const double* src = is_rhs ? bsrc : M + (size_t)(kb + (is_row ? lane : 0)) * n + kb;
 #pragma unroll
     for (int c = 0; c < BCH_NB; ++c) {
-        double v = 0.0;
-        if (is_row && c <= lane) v = M[(size_t)(kb + lane) * n + kb + c];
-        if (is_rhs && c < nb) v = bsrc[c];
-        a[c] = v;
+        const double v = src[c < nb ? c : nb - 1];
+        a[c] = ((is_row & (c <= lane)) | (is_rhs & (c < nb))) ? v : 0.0;
     }
+    // ALLSTEPS: every step runs (no branch on nb), so that each step's LDS
+    // reads are issued together; a guarded read is issued and waited for on
+    // its own.  Steps j >= nb find a zero pivot on a lane that holds no row,
+    // count it as no failure and change nothing that is used: rows of lrow
+    // beyond nb stay zero, dinv beyond nb is one.  Without ALLSTEPS the steps
+    // and reads beyond nb are skipped (fewer registers where the factorization
+    // shares a kernel with other phases).
     bool bad = false;
     double dv = 0.0;
 #pragma unroll
     for (int j = 0; j < BCH_NB; ++j) {
-        if (j < nb) {
-            const double piv = readlane_f64(a[j], j);
-            bad = bad || !(piv > 0.0);
-            const double inv = rsqrt_f64(piv > 0.0 ? piv : 1.0);
-            // column j of L: lanes below the pivot scale, the pivot lane
-            // takes sqrt(piv); the rhs lane gets y_j
-            a[j] = (lane == j) ? piv * inv : a[j] * inv;
-            if (lane == j) dv = inv;
-            // broadcast column j through LDS: lrow(r, j) = L(r, j), read back
-            // by every lane of the wave
-            if (is_row) lrow[lane * BCH_LD + j] = a[j];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (!ALLSTEPS && j >= nb) continue;
+        const double piv = readlane_f64(a[j], j);
+        bad = bad || ((j < nb) & !(piv > 0.0));
+        const double inv = rsqrt_f64(piv > 0.0 ? piv : 1.0);
+        // column j of L: lanes below the pivot scale, the pivot lane takes
+        // sqrt(piv); the rhs lane gets y_j
+        a[j] = (lane == j) ? piv * inv : a[j] * inv;
+        if (lane == j) dv = inv;
+        // broadcast column j through LDS: lrow(r, j) = L(r, j), read back by
+        // every lane of the wave
+        if (lane < BCH_NB) lrow[lane * BCH_LD + j] = is_row ? a[j] : 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-            for (int c = j + 1; c < BCH_NB; ++c) {
-                if (c < nb) {
-                    const double lcj = lrow[c * BCH_LD + j];
-                    a[c] = fma(-a[j], lcj, a[c]);
-                }
-            }
+        for (int c = j + 1; c < BCH_NB; ++c) {
+            if (ALLSTEPS || c < nb) a[c] = fma(-a[j], lrow[c * BCH_LD + j], a[c]);
         }
     }
-    if (is_row) {
+    if (lane < BCH_NB) {
 #pragma unroll
         for (int c = 0; c < BCH_NB; ++c) {
-            if (c > lane) a[c] = 0.0;
+            if (!is_row || c > lane) a[c] = 0.0;
             lrow[lane * BCH_LD + c] = a[c];
         }
         dinv[lane] = dv;
@@ -1049,13 +1052,14 @@ __device__ __forceinline__ bool bch_diag(int n, int kb, int nb, const double* M,
     return bad;
 }
 
-// Step 2 for one row below the block: row[0, nb) <- x with x L_D^T = row;
-// returns the row's share sum_c x_c y_c of the forward substitution.
-__device__ __forceinline__ double bch_row(double* row, int nb, const double* lrow, const double* dinv,
-                                          const double* yd) {
-    double x[BCH_NB];
-#pragma unroll
-    for (int c = 0; c < BCH_NB; ++c) x[c] = c < nb ? row[c] : 0.0;
+// Step 2 for one row below the block, its entries already in x:
+// row[0, nb) <- x with x L_D^T = row; returns the row's share
+// sum_c x_c y_c of the forward substitution.
+__device__ __forceinline__ double bch_row_solve(double (&x)[BCH_NB], double* row, int nb, const double* lrow,
+                                                const double* dinv, const double* yd) {
+    // all BCH_NB columns (x_j = 0 for j >= nb: zero rows of L_D beyond nb);
+    // one batch of LDS reads per column (the scheduling barrier keeps the
+    // compiler from hoisting every column's reads at once, which would spill)
 #pragma unroll
     for (int j = 0; j < BCH_NB; ++j) {
         if (j < nb) {
@@ -1068,12 +1072,24 @@ __device__ __forceinline__ double bch_row(double* row, int nb, const double* lro
     double by = 0.0;
 #pragma unroll
     for (int c = 0; c < BCH_NB; ++c) {
-        if (c < nb) {
-            row[c] = x[c];
-            by = fma(x[c], yd[c], by);
-        }
+        const double yv = yd[c < nb ? c : nb - 1];
+        by = fma(x[c], c < nb ? yv : 0.0, by);
     }
+#pragma unroll
+    for (int c = 0; c < BCH_NB; ++c)
+        if (c < nb) row[c] = x[c];
     return by;
+}
+
+__device__ __forceinline__ double bch_row(double* row, int nb, const double* lrow, const double* dinv,
+                                          const double* yd) {
+    double x[BCH_NB];
+#pragma unroll
+    for (int c = 0; c < BCH_NB; ++c) {
+        const double v = row[c < nb ? c : nb - 1];
+        x[c] = c < nb ? v : 0.0;
+    }
+    return bch_row_solve(x, row, nb, lrow, dinv, yd);
 }
 
 // lower-triangle tile t of T x T tiles (row-major over TI >= TJ)
@@ -1101,11 +1117,15 @@ __device__ __forceinline__ void bch_tile(int n, double* M, int kb, int nb, int i
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             const int ri = i0 + 16 * p + l16, rj = j0 + 16 * p + l16;
+            const double* pa = M + (size_t)(ri < n ? ri : n - 1) * n + kb;
+            const double* pb = M + (size_t)(rj < n ? rj : n - 1) * n + kb;
 #pragma unroll
             for (int s2 = 0; s2 < 4; ++s2) {
                 const int k = 8 * g + 4 * h + s2;
-                av[p][s2] = (ri < n && k < nb) ? M[(size_t)ri * n + kb + k] : 0.0;
-                bv[p][s2] = (rj < n && k < nb) ? M[(size_t)rj * n + kb + k] : 0.0;
+                const int kc = k < nb ? k : nb - 1;
+                const double va = pa[kc], vb = pb[kc];
+                av[p][s2] = ((ri < n) & (k < nb)) ? va : 0.0;
+                bv[p][s2] = ((rj < n) & (k < nb)) ? vb : 0.0;
             }
         }
 #pragma unroll
@@ -1115,6 +1135,10 @@ __device__ __forceinline__ void bch_tile(int n, double* M, int kb, int nb, int i
 #pragma unroll
                 for (int q = 0; q < 2; ++q) acc[p][q] = mfma_f64_16x16x4(av[p][s2], bv[q][s2], acc[p][q]);
     }
+    // the tile's entries are loaded by every lane from a valid address and
+    // written back where they belong (a load under a per-lane condition
+    // would wait on its own)
+    double cv[2][2][4];
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -1122,7 +1146,16 @@ __device__ __forceinline__ void bch_tile(int n, double* M, int kb, int nb, int i
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int i = i0 + 16 * p + 4 * e + g, j = j0 + 16 * q + l16;
-                if (i < n && j <= i) M[(size_t)i * n + j] -= acc[p][q][e];
+                cv[p][q][e] = M[(size_t)(i < n ? i : n - 1) * n + (j < n ? j : n - 1)];
+            }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = i0 + 16 * p + 4 * e + g, j = j0 + 16 * q + l16;
+                if (i < n && j <= i) M[(size_t)i * n + j] = cv[p][q][e] - acc[p][q][e];
             }
 }
 
@@ -1138,14 +1171,24 @@ __device__ __forceinline__ void bch_back(int n, const double* M, double* b) {
             // lane r < nb holds column r of L_D (L(c, r), c >= r) and y_r
             double lc[BCH_NB];
 #pragma unroll
+            for (int c = 0; c < BCH_NB; ++c) {
+                const double v = M[(size_t)(kb + (c < nb ? c : nb - 1)) * n + kb + (lane < nb ? lane : nb - 1)];
+                lc[c] = ((lane < nb) & (c < nb) & (c >= lane)) ? v : 0.0;
+            }
+            double y = b[kb + (lane < nb ? lane : nb - 1)];
+            if (lane >= nb) y = 0.0;
+            // lane r's own diagonal L(r, r) is lc[r]: its reciprocal, formed
+            // by every lane at once, keeps the division off the chain
+            double dl = 1.0;
+#pragma unroll
             for (int c = 0; c < BCH_NB; ++c)
-                lc[c] = (lane < nb && c < nb && c >= lane) ? M[(size_t)(kb + c) * n + kb + lane] : 0.0;
-            double y = lane < nb ? b[kb + lane] : 0.0;
+                if (c == lane) dl = lc[c];
+            const double rd = 1.0 / dl;
             double xs = 0.0;
 #pragma unroll
             for (int j = BCH_NB - 1; j >= 0; --j) {
                 if (j < nb) {
-                    const double xj = readlane_f64(y, j) / readlane_f64(lc[j], j);
+                    const double xj = readlane_f64(y, j) * readlane_f64(rd, j);
                     if (lane == j) xs = xj;
                     if (lane < j) y = fma(-lc[j], xj, y);
                 }
@@ -1181,7 +1224,7 @@ __device__ __forceinline__ int chol_solve_blocked(int n, double* M, double* b, d
         // ---- 1. diagonal block (wave 0); L_D to M, y_D to b
         if (w == 0) {
             double a[BCH_NB];
-            const bool bad = bch_diag(n, kb, nb, M, b + kb, lrow, dinv, a);
+            const bool bad = bch_diag<false>(n, kb, nb, M, b + kb, lrow, dinv, a);
             if (lane < nb) {
 #pragma unroll
                 for (int c = 0; c < BCH_NB; ++c)
@@ -1256,8 +1299,18 @@ __global__ __launch_bounds__(WAVE) void mchol_panel_kernel(MChol a, int kb) {
     double* dinv = lw + BCH_NB * BCH_LD;
     double* yd = dinv + BCH_NB;
     const int n = a.n, nb = min(BCH_NB, n - kb), lane = threadIdx.x;
+    // this lane's panel row, loaded before the diagonal block is factored
+    // (the loads do not depend on it)
+    const int i = kb + nb + blockIdx.x * WAVE + lane;
+    double* row = a.M + (size_t)(i < n ? i : n - 1) * n + kb;
+    double x[BCH_NB];
+#pragma unroll
+    for (int c = 0; c < BCH_NB; ++c) {
+        const double v = row[c < nb ? c : nb - 1];
+        x[c] = ((i < n) & (c < nb)) ? v : 0.0;
+    }
     double r[BCH_NB];
-    const bool bad = bch_diag(n, kb, nb, a.M, a.b + kb, lrow, dinv, r);
+    const bool bad = bch_diag<true>(n, kb, nb, a.M, a.b + kb, lrow, dinv, r);
     if (bad) {
         if (blockIdx.x == 0 && lane == 0) *a.bad = 1.0;
         return;
@@ -1278,8 +1331,7 @@ __global__ __launch_bounds__(WAVE) void mchol_panel_kernel(MChol a, int kb) {
         }
     }
     __syncthreads();
-    const int i = kb + nb + blockIdx.x * WAVE + lane;
-    if (i < n) a.b[i] -= bch_row(a.M + (size_t)i * n + kb, nb, lrow, dinv, yd);
+    if (i < n) a.b[i] -= bch_row_solve(x, row, nb, lrow, dinv, yd);
 }
 
 __global__ __launch_bounds__(WAVE * MCHOL_UPDATE_WAVES) void mchol_update_kernel(MChol a, int kb) {
@@ -1301,18 +1353,94 @@ __global__ __launch_bounds__(WAVE * MCHOL_UPDATE_WAVES) void mchol_update_kernel
     bch_tile(n, a.M, kb, nb, t0 + 32 * TI, t0 + 32 * TJ);
 }
 
+// Back substitution L^T x = y by one workgroup of MCHOL_BACK_THREADS, as
+// bch_back, with the operands of each block's column update loaded (up to
+// two columns per thread) before the diagonal block is solved, so that their
+// latency overlaps the solve.  b (LDS, n): y on entry, x on return.
+constexpr int MCHOL_BACK_THREADS = 512;
+constexpr int MCHOL_BACK_CPT = 2;
+__device__ __forceinline__ void bch_back_prefetch(int n, const double* M, double* b) {
+    const int tid = threadIdx.x, lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int nblk = (n + BCH_NB - 1) / BCH_NB;
+    for (int bk = nblk - 1; bk >= 0; --bk) {
+        const int kb = bk * BCH_NB, nb = min(BCH_NB, n - kb);
+        // wave 0's diagonal block first, so that its solve can start while
+        // the column-update operands are still arriving
+        double lc[BCH_NB];
+        double y = 0.0;
+        if (w == 0) {
+#pragma unroll
+            for (int c = 0; c < BCH_NB; ++c) {
+                const double v = M[(size_t)(kb + (c < nb ? c : nb - 1)) * n + kb + (lane < nb ? lane : nb - 1)];
+                lc[c] = ((lane < nb) & (c < nb) & (c >= lane)) ? v : 0.0;
+            }
+            y = b[kb + (lane < nb ? lane : nb - 1)];
+            if (lane >= nb) y = 0.0;
+        }
+        double pv[MCHOL_BACK_CPT][BCH_NB];
+#pragma unroll
+        for (int q = 0; q < MCHOL_BACK_CPT; ++q) {
+            const int c = tid + q * MCHOL_BACK_THREADS;
+            const int cc = c < kb ? c : 0;
+#pragma unroll
+            for (int j = 0; j < BCH_NB; ++j) {
+                const double v = M[(size_t)(kb + (j < nb ? j : nb - 1)) * n + cc];
+                pv[q][j] = ((c < kb) & (j < nb)) ? v : 0.0;
+            }
+        }
+        if (w == 0) {
+            // lane r's own diagonal L(r, r) is lc[r]: its reciprocal, formed
+            // by every lane at once, keeps the division off the chain
+            double dl = 1.0;
+#pragma unroll
+            for (int c = 0; c < BCH_NB; ++c)
+                if (c == lane) dl = lc[c];
+            const double rd = 1.0 / dl;
+            double xs = 0.0;
+#pragma unroll
+            for (int j = BCH_NB - 1; j >= 0; --j) {
+                if (j < nb) {
+                    const double xj = readlane_f64(y, j) * readlane_f64(rd, j);
+                    if (lane == j) xs = xj;
+                    if (lane < j) y = fma(-lc[j], xj, y);
+                }
+            }
+            if (lane < nb) b[kb + lane] = xs;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MCHOL_BACK_CPT; ++q) {
+            const int c = tid + q * MCHOL_BACK_THREADS;
+            if (c < kb) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < BCH_NB; ++j)
+                    if (j < nb) acc = fma(pv[q][j], b[kb + j], acc);
+                b[c] -= acc;
+            }
+        }
+        for (int c = tid + MCHOL_BACK_CPT * MCHOL_BACK_THREADS; c < kb; c += MCHOL_BACK_THREADS) {
+            double acc = 0.0;
+            for (int j = 0; j < nb; ++j) acc = fma(M[(size_t)(kb + j) * n + c], b[kb + j], acc);
+            b[c] -= acc;
+        }
+        __syncthreads();
+    }
+}
+
 // back substitution of the multi-workgroup factorization: x from y, by one
-// workgroup (n doubles of dynamic LDS)
+// workgroup of MCHOL_BACK_THREADS (n doubles of dynamic LDS)
 __device__ __forceinline__ void mchol_back(const MChol& a, double* bl) {
     const int n = a.n;
     for (int k = threadIdx.x; k < n; k += blockDim.x) bl[k] = a.y[k];
     __syncthreads();
-    bch_back(n, a.M, bl);
+    bch_back_prefetch(n, a.M, bl);
     for (int k = threadIdx.x; k < n; k += blockDim.x) a.x[k] = bl[k];
     __syncthreads();
 }
 
-__global__ __launch_bounds__(1024) void mchol_back_kernel(MChol a, int* info) {
+__global__ __launch_bounds__(MCHOL_BACK_THREADS) void mchol_back_kernel(MChol a, int* info) {
     extern __shared__ __align__(16) double sm[];
     const bool live = mchol_live(a);
     if (live) mchol_back(a, sm);
@@ -1353,7 +1481,7 @@ hipError_t launch_chol_solve_mwg(int n, double* A, double* b, double* yw, double
     const size_t lds = sizeof(double) * (size_t)n;
     e = ensure_dynamic_lds((const void*)mchol_back_kernel, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mchol_back_kernel, dim3(1), dim3(1024), lds, s, a, info);
+    hipLaunchKernelGGL(mchol_back_kernel, dim3(1), dim3(MCHOL_BACK_THREADS), lds, s, a, info);
     return hipGetLastError();
 }
 
@@ -1366,32 +1494,28 @@ constexpr int CTRL_SHIFT_TRIES = 8;       // raises of the diagonal before an in
 __host__ __device__ inline bool newton_large(int n1) {
     return !(n1 >= 1 && n1 <= RCH_MAX_N) && n1 > CTRL_CHOL_LDS_MAX_N;
 }
-// Factorizations of the small systems (n1 <= CTRL_CHOL_LDS_MAX_N): LDL^T in
-// registers, Cholesky in LDS, or the blocked factorization on a copy in LDS
-enum : int { NSMALL_REGS = 1, NSMALL_LDS = 2, NSMALL_BLOCKED = 3 };
-constexpr int NSMALL_BLOCKED_MAX_N = 132;  // CTRL_THREADS + n^2 + blocked scratch doubles < 160 KiB
-__host__ __device__ inline int newton_small_kind(int n1, int force) {
-    if (force == NSMALL_BLOCKED && n1 <= NSMALL_BLOCKED_MAX_N) return NSMALL_BLOCKED;
-    if (force == NSMALL_LDS && n1 <= CTRL_CHOL_LDS_MAX_N) return NSMALL_LDS;
-    return (n1 >= 1 && n1 <= RCH_MAX_N) ? NSMALL_REGS : NSMALL_LDS;
-}
-// kernel instances of the one-workgroup Newton step
-enum : int { NK_SMALL = 0, NK_SBLOCK = 1, NK_LARGE = 2 };
-__host__ __device__ inline int newton_kind(int n1, int force) {
-    if (newton_large(n1)) return NK_LARGE;
-    return newton_small_kind(n1, force) == NSMALL_BLOCKED ? NK_SBLOCK : NK_SMALL;
-}
+// kernel instances of the one-workgroup Newton step: the register and LDS
+// factorizations, or the blocked one in global memory
+enum : int { NK_SMALL = 0, NK_LARGE = 1 };
+__host__ __device__ inline int newton_kind(int n1) { return newton_large(n1) ? NK_LARGE : NK_SMALL; }
+// threads of each instance: the register factorization needs 16 waves; the
+// blocked one keeps more values per lane than 16 waves could hold without
+// spilling, and a system below MCHOL_MIN_N needs no more than eight
+__host__ __device__ constexpr int newton_threads(int nk) { return nk == NK_LARGE ? 512 : CTRL_THREADS; }
 // LDS scratch of the control step: two n1-vectors and the wave sums of a
 // block reduction after them, and at least one double per thread
 __host__ __device__ inline int ctrl_scratch_doubles(int n1) {
     return CTRL_THREADS > 2 * n1 + 64 ? CTRL_THREADS : 2 * n1 + 64;
 }
 
-__global__ __launch_bounds__(CTRL_THREADS) void chol_solve_kernel(int n, double* A, double* b, int* info) {
+// THREADS: CTRL_THREADS for the register factorization (it needs 16 waves),
+// 512 for the others (more registers per lane for the blocked one)
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void chol_solve_kernel(int n, double* A, double* b, int* info) {
     extern __shared__ __align__(16) double sm[];
-    int rc;
-    if (rch_fits(n, blockDim.x)) {
-        rc = chol_solve_regs(n, A, b, b, sm);
+    int rc = 0;
+    if constexpr (THREADS == CTRL_THREADS) {
+        if (rch_fits(n, blockDim.x)) rc = chol_solve_regs(n, A, b, b, sm);
     } else if (n <= CHOL_LDS_MAX_N) {
         // LDS: rd (n), rhs (n), M (n x ld)
         const int ld = chol_ld(n);
@@ -1418,9 +1542,15 @@ hipError_t launch_chol_solve(int n, double* A, double* b, int* info, hipStream_t
     size_t lds = sizeof(double) * (rch_fits(n, CTRL_THREADS) ? rch_lds_doubles(n)
                                    : (size_t)(n <= CHOL_LDS_MAX_N ? (size_t)n * chol_ld(n) + 2 * n
                                                                   : (size_t)n + bch_lds_doubles()));
-    hipError_t ea = ensure_dynamic_lds((const void*)chol_solve_kernel, lds);
-    if (ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(CTRL_THREADS), lds, s, n, A, b, info);
+    if (rch_fits(n, CTRL_THREADS)) {
+        hipError_t ea = ensure_dynamic_lds((const void*)chol_solve_kernel<CTRL_THREADS>, lds);
+        if (ea != hipSuccess) return ea;
+        hipLaunchKernelGGL(chol_solve_kernel<CTRL_THREADS>, dim3(1), dim3(CTRL_THREADS), lds, s, n, A, b, info);
+    } else {
+        hipError_t ea = ensure_dynamic_lds((const void*)chol_solve_kernel<512>, lds);
+        if (ea != hipSuccess) return ea;
+        hipLaunchKernelGGL(chol_solve_kernel<512>, dim3(1), dim3(512), lds, s, n, A, b, info);
+    }
     return hipGetLastError();
 }
 
@@ -1461,18 +1591,19 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
     return a[0];
 }
 
-__device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayout rl, const double* red) {
+__device__ __forceinline__ void control_body_impl(double* st, double* hs, StateLayout sl, RecLayout rl,
+                                                  const double* red) {
     extern __shared__ __align__(16) double sm[];
     double* scratch = sm;  // ctrl_scratch_doubles(n1)
     __shared__ int s_next;  // 0 = continue to EVAL_AT_BASE, 1 = return
     __shared__ double s_eta;
-    const int mode = (int)st[S_MODE];
+    const int mode = (int)hs[S_MODE];
     if (mode != PM_EVAL && mode != PM_MULT) return;  // done, or a Newton system being re-solved
     const int n1 = sl.n1, d = n1 - 1;
-    const double L = st[S_L];
-    const double sigma = st[S_SIGMA];
-    const double tau = st[S_TAU];
-    const double eps = st[S_EPS];
+    const double L = hs[S_L];
+    const double sigma = hs[S_SIGMA];
+    const double tau = hs[S_TAU];
+    const double eps = hs[S_EPS];
     double* xb = st + sl.xb;
     double* dir = st + sl.dir;
     double* xbar = st + sl.xbar;
@@ -1483,25 +1614,25 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
     if (threadIdx.x == 0) s_next = 0;
     __syncthreads();
     // the run's first evaluation opens its first inner solve
-    if (mode == PM_EVAL && st[S_NPASS] == 1.0 && st[S_FO_OUTER] > 0.0) {
+    if (mode == PM_EVAL && hs[S_NPASS] == 1.0 && hs[S_FO_OUTER] > 0.0) {
         for (int k = threadIdx.x; k < n1; k += blockDim.x) xprev[k] = xb[k];
         __syncthreads();
         if (threadIdx.x == 0) {
-            st[S_FO_ON] = 1.0;
-            st[S_FO_PHASE] = 0.0;
-            st[S_FO_T] = 1.0;
+            hs[S_FO_ON] = 1.0;
+            hs[S_FO_PHASE] = 0.0;
+            hs[S_FO_T] = 1.0;
         }
         __syncthreads();
     }
 
     if (threadIdx.x == 0) {
-        st[S_NPASS] += 1.0;
-        st[S_BYTES] += red[rl.bytes];
-        st[S_SUMK] += red[rl.nm];
-        st[S_MAXK] = fmax(st[S_MAXK], red[rl.nm]);
-        if (st[S_VERBOSE] >= 2.0)
-            printf("[meb] pass %d mode %d K %.0f NI %.0f have_dir %d\n", (int)st[S_NPASS], mode, red[rl.nm],
-                   red[rl.ni], (int)st[S_HAVE_DIR]);
+        hs[S_NPASS] += 1.0;
+        hs[S_BYTES] += red[rl.bytes];
+        hs[S_SUMK] += red[rl.nm];
+        hs[S_MAXK] = fmax(hs[S_MAXK], red[rl.nm]);
+        if (hs[S_VERBOSE] >= 2.0)
+            printf("[meb] pass %d mode %d K %.0f NI %.0f have_dir %d\n", (int)hs[S_NPASS], mode, red[rl.nm],
+                   red[rl.ni], (int)hs[S_HAVE_DIR]);
     }
 
     if (mode == PM_MULT) {
@@ -1513,34 +1644,34 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
             const double p0 = fabs(1.0 - red[rl.ku]);
             const double p2 = red[rl.kmax + 0] / L, p3 = red[rl.kmax + 1], p4 = red[rl.kmax + 2] / L;
             const double kkt = fmax(fmax(fmax(p0, nsv), fmax(p2, p3)), p4);
-            st[S_KKT] = kkt;
-            st[S_KKT_P0] = p0;
-            st[S_KKT_P1] = nsv;
-            st[S_KKT_P2] = p2;
-            st[S_KKT_P3] = p3;
-            st[S_KKT_P4] = p4;
-            st[S_K] += 1.0;
+            hs[S_KKT] = kkt;
+            hs[S_KKT_P0] = p0;
+            hs[S_KKT_P1] = nsv;
+            hs[S_KKT_P2] = p2;
+            hs[S_KKT_P3] = p3;
+            hs[S_KKT_P4] = p4;
+            hs[S_K] += 1.0;
             int done = 0;
-            if (kkt <= st[S_TOL]) {
-                st[S_STATUS] = 1.0;
+            if (kkt <= hs[S_TOL]) {
+                hs[S_STATUS] = 1.0;
                 done = 1;
             } else {
-                if (kkt < 0.5 * st[S_BEST_KKT]) {
-                    st[S_BEST_KKT] = kkt;
-                    st[S_STALL] = 0.0;
+                if (kkt < 0.5 * hs[S_BEST_KKT]) {
+                    hs[S_BEST_KKT] = kkt;
+                    hs[S_STALL] = 0.0;
                 } else {
-                    st[S_STALL] += 1.0;
+                    hs[S_STALL] += 1.0;
                 }
-                if (st[S_K] >= st[S_MAX_OUTER] || st[S_STALL] >= st[S_STALL_OUTER]) {
-                    st[S_STATUS] = 2.0;
+                if (hs[S_K] >= hs[S_MAX_OUTER] || hs[S_STALL] >= hs[S_STALL_OUTER]) {
+                    hs[S_STATUS] = 2.0;
                     done = 1;
-                } else if (st[S_FLOOR] != 0.0) {
-                    st[S_STATUS] = 3.0;
+                } else if (hs[S_FLOOR] != 0.0) {
+                    hs[S_STATUS] = 3.0;
                     done = 1;
                 }
             }
             if (done) {
-                st[S_MODE] = (double)PM_DONE;
+                hs[S_MODE] = (double)PM_DONE;
                 s_next = 1;
             }
         }
@@ -1554,26 +1685,26 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
             return;
         }
         // next outer iteration: sigma, proximal center, inner solver
-        const bool fo = st[S_K] < st[S_FO_OUTER];
+        const bool fo = hs[S_K] < hs[S_FO_OUTER];
         for (int k = threadIdx.x; k < n1; k += blockDim.x) {
             xbar[k] = xb[k];
             if (fo) xprev[k] = xb[k];
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            const double sn = st[S_SIGMA_NEXT];
-            st[S_SIGMA] = sn;
-            st[S_SIGMA_NEXT] = fmin(sn * st[S_GROWTH], st[S_SIGMA_MAX]);
-            st[S_J] = 0.0;
-            st[S_HAVE_DIR] = 0.0;
-            st[S_FO_ON] = fo ? 1.0 : 0.0;
-            st[S_FO_PHASE] = 0.0;
-            st[S_FO_T] = 1.0;
-            st[S_FO_STEP] = 0.0;  // re-estimated for the new penalty
+            const double sn = hs[S_SIGMA_NEXT];
+            hs[S_SIGMA] = sn;
+            hs[S_SIGMA_NEXT] = fmin(sn * hs[S_GROWTH], hs[S_SIGMA_MAX]);
+            hs[S_J] = 0.0;
+            hs[S_HAVE_DIR] = 0.0;
+            hs[S_FO_ON] = fo ? 1.0 : 0.0;
+            hs[S_FO_PHASE] = 0.0;
+            hs[S_FO_T] = 1.0;
+            hs[S_FO_STEP] = 0.0;  // re-estimated for the new penalty
         }
         __syncthreads();
         // fall through: the record's evaluation part is at (x_j, w+, sigma_{k+1})
-    } else if (st[S_HAVE_DIR] != 0.0 && st[S_FO_PHASE] != 0.0) {
+    } else if (hs[S_HAVE_DIR] != 0.0 && hs[S_FO_PHASE] != 0.0) {
         // accelerated gradient method (first-order inner solver for the
         // early outer iterations, Section 4.1): the trials gave Psi at
         // y - eta s g (dir = -s g, y = x_base).  Backtracking on the step:
@@ -1595,7 +1726,7 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
             const double sg = sigma;
             const double z0 = red[rl.trial + NT - 1];
             const double psi0 = xb[0] + 0.5 * sg * z0 - red[rl.ww] / (2.0 * sg) + tau / (2.0 * sg) * xx;
-            const double gd = st[S_GD];
+            const double gd = hs[S_GD];
             const double allow = 8.0 * eps * (fabs(psi0) + 1.0);
             int acc = -1;
             for (int l = 0; l < NT - 1; ++l) {
@@ -1610,9 +1741,9 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
             // no trial passed: stay at y with a step shorter than every trial
             const double eta = acc >= 0 ? solver_eta(acc) : 0.0;
             // the step grows again after a full step, so it tracks the local curvature
-            st[S_FO_STEP] *= acc == 0 ? 2.0 : (acc > 0 ? eta : solver_eta(NT - 2) * 0.5);
+            hs[S_FO_STEP] *= acc == 0 ? 2.0 : (acc > 0 ? eta : solver_eta(NT - 2) * 0.5);
             s_eta = eta;
-            st[S_NFO] += 1.0;
+            hs[S_NFO] += 1.0;
         }
         __syncthreads();
         const double eta = s_eta;
@@ -1622,13 +1753,13 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
         const double rs = block_sum(prs, scratch);
         __shared__ double s_beta;
         if (threadIdx.x == 0) {
-            double t = st[S_FO_T];
+            double t = hs[S_FO_T];
             if (rs > 0.0 || eta == 0.0) t = 1.0;  // restart
             const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
             s_beta = (t - 1.0) / tn;
-            st[S_FO_T] = tn;
-            st[S_FO_PHASE] = 0.0;
-            st[S_HAVE_DIR] = 0.0;
+            hs[S_FO_T] = tn;
+            hs[S_FO_PHASE] = 0.0;
+            hs[S_HAVE_DIR] = 0.0;
         }
         __syncthreads();
         const double beta = s_beta;
@@ -1638,7 +1769,7 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
             xprev[k] = xn;
         }
         return;  // next pass evaluates at the momentum point
-    } else if (st[S_HAVE_DIR] != 0.0) {
+    } else if (hs[S_HAVE_DIR] != 0.0) {
         // single-pass Armijo decision along x_base + eta dir
         const double sg = sigma;
         double pdd = 0.0, pdx = 0.0, pxx = 0.0;
@@ -1657,7 +1788,7 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
             for (int l = 0; l < NT; ++l) trl[l] = red[rl.trial + l];
             const double z0 = trl[NT - 1];
             const double psi0 = xb[0] + 0.5 * sg * z0 - red[rl.ww] / (2.0 * sg) + tau / (2.0 * sg) * xx;
-            const double gd = st[S_GD];
+            const double gd = hs[S_GD];
             const double allow = 8.0 * eps * (fabs(psi0) + 1.0);
             int acc = -1;
             for (int l = 0; l < NT - 1; ++l) {
@@ -1669,41 +1800,41 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
                     break;
                 }
             }
-            if (st[S_VERBOSE] >= 2.0)
+            if (hs[S_VERBOSE] >= 2.0)
                 printf("[meb]   armijo acc=%d gd=%.17g psi0=%.17g dpsi1=%.17g\n", acc, gd, psi0,
                        dir[0] + 0.5 * sg * (trl[0] - z0) + tau / (2.0 * sg) * (2.0 * dxd + dd));
-            if (acc == 0 && st[S_HSKIP] != 0.0) {
+            if (acc == 0 && hs[S_HSKIP] != 0.0) {
                 // full step, but its Hessian contraction was skipped:
                 // move there and evaluate again
                 s_next = 2;
                 s_eta = 1.0;
-                st[S_HAVE_DIR] = 0.0;
+                hs[S_HAVE_DIR] = 0.0;
             } else if (acc == 0) {
                 s_next = 0;  // full step: record is at x_base + dir
-                st[S_PSI] = psi0;
+                hs[S_PSI] = psi0;
             } else {
                 double eta;
                 if (acc > 0) {
                     eta = solver_eta(acc);
-                    st[S_HAVE_DIR] = 0.0;
+                    hs[S_HAVE_DIR] = 0.0;
                 } else {
                     eta = solver_eta(NT - 2);
-                    st[S_LSH] += (double)(NT - 2);
-                    if (st[S_LSH] >= st[S_MAX_LS]) {
-                        st[S_HAVE_DIR] = 0.0;  // take the smallest step
+                    hs[S_LSH] += (double)(NT - 2);
+                    if (hs[S_LSH] >= hs[S_MAX_LS]) {
+                        hs[S_HAVE_DIR] = 0.0;  // take the smallest step
                     } else {
-                        st[S_GD] = gd * eta;  // retry along the shorter direction
+                        hs[S_GD] = gd * eta;  // retry along the shorter direction
                     }
                 }
                 s_eta = eta;
-                s_next = (acc > 0 || st[S_HAVE_DIR] == 0.0) ? 2 : 3;
+                s_next = (acc > 0 || hs[S_HAVE_DIR] == 0.0) ? 2 : 3;
             }
         }
         __syncthreads();
         if (s_next == 0) {
             for (int k = threadIdx.x; k < n1; k += blockDim.x) xb[k] += dir[k];
             __syncthreads();
-            if (threadIdx.x == 0) st[S_HAVE_DIR] = 0.0;
+            if (threadIdx.x == 0) hs[S_HAVE_DIR] = 0.0;
         } else {
             const double eta = s_eta;
             if (s_next == 2) {
@@ -1721,7 +1852,7 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
     for (int k = threadIdx.x; k < n1; k += blockDim.x) {
         const double dx = xb[k] - xbar[k];
         const double sv = (k == 0) ? red[rl.su] : red[rl.sv + k - 1];
-        const double g = (k == 0 ? 1.0 : 0.0) - sv + (tau / st[S_SIGMA]) * dx;
+        const double g = (k == 0 ? 1.0 : 0.0) - sv + (tau / hs[S_SIGMA]) * dx;
         gb[k] = g;
         pgg += g * g;
         pag += (ab[k] - xb[k]) * g;
@@ -1730,28 +1861,28 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
     double sums[3] = {pgg, pag, pxx};
     block_sum_n<3>(sums, scratch);
     const double gg = sums[0], ag = sums[1], xx = sums[2];
-    const double sgm = st[S_SIGMA];
+    const double sgm = hs[S_SIGMA];
     if (threadIdx.x == 0) {
-        st[S_J] += 1.0;
-        st[S_NINNER] += 1.0;
+        hs[S_J] += 1.0;
+        hs[S_NINNER] += 1.0;
         // relative-type stopping test of Algorithm 1 in normalized units
         const double sN = sgm * L, tN = tau * L * L;
         const double lhs = 2.0 * sN * fabs(ag / L) + sN * sN * gg;
-        const double rhs = st[S_RHO] * (red[rl.dm] + tN * xx / (L * L));
+        const double rhs = hs[S_RHO] * (red[rl.dm] + tN * xx / (L * L));
         const double floor_g = 8.0 * eps * (1.0 + sgm * red[rl.rs]);
         const bool rel = lhs <= rhs;
         const bool flo = sqrt(gg) <= floor_g;
-        const bool stop = rel || flo || (st[S_J] >= st[S_MAX_INNER]);
-        if (st[S_VERBOSE] >= 2.0)
+        const bool stop = rel || flo || (hs[S_J] >= hs[S_MAX_INNER]);
+        if (hs[S_VERBOSE] >= 2.0)
             printf("[meb]   eval x0=%.17g |g|=%.6e lhs=%.6e rhs=%.6e floor=%.3e dm=%.6e stop=%d\n", xb[0], sqrt(gg),
                    lhs, rhs, floor_g, red[rl.dm], (int)stop);
         if (stop) {
-            st[S_MODE] = (double)PM_MULT;
-            st[S_HAVE_DIR] = 0.0;
+            hs[S_MODE] = (double)PM_MULT;
+            hs[S_HAVE_DIR] = 0.0;
             // in a low-precision (screening) run, an inner solve that ends at
             // the rounding floor means the working precision is exhausted:
             // the run ends after this multiplier update
-            st[S_FLOOR] = (flo && !rel && eps > 1e-10) ? 1.0 : 0.0;
+            hs[S_FLOOR] = (flo && !rel && eps > 1e-10) ? 1.0 : 0.0;
             s_next = 1;
         } else {
             s_next = 0;
@@ -1759,26 +1890,26 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
     }
     __syncthreads();
     if (s_next) return;
-    if (st[S_FO_ON] != 0.0) {
+    if (hs[S_FO_ON] != 0.0) {
         // first-order step from y = x_base along -s g (its trials come next)
-        if (threadIdx.x == 0 && !(st[S_FO_STEP] > 0.0)) {
+        if (threadIdx.x == 0 && !(hs[S_FO_STEP] > 0.0)) {
             // first step: 1 / (a curvature estimate): tau/sigma + sigma (interior + mid/2)
-            st[S_FO_STEP] = 1.0 / (tau / sgm + sgm * (red[rl.ni] + 0.5 * red[rl.nm]) + 1e-300);
+            hs[S_FO_STEP] = 1.0 / (tau / sgm + sgm * (red[rl.ni] + 0.5 * red[rl.nm]) + 1e-300);
         }
         __syncthreads();
-        const double step = st[S_FO_STEP];
+        const double step = hs[S_FO_STEP];
         for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = -step * gb[k];
         __syncthreads();
         if (threadIdx.x == 0) {
-            st[S_GD] = -step * gg;
-            st[S_HAVE_DIR] = 1.0;
-            st[S_FO_PHASE] = 1.0;
-            st[S_LSH] = 0.0;
-            st[S_MODE] = (double)PM_EVAL;
+            hs[S_GD] = -step * gg;
+            hs[S_HAVE_DIR] = 1.0;
+            hs[S_FO_PHASE] = 1.0;
+            hs[S_LSH] = 0.0;
+            hs[S_MODE] = (double)PM_EVAL;
         }
         return;
     }
-    if (st[S_CG] != 0.0) {
+    if (hs[S_CG] != 0.0) {
         // matrix-free Newton direction: x = 0, r = -g; the CG launches follow
         const int cs = cg_stride(n1);
         for (int k = threadIdx.x; k < n1; k += blockDim.x) {
@@ -1787,14 +1918,27 @@ __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayo
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            st[S_CG_IT] = 0.0;
-            st[S_CG_DONE] = 0.0;
-            st[S_MODE] = (double)PM_CG;
+            hs[S_CG_IT] = 0.0;
+            hs[S_CG_DONE] = 0.0;
+            hs[S_MODE] = (double)PM_CG;
         }
         return;
     }
     // the Newton system H dir = -g is solved by the next kernel of the step
-    if (threadIdx.x == 0) st[S_MODE] = (double)PM_SOLVE;
+    if (threadIdx.x == 0) hs[S_MODE] = (double)PM_SOLVE;
+}
+
+// The control step works on a copy of the state's scalar header in LDS
+// (read with one load per thread, written back at the end): the scalars are
+// read and updated one after another by one thread, and in global memory each
+// access would wait for the one before.
+__device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayout rl, const double* red) {
+    __shared__ double hs[S_NSCALAR];
+    if (threadIdx.x < S_NSCALAR) hs[threadIdx.x] = st[threadIdx.x];
+    __syncthreads();
+    control_body_impl(st, hs, sl, rl, red);
+    __syncthreads();
+    if (threadIdx.x < S_NSCALAR) st[threadIdx.x] = hs[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -2195,15 +2339,14 @@ __device__ __forceinline__ void newton_finish(double* st, StateLayout sl, int rc
 // tries the next raise (a loop here would keep the register-resident
 // factorization's state live across attempts and spill).
 template <int NK>
-__device__ __forceinline__ void newton_body(double* st, StateLayout sl, int force) {
+__device__ __forceinline__ void newton_body(double* st, StateLayout sl) {
     extern __shared__ __align__(16) double sm[];
     if ((int)st[S_MODE] != PM_SOLVE) return;
-    if (newton_kind(sl.n1, force) != NK) return;
+    if (newton_kind(sl.n1) != NK) return;
     constexpr bool LARGE = NK == NK_LARGE;
     double* scratch = sm;                            // ctrl_scratch_doubles(n1)
     double* lmat = sm + ctrl_scratch_doubles(sl.n1);  // Cholesky matrix when it fits
     const int n1 = sl.n1;
-    const int kind = LARGE ? 0 : newton_small_kind(n1, force);
     double* dir = st + sl.dir;
     const double* gb = st + sl.gb;
     double* H = st + sl.H;
@@ -2218,17 +2361,7 @@ __device__ __forceinline__ void newton_body(double* st, StateLayout sl, int forc
         rc = chol_solve_blocked(n1, H, bv, lmat);
         for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
         __syncthreads();
-    } else if (NK == NK_SBLOCK) {
-        // the blocked factorization on a copy of H in LDS (row stride n1)
-        double* bv = scratch;
-        double* lw = lmat + (size_t)n1 * n1;
-        for (int e = threadIdx.x; e < n1 * n1; e += blockDim.x) lmat[e] = H[e];
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
-        __syncthreads();
-        rc = chol_solve_blocked(n1, lmat, bv, lw);
-        for (int k = threadIdx.x; k < n1; k += blockDim.x) dir[k] = bv[k];
-        __syncthreads();
-    } else if (kind == NSMALL_REGS) {
+    } else if (rch_fits(n1, blockDim.x)) {
         double* bv = scratch;
         for (int k = threadIdx.x; k < n1; k += blockDim.x) bv[k] = -gb[k];
         __syncthreads();
@@ -2277,7 +2410,7 @@ __global__ __launch_bounds__(CTRL_THREADS) void newton_pre_kernel(double* st, St
     if (threadIdx.x == 0) st[S_CHOL_BAD] = 0.0;
 }
 
-__global__ __launch_bounds__(CTRL_THREADS) void newton_post_kernel(double* st, StateLayout sl, int* flag) {
+__global__ __launch_bounds__(MCHOL_BACK_THREADS) void newton_post_kernel(double* st, StateLayout sl, int* flag) {
     extern __shared__ __align__(16) double sm[];
     if ((int)st[S_MODE] == PM_SOLVE) {
         const MChol a = newton_mchol(st, sl);
@@ -2293,8 +2426,8 @@ __global__ __launch_bounds__(CTRL_THREADS) void newton_post_kernel(double* st, S
 // `flag` (nullable, typically host-mapped) receives the state's mode after
 // the step.
 template <int NK>
-__global__ __launch_bounds__(CTRL_THREADS) void newton_kernel(double* st, StateLayout sl, int* flag, int force) {
-    newton_body<NK>(st, sl, force);
+__global__ __launch_bounds__(newton_threads(NK)) void newton_kernel(double* st, StateLayout sl, int* flag) {
+    newton_body<NK>(st, sl);
     if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
 }
 
@@ -2308,57 +2441,35 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
 
 size_t control_lds_bytes(int n1) { return sizeof(double) * (size_t)ctrl_scratch_doubles(n1); }
 
-// tuning override of the small systems' factorization (MEB_NEWTON_SMALL =
-// regs, lds or blocked; otherwise chosen by size)
-int newton_small_force() {
-    static const int v = [] {
-        const char* e = getenv("MEB_NEWTON_SMALL");
-        if (!e) return 0;
-        if (!strcmp(e, "regs")) return (int)NSMALL_REGS;
-        if (!strcmp(e, "lds")) return (int)NSMALL_LDS;
-        if (!strcmp(e, "blocked")) return (int)NSMALL_BLOCKED;
-        return 0;
-    }();
-    return v;
-}
-
 size_t newton_lds_bytes(int n1) {
     size_t lds = sizeof(double) * (size_t)ctrl_scratch_doubles(n1);
     if (newton_large(n1)) return lds + sizeof(double) * (size_t)bch_lds_doubles();
-    switch (newton_small_kind(n1, newton_small_force())) {
-        case NSMALL_REGS: return lds + sizeof(double) * rch_lds_doubles(n1);
-        case NSMALL_BLOCKED: return lds + sizeof(double) * ((size_t)n1 * n1 + bch_lds_doubles());
-        default: return lds + sizeof(double) * (size_t)n1 * chol_ld(n1);
-    }
+    if (rch_fits(n1, CTRL_THREADS)) return lds + sizeof(double) * rch_lds_doubles(n1);
+    return lds + sizeof(double) * (size_t)n1 * chol_ld(n1);
 }
 
 hipError_t launch_newton(double* state, StateLayout sl, int* flag, hipStream_t s) {
     if (sl.n1 >= MCHOL_MIN_N) {
         // LDS: the back substitution's vector, then block-sum scratch
-        const size_t lds = sizeof(double) * ((size_t)sl.n1 + CTRL_THREADS);
+        const size_t lds = sizeof(double) * ((size_t)sl.n1 + MCHOL_BACK_THREADS);
         hipError_t ea = ensure_dynamic_lds((const void*)newton_post_kernel, lds);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(newton_pre_kernel, dim3(1), dim3(CTRL_THREADS), sizeof(double) * CTRL_THREADS, s, state,
                            sl);
         ea = launch_mchol_factor(newton_mchol(state, sl), s);
         if (ea != hipSuccess) return ea;
-        hipLaunchKernelGGL(newton_post_kernel, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag);
+        hipLaunchKernelGGL(newton_post_kernel, dim3(1), dim3(MCHOL_BACK_THREADS), lds, s, state, sl, flag);
         return hipGetLastError();
     }
     const size_t lds = newton_lds_bytes(sl.n1);
-    const int force = newton_small_force();
-    const int nk = newton_kind(sl.n1, force);
-    const void* fn = nk == NK_LARGE    ? (const void*)newton_kernel<NK_LARGE>
-                     : nk == NK_SBLOCK ? (const void*)newton_kernel<NK_SBLOCK>
-                                       : (const void*)newton_kernel<NK_SMALL>;
+    const int nk = newton_kind(sl.n1);
+    const void* fn = nk == NK_LARGE ? (const void*)newton_kernel<NK_LARGE> : (const void*)newton_kernel<NK_SMALL>;
     hipError_t ea = ensure_dynamic_lds(fn, lds);
     if (ea != hipSuccess) return ea;
     if (nk == NK_LARGE)
-        hipLaunchKernelGGL(newton_kernel<NK_LARGE>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag, force);
-    else if (nk == NK_SBLOCK)
-        hipLaunchKernelGGL(newton_kernel<NK_SBLOCK>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag, force);
+        hipLaunchKernelGGL(newton_kernel<NK_LARGE>, dim3(1), dim3(newton_threads(NK_LARGE)), lds, s, state, sl, flag);
     else
-        hipLaunchKernelGGL(newton_kernel<NK_SMALL>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag, force);
+        hipLaunchKernelGGL(newton_kernel<NK_SMALL>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag);
     return hipGetLastError();
 }
 
@@ -2395,12 +2506,12 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_batch_kernel(const Batch
 }
 
 template <int NK>
-__global__ __launch_bounds__(CTRL_THREADS) void newton_batch_kernel(const BatchItem* tab, TickList L, int force) {
+__global__ __launch_bounds__(newton_threads(NK)) void newton_batch_kernel(const BatchItem* tab, TickList L) {
     const BatchItem& it = tab[L.slot[blockIdx.x]];
     double* st = const_cast<double*>(it.pa.state);
-    newton_body<NK>(st, it.pa.sl, force);
+    newton_body<NK>(st, it.pa.sl);
     // the flag after the item's own Newton instance
-    if (threadIdx.x == 0 && it.flag && newton_kind(it.pa.sl.n1, force) == NK) *it.flag = (int)st[S_MODE];
+    if (threadIdx.x == 0 && it.flag && newton_kind(it.pa.sl.n1) == NK) *it.flag = (int)st[S_MODE];
 }
 
 namespace {
@@ -2473,28 +2584,22 @@ hipError_t launch_tick(const BatchItem* dtab, const BatchItem* htab, const int* 
         if (e != hipSuccess) return e;
         // the Newton solves: one launch per instance that some item needs
         // (items of the other kinds return)
-        const int force = newton_small_force();
-        size_t nlds[3] = {0, 0, 0};
+        size_t nlds[2] = {0, 0};
         for (int k = 0; k < cn; ++k) {
             const int n1 = htab[sl[k]].pa.sl.n1;
-            const int nk = newton_kind(n1, force);
+            const int nk = newton_kind(n1);
             nlds[nk] = std::max(nlds[nk], newton_lds_bytes(n1));
         }
-        const void* fns[3] = {(const void*)newton_batch_kernel<NK_SMALL>, (const void*)newton_batch_kernel<NK_SBLOCK>,
-                              (const void*)newton_batch_kernel<NK_LARGE>};
-        for (int nk = 0; nk < 3; ++nk) {
+        const void* fns[2] = {(const void*)newton_batch_kernel<NK_SMALL>, (const void*)newton_batch_kernel<NK_LARGE>};
+        for (int nk = 0; nk < 2; ++nk) {
             if (nlds[nk] == 0) continue;
             const hipError_t eb = ensure_dynamic_lds(fns[nk], nlds[nk]);
             if (eb != hipSuccess) return eb;
             if (nk == NK_SMALL)
-                hipLaunchKernelGGL(newton_batch_kernel<NK_SMALL>, dim3(cn), dim3(CTRL_THREADS), nlds[nk], s, dtab, L,
-                                   force);
-            else if (nk == NK_SBLOCK)
-                hipLaunchKernelGGL(newton_batch_kernel<NK_SBLOCK>, dim3(cn), dim3(CTRL_THREADS), nlds[nk], s, dtab,
-                                   L, force);
+                hipLaunchKernelGGL(newton_batch_kernel<NK_SMALL>, dim3(cn), dim3(CTRL_THREADS), nlds[nk], s, dtab, L);
             else
-                hipLaunchKernelGGL(newton_batch_kernel<NK_LARGE>, dim3(cn), dim3(CTRL_THREADS), nlds[nk], s, dtab, L,
-                                   force);
+                hipLaunchKernelGGL(newton_batch_kernel<NK_LARGE>, dim3(cn), dim3(newton_threads(NK_LARGE)), nlds[nk], s,
+                                   dtab, L);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

@@ -19,6 +19,17 @@ static void group_shape(PassConfig& c, int d, int per_lane) {
     c.nlmax = c.nl <= 2 ? 2 : (c.nl <= 4 ? 4 : (c.nl <= 8 ? 8 : 16));
 }
 
+// steps per wave at least (tuning override MEB_PASS_MIN_STEPS; default 1: as
+// many waves as steps, up to the resident ones)
+int pass_min_steps() {
+    static const int v = [] {
+        const char* e = getenv("MEB_PASS_MIN_STEPS");
+        const int k = e ? atoi(e) : 1;
+        return k >= 1 && k <= 1024 ? k : 1;
+    }();
+    return v;
+}
+
 PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     PassConfig c;
     // 16-byte loads where the row length allows
@@ -103,7 +114,9 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
         c.stages = stages_generic;
         max_waves = mw_generic;
     }
-    int64_t waves = steps < max_waves ? steps : max_waves;
+    const int64_t min_steps = pass_min_steps();
+    int64_t waves = (steps + min_steps - 1) / min_steps;
+    if (waves > max_waves) waves = max_waves;
     if (waves < 1) waves = 1;
     int64_t steps_per_wave = (steps + waves - 1) / waves;
     c.bw = steps_per_wave * bpw;
