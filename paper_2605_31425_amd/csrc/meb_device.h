@@ -589,15 +589,21 @@ __device__ __forceinline__ void sum_records(const double* src, int n, int len, i
                                             double* out, bool shared_out) {
     for (int e = threadIdx.x; e < len; e += blockDim.x) {
         const bool ismax = e >= kmax && e < kmax + 3;
-        double v = ld_shared_dev(src + e);
-        for (int k0 = 1; k0 < n; k0 += 16) {
-            double x[16];
+        // all loads of a batch issue before the first is used (indices past
+        // n read record n - 1 and are not added), so a group of RED_GROUP
+        // records costs one memory round trip
+        double v = 0.0;
+        for (int k0 = 0; k0 < n; k0 += RED_GROUP) {
+            double x[RED_GROUP];
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-                x[q] = (k0 + q < n) ? ld_shared_dev(src + (int64_t)(k0 + q) * stride + e) : 0.0;
+            for (int q = 0; q < RED_GROUP; ++q) {
+                const int k = k0 + q < n ? k0 + q : n - 1;
+                x[q] = ld_shared_dev(src + (int64_t)k * stride + e);
+            }
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-                if (k0 + q < n) v = ismax ? fmax(v, x[q]) : v + x[q];
+            for (int q = 0; q < RED_GROUP; ++q) {
+                if (k0 + q < n) v = (k0 + q == 0) ? x[q] : (ismax ? fmax(v, x[q]) : v + x[q]);
+            }
         }
         if (shared_out)
             st_shared_dev(out + e, v);
@@ -688,36 +694,59 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const PassConfig& c
 
     constexpr bool is_mult = (KIND == 2);
     constexpr bool want_kkt = (KIND != 0);
-    const bool have_dir = (KIND != 2) && st[S_HAVE_DIR] != 0.0;
+    // every state value the pass needs is loaded before any is used (one
+    // memory round trip; the direction is read even when there is none and
+    // then ignored)
+    const double hd_raw = st[S_HAVE_DIR];
+    const double dir0_raw = st[sl.dir];
+    const double xb0 = st[sl.xb];
+    const double sig_a_d = st[S_SIGMA];
+    const double sig_b_d = st[S_SIGMA_NEXT];
+    constexpr int KQ = (MEB_MAX_D + PASS_THREADS - 1) / PASS_THREADS;
+    const int nq = (d + PASS_THREADS - 1) / PASS_THREADS;  // uniform
+    double dk_raw[KQ], xk_raw[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+        if (q < nq) {
+            const int k = threadIdx.x + q * PASS_THREADS;
+            const int kc = k < d ? k : d - 1;
+            dk_raw[q] = st[sl.dir + 1 + kc];
+            xk_raw[q] = st[sl.xb + 1 + kc];
+        }
+    }
+    const bool have_dir = (KIND != 2) && hd_raw != 0.0;
 
     // the evaluation point y = x_base + dir and the direction, staged in LDS
     double* l_c = lds;
     double* l_dc = lds + d;
     double* l_red = lds + 2 * d;
     double part = 0.0;
-    for (int k = threadIdx.x; k < d; k += PASS_THREADS) {
-        double dk = have_dir ? st[sl.dir + 1 + k] : 0.0;
-        l_c[k] = st[sl.xb + 1 + k] + dk;
-        l_dc[k] = dk;
-        part += dk * dk;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+        const int k = threadIdx.x + q * PASS_THREADS;
+        if (q < nq && k < d) {
+            const double dk = have_dir ? dk_raw[q] : 0.0;
+            l_c[k] = xk_raw[q] + dk;
+            l_dc[k] = dk;
+            part += dk * dk;
+        }
     }
-    l_red[threadIdx.x] = part;
     if constexpr (pass_ring_capable(NLMAX)) {
         if (threadIdx.x < 4)
             reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(lds) +
                                         pass_lds_zero_offset<T, VEC, NLMAX>(d, cfg.stages))[threadIdx.x] = 0u;
     }
+    // ||dir||^2: each wave sums its lanes, then the WPB wave sums in order
+    part = wave_sum_t<double>(part);
+    if ((threadIdx.x & (WAVE - 1)) == 0) l_red[threadIdx.x / WAVE] = part;
     __syncthreads();
-    for (int o = PASS_THREADS / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) l_red[threadIdx.x] += l_red[threadIdx.x + o];
-        __syncthreads();
-    }
-    const T dc2 = (T)l_red[0];
-    const double dirr_d = have_dir ? st[sl.dir] : 0.0;
-    const T r1 = (T)(st[sl.xb] + dirr_d);
+    double dsum = 0.0;
+#pragma unroll
+    for (int w = 0; w < WPB; ++w) dsum += l_red[w];
+    const T dc2 = (T)dsum;
+    const double dirr_d = have_dir ? dir0_raw : 0.0;
+    const T r1 = (T)(xb0 + dirr_d);
     const T dirr = (T)dirr_d;
-    const double sig_a_d = st[S_SIGMA];
-    const double sig_b_d = st[S_SIGMA_NEXT];
     const T sig_a = (T)sig_a_d;
     const T inv_a = (T)(1.0 / sig_a_d);
     const T sig_b = (T)sig_b_d;

@@ -7,6 +7,8 @@
 
 #include <string>
 
+#include "meb.h"
+
 namespace meb {
 
 // Number of Armijo trial step sizes evaluated in one data pass.  The solver
@@ -223,6 +225,8 @@ struct PassConfig {
 
 PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu);
 int pass_min_steps();
+constexpr int PASS_OVERSUB_DEFAULT = 1;
+int pass_oversub();
 
 // Arguments of the evaluation pass.
 struct PassArgs {

@@ -1353,98 +1353,79 @@ __global__ __launch_bounds__(WAVE * MCHOL_UPDATE_WAVES) void mchol_update_kernel
     bch_tile(n, a.M, kb, nb, t0 + 32 * TI, t0 + 32 * TJ);
 }
 
-// Back substitution L^T x = y by one workgroup of MCHOL_BACK_THREADS, as
-// bch_back, with the operands of each block's column update loaded (up to
-// two columns per thread) before the diagonal block is solved, so that their
-// latency overlaps the solve.  b (LDS, n): y on entry, x on return.
-constexpr int MCHOL_BACK_THREADS = 512;
-constexpr int MCHOL_BACK_CPT = 2;
-__device__ __forceinline__ void bch_back_prefetch(int n, const double* M, double* b) {
+// Back substitution L^T x = y across workgroups, one launch per diagonal
+// block from the bottom (the launches order the blocks): every workgroup
+// loads its threads' column-update operands L(kb + j, c), c < kb, then its
+// first wave solves the diagonal block for x_D itself (the same arithmetic in
+// each workgroup, so the same x_D), and each thread subtracts its column's
+// share, y_c -= sum_j L(kb + j, c) x_j.  Workgroup 0 stores x_D.  y (global)
+// holds the forward substitution's result on entry of the first launch.
+constexpr int MCHOL_BACK_COLS = 256;  // columns (threads) per workgroup
+__global__ __launch_bounds__(MCHOL_BACK_COLS) void mchol_back_kernel(MChol a, int kb) {
+    __shared__ double xd[BCH_NB];
+    if (!mchol_live(a)) return;
+    const int n = a.n, nb = min(BCH_NB, n - kb);
     const int tid = threadIdx.x, lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    const int nblk = (n + BCH_NB - 1) / BCH_NB;
-    for (int bk = nblk - 1; bk >= 0; --bk) {
-        const int kb = bk * BCH_NB, nb = min(BCH_NB, n - kb);
-        // wave 0's diagonal block first, so that its solve can start while
-        // the column-update operands are still arriving
+    const int c = blockIdx.x * MCHOL_BACK_COLS + tid;
+    const int cc = c < kb ? c : 0;
+    double pv[BCH_NB];
+#pragma unroll
+    for (int j = 0; j < BCH_NB; ++j) {
+        const double v = a.M[(size_t)(kb + (j < nb ? j : nb - 1)) * n + cc];
+        pv[j] = ((c < kb) & (j < nb)) ? v : 0.0;
+    }
+    if (w == 0) {
+        // lane r holds column r of L_D (L(k, r), k >= r) and y_r
         double lc[BCH_NB];
-        double y = 0.0;
-        if (w == 0) {
 #pragma unroll
-            for (int c = 0; c < BCH_NB; ++c) {
-                const double v = M[(size_t)(kb + (c < nb ? c : nb - 1)) * n + kb + (lane < nb ? lane : nb - 1)];
-                lc[c] = ((lane < nb) & (c < nb) & (c >= lane)) ? v : 0.0;
-            }
-            y = b[kb + (lane < nb ? lane : nb - 1)];
-            if (lane >= nb) y = 0.0;
+        for (int k = 0; k < BCH_NB; ++k) {
+            const double v = a.M[(size_t)(kb + (k < nb ? k : nb - 1)) * n + kb + (lane < nb ? lane : nb - 1)];
+            lc[k] = ((lane < nb) & (k < nb) & (k >= lane)) ? v : 0.0;
         }
-        double pv[MCHOL_BACK_CPT][BCH_NB];
+        double y = a.y[kb + (lane < nb ? lane : nb - 1)];
+        if (lane >= nb) y = 0.0;
+        // lane r's own pivot L(r, r) is lc[r]: its reciprocal, formed by every
+        // lane at once, keeps the division off the chain
+        double dl = 1.0;
 #pragma unroll
-        for (int q = 0; q < MCHOL_BACK_CPT; ++q) {
-            const int c = tid + q * MCHOL_BACK_THREADS;
-            const int cc = c < kb ? c : 0;
+        for (int k = 0; k < BCH_NB; ++k)
+            if (k == lane) dl = lc[k];
+        const double rd = 1.0 / dl;
+        double xs = 0.0;
 #pragma unroll
-            for (int j = 0; j < BCH_NB; ++j) {
-                const double v = M[(size_t)(kb + (j < nb ? j : nb - 1)) * n + cc];
-                pv[q][j] = ((c < kb) & (j < nb)) ? v : 0.0;
-            }
-        }
-        if (w == 0) {
-            // lane r's own diagonal L(r, r) is lc[r]: its reciprocal, formed
-            // by every lane at once, keeps the division off the chain
-            double dl = 1.0;
-#pragma unroll
-            for (int c = 0; c < BCH_NB; ++c)
-                if (c == lane) dl = lc[c];
-            const double rd = 1.0 / dl;
-            double xs = 0.0;
-#pragma unroll
-            for (int j = BCH_NB - 1; j >= 0; --j) {
-                if (j < nb) {
-                    const double xj = readlane_f64(y, j) * readlane_f64(rd, j);
-                    if (lane == j) xs = xj;
-                    if (lane < j) y = fma(-lc[j], xj, y);
-                }
-            }
-            if (lane < nb) b[kb + lane] = xs;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < MCHOL_BACK_CPT; ++q) {
-            const int c = tid + q * MCHOL_BACK_THREADS;
-            if (c < kb) {
-                double acc = 0.0;
-#pragma unroll
-                for (int j = 0; j < BCH_NB; ++j)
-                    if (j < nb) acc = fma(pv[q][j], b[kb + j], acc);
-                b[c] -= acc;
+        for (int j = BCH_NB - 1; j >= 0; --j) {
+            if (j < nb) {
+                const double xj = readlane_f64(y, j) * readlane_f64(rd, j);
+                if (lane == j) xs = xj;
+                if (lane < j) y = fma(-lc[j], xj, y);
             }
         }
-        for (int c = tid + MCHOL_BACK_CPT * MCHOL_BACK_THREADS; c < kb; c += MCHOL_BACK_THREADS) {
-            double acc = 0.0;
-            for (int j = 0; j < nb; ++j) acc = fma(M[(size_t)(kb + j) * n + c], b[kb + j], acc);
-            b[c] -= acc;
-        }
-        __syncthreads();
+        if (lane < BCH_NB) xd[lane] = lane < nb ? xs : 0.0;
+        if (blockIdx.x == 0 && lane < nb) a.x[kb + lane] = xs;
+    }
+    __syncthreads();
+    if (c < kb) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < BCH_NB; ++j) acc = fma(pv[j], xd[j], acc);
+        a.y[c] -= acc;
     }
 }
 
-// back substitution of the multi-workgroup factorization: x from y, by one
-// workgroup of MCHOL_BACK_THREADS (n doubles of dynamic LDS)
-__device__ __forceinline__ void mchol_back(const MChol& a, double* bl) {
-    const int n = a.n;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) bl[k] = a.y[k];
-    __syncthreads();
-    bch_back_prefetch(n, a.M, bl);
-    for (int k = threadIdx.x; k < n; k += blockDim.x) a.x[k] = bl[k];
-    __syncthreads();
+// the solve's outcome: 0, or -1 if a pivot was not positive
+__global__ void mchol_info_kernel(MChol a, int* info) {
+    if (threadIdx.x == 0) *info = *a.bad == 0.0 ? 0 : -1;
 }
 
-__global__ __launch_bounds__(MCHOL_BACK_THREADS) void mchol_back_kernel(MChol a, int* info) {
-    extern __shared__ __align__(16) double sm[];
-    const bool live = mchol_live(a);
-    if (live) mchol_back(a, sm);
-    if (threadIdx.x == 0 && info) *info = live ? 0 : -1;
+// the back-substitution launches of one solve
+hipError_t launch_mchol_back(const MChol& a, hipStream_t s) {
+    const int n = a.n;
+    for (int kb = (n - 1) / BCH_NB * BCH_NB; kb >= 0; kb -= BCH_NB) {
+        const int blocks = std::max(1, (kb + MCHOL_BACK_COLS - 1) / MCHOL_BACK_COLS);
+        hipLaunchKernelGGL(mchol_back_kernel, dim3(blocks), dim3(MCHOL_BACK_COLS), 0, s, a, kb);
+    }
+    return hipGetLastError();
 }
 
 // the panel and update launches of one factorization
@@ -1478,10 +1459,9 @@ hipError_t launch_chol_solve_mwg(int n, double* A, double* b, double* yw, double
     if (e != hipSuccess) return e;
     e = launch_mchol_factor(a, s);
     if (e != hipSuccess) return e;
-    const size_t lds = sizeof(double) * (size_t)n;
-    e = ensure_dynamic_lds((const void*)mchol_back_kernel, lds);
+    e = launch_mchol_back(a, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mchol_back_kernel, dim3(1), dim3(MCHOL_BACK_THREADS), lds, s, a, info);
+    hipLaunchKernelGGL(mchol_info_kernel, dim3(1), dim3(WAVE), 0, s, a, info);
     return hipGetLastError();
 }
 
@@ -2386,8 +2366,10 @@ __device__ __forceinline__ void newton_body(double* st, StateLayout sl) {
 // The Newton step with the multi-workgroup factorization (systems of at
 // least MCHOL_MIN_N unknowns, single-instance runs): newton_pre_kernel
 // (breakdown guard, b = -g in dir, the failure flag cleared), the panel and
-// update launches (gated on the mode), then newton_post_kernel (back
-// substitution into dir and the bookkeeping of newton_finish).
+// update launches and the back-substitution launches into dir (all gated on
+// the mode), then newton_post_kernel (the bookkeeping of newton_finish).
+constexpr int NEWTON_POST_THREADS = 256;
+
 __host__ __device__ inline MChol newton_mchol(double* st, StateLayout sl) {
     MChol a;
     a.n = sl.n1;
@@ -2410,15 +2392,13 @@ __global__ __launch_bounds__(CTRL_THREADS) void newton_pre_kernel(double* st, St
     if (threadIdx.x == 0) st[S_CHOL_BAD] = 0.0;
 }
 
-__global__ __launch_bounds__(MCHOL_BACK_THREADS) void newton_post_kernel(double* st, StateLayout sl, int* flag) {
-    extern __shared__ __align__(16) double sm[];
+__global__ __launch_bounds__(NEWTON_POST_THREADS) void newton_post_kernel(double* st, StateLayout sl, int* flag) {
+    __shared__ double sm[NEWTON_POST_THREADS / WAVE];
     if ((int)st[S_MODE] == PM_SOLVE) {
-        const MChol a = newton_mchol(st, sl);
         const int rc = st[S_CHOL_BAD] != 0.0 ? -1 : 0;
-        if (rc == 0) mchol_back(a, sm);
         const int attempt = (int)st[S_SHIFT_TRY];
         const double mu = attempt > 0 ? st[S_SHIFT_MU0] * (double)(1u << (4 * (attempt - 1))) : 0.0;
-        newton_finish(st, sl, rc, mu, sm + sl.n1);
+        newton_finish(st, sl, rc, mu, sm);
     }
     if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
 }
@@ -2450,15 +2430,13 @@ size_t newton_lds_bytes(int n1) {
 
 hipError_t launch_newton(double* state, StateLayout sl, int* flag, hipStream_t s) {
     if (sl.n1 >= MCHOL_MIN_N) {
-        // LDS: the back substitution's vector, then block-sum scratch
-        const size_t lds = sizeof(double) * ((size_t)sl.n1 + MCHOL_BACK_THREADS);
-        hipError_t ea = ensure_dynamic_lds((const void*)newton_post_kernel, lds);
-        if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(newton_pre_kernel, dim3(1), dim3(CTRL_THREADS), sizeof(double) * CTRL_THREADS, s, state,
                            sl);
-        ea = launch_mchol_factor(newton_mchol(state, sl), s);
+        hipError_t ea = launch_mchol_factor(newton_mchol(state, sl), s);
         if (ea != hipSuccess) return ea;
-        hipLaunchKernelGGL(newton_post_kernel, dim3(1), dim3(MCHOL_BACK_THREADS), lds, s, state, sl, flag);
+        ea = launch_mchol_back(newton_mchol(state, sl), s);
+        if (ea != hipSuccess) return ea;
+        hipLaunchKernelGGL(newton_post_kernel, dim3(1), dim3(NEWTON_POST_THREADS), 0, s, state, sl, flag);
         return hipGetLastError();
     }
     const size_t lds = newton_lds_bytes(sl.n1);

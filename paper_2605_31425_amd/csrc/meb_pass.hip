@@ -30,6 +30,17 @@ int pass_min_steps() {
     return v;
 }
 
+// rounds of resident blocks a long pass is cut into (tuning override
+// MEB_PASS_OVERSUB, 1 to 8)
+int pass_oversub() {
+    static const int v = [] {
+        const char* e = getenv("MEB_PASS_OVERSUB");
+        const int k = e ? atoi(e) : PASS_OVERSUB_DEFAULT;
+        return k >= 1 && k <= 8 ? k : PASS_OVERSUB_DEFAULT;
+    }();
+    return v;
+}
+
 PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
     PassConfig c;
     // 16-byte loads where the row length allows
@@ -91,7 +102,10 @@ PassConfig choose_pass_config(int64_t m, int d, int dtype, int num_cu) {
             }
         }
         if (per_cu < 1) per_cu = 1;
-        int64_t mw = (int64_t)num_cu * per_cu * WPB;
+        // pass_oversub() times the resident waves: the blocks beyond one
+        // round start as others finish, so compute units that stream faster
+        // take more blocks (per-block records keep the sums' order fixed)
+        int64_t mw = (int64_t)num_cu * per_cu * WPB * pass_oversub();
         // the in-kernel reduction takes at most RED_GROUP * SYNC_GROUPS blocks
         if (mw > (int64_t)RED_GROUP * SYNC_GROUPS * WPB) mw = (int64_t)RED_GROUP * SYNC_GROUPS * WPB;
         return mw;
