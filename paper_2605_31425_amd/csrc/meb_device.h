@@ -587,28 +587,38 @@ __device__ __forceinline__ void published() { wait_vm<0>(); }
 // they are combined.
 __device__ __forceinline__ void sum_records(const double* src, int n, int len, int64_t stride, int kmax,
                                             double* out, bool shared_out) {
-    for (int e = threadIdx.x; e < len; e += blockDim.x) {
-        const bool ismax = e >= kmax && e < kmax + 3;
-        // all loads of a batch issue before the first is used (indices past
-        // n read record n - 1 and are not added), so a group of RED_GROUP
-        // records costs one memory round trip
-        double v = 0.0;
+    // two elements per thread at a time, and all loads of a batch of
+    // RED_GROUP records issued before the first is used (indices past n read
+    // record n - 1 and are not added): a group costs one memory round trip
+    // for records of up to two elements per thread
+    for (int e0 = threadIdx.x; e0 < len; e0 += 2 * blockDim.x) {
+        const int e1 = e0 + blockDim.x;
+        const int e1c = e1 < len ? e1 : e0;
+        const bool max0 = e0 >= kmax && e0 < kmax + 3, max1 = e1 >= kmax && e1 < kmax + 3;
+        double v0 = 0.0, v1 = 0.0;
         for (int k0 = 0; k0 < n; k0 += RED_GROUP) {
-            double x[RED_GROUP];
+            double x0[RED_GROUP], x1[RED_GROUP];
 #pragma unroll
             for (int q = 0; q < RED_GROUP; ++q) {
                 const int k = k0 + q < n ? k0 + q : n - 1;
-                x[q] = ld_shared_dev(src + (int64_t)k * stride + e);
+                x0[q] = ld_shared_dev(src + (int64_t)k * stride + e0);
+                x1[q] = ld_shared_dev(src + (int64_t)k * stride + e1c);
             }
 #pragma unroll
             for (int q = 0; q < RED_GROUP; ++q) {
-                if (k0 + q < n) v = (k0 + q == 0) ? x[q] : (ismax ? fmax(v, x[q]) : v + x[q]);
+                if (k0 + q < n) {
+                    v0 = (k0 + q == 0) ? x0[q] : (max0 ? fmax(v0, x0[q]) : v0 + x0[q]);
+                    v1 = (k0 + q == 0) ? x1[q] : (max1 ? fmax(v1, x1[q]) : v1 + x1[q]);
+                }
             }
         }
-        if (shared_out)
-            st_shared_dev(out + e, v);
-        else
-            out[e] = v;
+        if (shared_out) {
+            st_shared_dev(out + e0, v0);
+            if (e1 < len) st_shared_dev(out + e1, v1);
+        } else {
+            out[e0] = v0;
+            if (e1 < len) out[e1] = v1;
+        }
     }
 }
 

@@ -29,7 +29,8 @@ constexpr int SYRK_SEGS = 1024; // most wave segments one block walks
 // Blocks along the mid list per tile pair: the launch provides up to
 // SyrkArgs::ksplit of them (enough for about SYRK_BLOCKS blocks in all when
 // d is small), and each pass uses one per SYRK_ROWS mid rows, at least
-// SYRK_KSPLIT_MIN; the others return at once.
+// SYRK_KSPLIT_MIN; the others return at once.  (More blocks for short lists
+// -- about 256 in all -- made the benchmark's contractions slower: 12 -> 17 us.)
 constexpr int SYRK_KSPLIT_MIN = 8;
 constexpr int SYRK_KSPLIT_MAX = 1024;
 constexpr int SYRK_BLOCKS = 2048;
@@ -182,15 +183,29 @@ __device__ __forceinline__ void syrk_finish(const SyrkArgs& a, const SyrkCtx& c,
         const int k = c.I * T + r, l = c.J * T + cc;
         const double* src = a.out + (size_t)bx * T * T + r * T + cc;
         double v = 0.0;
-        int ks = 0;
-        for (; ks + 8 <= c.ks; ks += 8) {
+        // the partial tiles' loads in flight together: 8 at a time for the
+        // usual split, 32 for long lists (past c.ks: the last one again, not
+        // added)
+        if (c.ks <= 8) {
             double part[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) part[u] = ld_shared_dev(src + (size_t)(ks + u) * stride);
+            for (int u = 0; u < 8; ++u) part[u] = ld_shared_dev(src + (size_t)(u < c.ks ? u : c.ks - 1) * stride);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v += part[u];
+            for (int u = 0; u < 8; ++u)
+                if (u < c.ks) v += part[u];
+        } else {
+            for (int ks = 0; ks < c.ks; ks += 32) {
+                double part[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) {
+                    const int k = ks + u < c.ks ? ks + u : c.ks - 1;
+                    part[u] = ld_shared_dev(src + (size_t)k * stride);
+                }
+#pragma unroll
+                for (int u = 0; u < 32; ++u)
+                    if (ks + u < c.ks) v += part[u];
+            }
         }
-        for (; ks < c.ks; ++ks) v += ld_shared_dev(src + (size_t)ks * stride);
         if (k == l) v += base + red[rl.sg];
         H[(1 + k) * n1 + 1 + l] = v;
         if (c.I != c.J) H[(1 + l) * n1 + 1 + k] = v;
@@ -974,7 +989,7 @@ __host__ __device__ inline int chol_ld(int n) { return n | 1; }
 // Then the back substitution L^T x = y runs block by block from the bottom.
 // Only the lower triangle is written; the upper triangle keeps A (the
 // breakdown guard restores the lower triangle from it).  Two drivers: one
-// workgroup of 16 waves (chol_solve_blocked), or one launch per phase across
+// workgroup of 8 waves (chol_solve_blocked), or one launch per phase across
 // many workgroups (the mchol kernels below) for the largest systems.
 // ---------------------------------------------------------------------------
 constexpr int BCH_NB = MCHOL_NB;
@@ -1207,7 +1222,7 @@ __device__ __forceinline__ void bch_back(int n, const double* M, double* b) {
     }
 }
 
-// One workgroup of 16 waves: M (global, n x n) factored in place, b (LDS, n)
+// One workgroup (8 waves): M (global, n x n) factored in place, b (LDS, n)
 // holds the solution on return.  lw: bch_lds_doubles() of LDS.  Returns -1 if
 // a pivot is not positive.
 __device__ __forceinline__ int chol_solve_blocked(int n, double* M, double* b, double* lw) {
@@ -1913,10 +1928,27 @@ __device__ __forceinline__ void control_body_impl(double* st, double* hs, StateL
 // read and updated one after another by one thread, and in global memory each
 // access would wait for the one before.
 __device__ __forceinline__ void control_body(double* st, StateLayout sl, RecLayout rl, const double* red) {
+    extern __shared__ __align__(16) double sm[];
     __shared__ double hs[S_NSCALAR];
+    // the pass's reduced record too, after the scratch: read once, with
+    // several loads per thread in flight, instead of one value at a time
+    double* lred = sm + ctrl_scratch_doubles(sl.n1);
     if (threadIdx.x < S_NSCALAR) hs[threadIdx.x] = st[threadIdx.x];
+    for (int e0 = 0; e0 < rl.len; e0 += 4 * (int)blockDim.x) {
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * blockDim.x + threadIdx.x;
+            v[q] = red[e < rl.len ? e : rl.len - 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * blockDim.x + threadIdx.x;
+            if (e < rl.len) lred[e] = v[q];
+        }
+    }
     __syncthreads();
-    control_body_impl(st, hs, sl, rl, red);
+    control_body_impl(st, hs, sl, rl, lred);
     __syncthreads();
     if (threadIdx.x < S_NSCALAR) st[threadIdx.x] = hs[threadIdx.x];
 }
@@ -2419,7 +2451,9 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
     if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
 }
 
-size_t control_lds_bytes(int n1) { return sizeof(double) * (size_t)ctrl_scratch_doubles(n1); }
+size_t control_lds_bytes(int n1) {
+    return sizeof(double) * ((size_t)ctrl_scratch_doubles(n1) + (size_t)RecLayout::make(n1 - 1).len);
+}
 
 size_t newton_lds_bytes(int n1) {
     size_t lds = sizeof(double) * (size_t)ctrl_scratch_doubles(n1);
