@@ -315,6 +315,9 @@ def main():
     ap.add_argument("--serve-max-active", type=int, default=128)
     ap.add_argument("--serve-pool-gb", type=float, default=64.0)
     ap.add_argument("--serve-check", type=int, default=8)
+    ap.add_argument("--contraction-probe", action="store_true",
+                    help="only run single evaluations with the Hessian contraction of 10^5 mid-case balls at d = 1000 "
+                         "in each arithmetic (time the kernels with rocprofv3)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (3 times), to scale HBM byte counters")
     a = ap.parse_args()
@@ -336,6 +339,31 @@ def main():
         return
 
     from paper_2605_31425_amd import inputs, meb
+
+    if a.contraction_probe:
+        # balls N(0, I) in d = 1000, radii |N(0, 0.05^2)|, evaluated at c = 0 with r the median reach: about half
+        # the balls lie in the third projection case, so the contraction has K ~ 10^5 rows
+        m, d = 200000, 1000
+        gen = torch.Generator(device="cuda:0").manual_seed(3)
+        C64 = torch.randn((m, d), generator=gen, device="cuda:0", dtype=torch.float64)
+        R64 = torch.randn(m, generator=gen, device="cuda:0", dtype=torch.float64).abs() * 0.05
+        x = np.zeros(d + 1)
+        x[0] = float((C64.norm(dim=1) + R64).median())
+        res = []
+        for dt, hess in [(torch.float32, "mfma_bf16"), (torch.float32, "mfma_f32"), (torch.float64, "mfma_f64"),
+                         (torch.float64, "f64")]:
+            C, R = C64.to(dt), R64.to(dt)
+            U = torch.zeros(m, device="cuda:0", dtype=dt)
+            V = torch.zeros((m, d), device="cuda:0", dtype=dt)
+            want = meb.WANT_PSI | meb.WANT_GRAD | meb.WANT_HESS | (meb._HESS[hess] << 8)
+            for _ in range(4):
+                out = meb.al_eval(C, R, U, V, x, x.copy(), 1.0, 1.0, want=want)
+            torch.cuda.synchronize()
+            k_mid = int(round(2.0 * (out["H"][0, 0] - 1.0)))  # H_rr = tau/sigma + sigma N_I + sigma/2 N_mid
+            res.append({"dtype": str(dt).replace("torch.", ""), "hess": hess, "mid_rows": k_mid,
+                        "flop_per_contraction": float(k_mid) * d * (d + 1)})
+        print(json.dumps({"contraction_probe": res}), flush=True)
+        return
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
