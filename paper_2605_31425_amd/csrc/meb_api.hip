@@ -208,7 +208,9 @@ int Engine::step(const PassArgs& a, bool control, hipStream_t s, hipEvent_t ev0,
         return MEB_OK;
     }
     if (a.want_mid) HIPCHK(launch_syrk(syrk_args(a.C, U, V), s));
-    if (control) {
+    if (control && control_newton_fused(sl.n1)) {
+        HIPCHK(launch_control_newton(state, sl, rl, red, flag, s));
+    } else if (control) {
         HIPCHK(launch_control(state, sl, rl, red, nullptr, s));
         HIPCHK(launch_newton(state, sl, flag, s));
     }

@@ -364,6 +364,12 @@ hipError_t launch_newton(double* state, StateLayout sl, int* flag, hipStream_t s
 int syrk_ksplit(int64_t m, int d, int nwaves);
 hipError_t launch_control(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag_host_mapped,
                           hipStream_t s);
+// control step and Newton step in one launch (systems of n1 unknowns for
+// which control_newton_fused(n1) holds); the same effect as launch_control
+// followed by launch_newton
+bool control_newton_fused(int n1);
+hipError_t launch_control_newton(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag,
+                                 hipStream_t s);
 // g of a single evaluation, and a copy of the H assembled in the state
 hipError_t launch_eval_outputs(const double* state, StateLayout sl, RecLayout rl, const double* red, double sigma,
                                double tau, const double* y, const double* xbar, double* out_g, double* out_H,

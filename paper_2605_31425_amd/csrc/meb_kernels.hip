@@ -2451,6 +2451,22 @@ __global__ __launch_bounds__(CTRL_THREADS) void control_kernel(double* st, State
     if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
 }
 
+// The control step and then the Newton step in one launch, for systems the
+// one-workgroup factorizations take (newton_kind NK_SMALL): the same bodies
+// as control_kernel and newton_kernel<NK_SMALL>, one after the other on the
+// same workgroup of CTRL_THREADS, so a solver step pays one kernel boundary
+// less.  The Newton body reads the header the control body wrote back to
+// global memory after the block barrier (same workgroup: no cache
+// maintenance).  Both bodies use the dynamic LDS from its start, one after
+// the other.  `flag` as for newton_kernel.
+__global__ __launch_bounds__(CTRL_THREADS) void control_newton_kernel(double* st, StateLayout sl, RecLayout rl,
+                                                                      const double* red, int* flag) {
+    control_body(st, sl, rl, red);
+    __syncthreads();
+    newton_body<NK_SMALL>(st, sl);
+    if (threadIdx.x == 0 && flag) *flag = (int)st[S_MODE];
+}
+
 size_t control_lds_bytes(int n1) {
     return sizeof(double) * ((size_t)ctrl_scratch_doubles(n1) + (size_t)RecLayout::make(n1 - 1).len);
 }
@@ -2482,6 +2498,18 @@ hipError_t launch_newton(double* state, StateLayout sl, int* flag, hipStream_t s
         hipLaunchKernelGGL(newton_kernel<NK_LARGE>, dim3(1), dim3(newton_threads(NK_LARGE)), lds, s, state, sl, flag);
     else
         hipLaunchKernelGGL(newton_kernel<NK_SMALL>, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, flag);
+    return hipGetLastError();
+}
+
+bool control_newton_fused(int n1) { return n1 < MCHOL_MIN_N && newton_kind(n1) == NK_SMALL; }
+
+hipError_t launch_control_newton(double* state, StateLayout sl, RecLayout rl, const double* red, int* flag,
+                                 hipStream_t s) {
+    if (!control_newton_fused(sl.n1)) return hipErrorInvalidValue;
+    const size_t lds = std::max(control_lds_bytes(sl.n1), newton_lds_bytes(sl.n1));
+    hipError_t ea = ensure_dynamic_lds((const void*)control_newton_kernel, lds);
+    if (ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(control_newton_kernel, dim3(1), dim3(CTRL_THREADS), lds, s, state, sl, rl, red, flag);
     return hipGetLastError();
 }
 
