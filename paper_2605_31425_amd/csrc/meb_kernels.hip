@@ -887,80 +887,56 @@ __device__ __forceinline__ int chol_solve_regs(int n, const double* H, const dou
         }
     }
     if (s_bad) return -1;
-    // L^T x = l (l in row n, L unit lower): x_k = w_k, then w_j -= L_kj x_k
-    // for j < k.  Four steps at a time: their w are broadcast together, the
-    // 4 x 4 triangle among them is solved in uniform registers, and the other
-    // lanes take one rank-4 update.  The loads of a group do not depend on
-    // the solve, so the next group's are issued before the current group is
-    // solved.  Steps past n - 1 (the top of the first group) find w = 0 and
-    // change nothing; L above the diagonal is 0, so no lane needs a mask.
+    // L^T x = l (l in row n, L unit lower), by wave 0: x_k = w_k, then
+    // w_j -= L_kj x_k for j < k (lane j holds w_j), one row at a time from the
+    // bottom; the dependent chain per row is one broadcast and one FMA.  Rows
+    // are read in blocks of eight aligned to 8 (one LDS round trip per block,
+    // the rows needed first issued first); a block lies wholly above or below
+    // row 64, so each block knows whether the upper half takes updates.  L
+    // above the diagonal is 0 (the diagonal itself only changes w_k after x_k
+    // has been taken), so no lane needs a mask; lanes past n only compute
+    // values that are never read.
     if (w == 0) {
         const double* yr = Lr + (size_t)n * ldr;
         double z0 = lane < n ? yr[lane] : 0.0;
         double z1 = lane + 64 < n ? yr[64 + lane] : 0.0;
         double x0 = 0.0, x1 = 0.0;
         const int i0 = lane < ldr ? lane : 0;  // stays inside a row of L for small n
-        struct Grp {
-            double s0[4], s1[4], c[4][4];  // rows k0 - u of L; c[u][v] = L(k0-u, k0-v)
-        };
-        auto load = [&](int k0, bool upper, Grp& g) {
+        for (int kb = (n - 1) & ~7; kb >= 0; kb -= 8) {
+            double l0[8], l1[8];
+            if (kb >= 64) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = k0 - u, kr = k < n ? k : n - 1;
-                const double* row = Lr + (size_t)kr * ldr;
-                g.s0[u] = row[i0];
-                if (upper) g.s1[u] = row[64 + lane];  // n > 64: inside L
+                for (int u = 7; u >= 0; --u) {
+                    const int kr = kb + u < n ? kb + u : n - 1;
+                    const double* row = Lr + (size_t)kr * ldr;
+                    l0[u] = row[i0];
+                    l1[u] = row[64 + lane];  // n > 64: inside L
+                }
 #pragma unroll
-                for (int v = u + 1; v < 4; ++v) g.c[u][v] = row[k0 - v < n ? k0 - v : n - 1];
-            }
-        };
-        auto solve = [&](int k0, bool upper, const Grp& g) {
-            const int off = upper ? 64 : 0;
-            double xk[4];
+                for (int u = 7; u >= 0; --u) {
+                    const int k = kb + u;
+                    if (k < n) {
+                        const double xk = readlane_f64(z1, k - 64);
+                        x1 = lane + 64 == k ? xk : x1;
+                        z0 -= l0[u] * xk;
+                        z1 -= l1[u] * xk;
+                    }
+                }
+            } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) xk[v] = readlane_f64(upper ? z1 : z0, k0 - v - off);
+                for (int u = 7; u >= 0; --u) {
+                    const int kr = kb + u < n ? kb + u : n - 1;
+                    l0[u] = Lr[(size_t)kr * ldr + i0];
+                }
 #pragma unroll
-            for (int v = 1; v < 4; ++v)
-#pragma unroll
-                for (int u = 0; u < v; ++u) xk[v] -= g.c[u][v] * xk[u];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (upper)
-                    x1 = lane + 64 == k0 - u ? xk[u] : x1;
-                else
-                    x0 = lane == k0 - u ? xk[u] : x0;
-                z0 -= g.s0[u] * xk[u];
-                if (upper) z1 -= g.s1[u] * xk[u];
-            }
-        };
-        Grp ga, gb;
-        if (n > 64) {
-            int k0 = 64 + ((n - 64 + 3) & ~3) - 1;
-            load(k0, true, ga);
-            for (;;) {
-                if (k0 - 4 >= 64) load(k0 - 4, true, gb);
-                solve(k0, true, ga);
-                k0 -= 4;
-                if (k0 < 64) break;
-                if (k0 - 4 >= 64) load(k0 - 4, true, ga);
-                solve(k0, true, gb);
-                k0 -= 4;
-                if (k0 < 64) break;
-            }
-        }
-        {
-            const int top = n < 64 ? n : 64;
-            int k0 = ((top + 3) & ~3) - 1;
-            load(k0, false, ga);
-            for (;;) {
-                if (k0 - 4 >= 0) load(k0 - 4, false, gb);
-                solve(k0, false, ga);
-                k0 -= 4;
-                if (k0 < 0) break;
-                if (k0 - 4 >= 0) load(k0 - 4, false, ga);
-                solve(k0, false, gb);
-                k0 -= 4;
-                if (k0 < 0) break;
+                for (int u = 7; u >= 0; --u) {
+                    const int k = kb + u;
+                    if (k < n) {
+                        const double xk = readlane_f64(z0, k);
+                        x0 = lane == k ? xk : x0;
+                        z0 -= l0[u] * xk;
+                    }
+                }
             }
         }
         if (lane < n) x[lane] = x0;
