@@ -807,18 +807,21 @@ int Job::on_ready(hipStream_t s) {
 
 // Solver steps per enqueued batch (two batches in flight).  The steps
 // queued behind the one that ends a run still launch and return at once
-// (≈ 4 us per kernel, many kernels per step for the factorization across
-// workgroups), and up to one and a half batches of them delay what follows
-// the run; batches of two keep the device fed with less of that tail than
-// four (the d = 1000 workload 51.1 -> 49.7 ms, the others unchanged), one
-// starves the small instances.  Tuning override MEB_STEP_BATCH, 1 to 8.
-int step_batch() {
+// (≈ 4 us per kernel), and up to one and a half batches of them delay what
+// follows the run; batches of two keep the device fed with less of that
+// tail than four (the d = 1000 workload 51.1 -> 49.7 ms, the others
+// unchanged), single steps starve the small instances.  A step of many
+// launches (the factorization across workgroups, conjugate gradients) is
+// long enough for single steps, and its queued copies cost the most.
+// Tuning override MEB_STEP_BATCH, 1 to 8.
+int step_batch(const Engine& e) {
     static const int v = [] {
-        const char* e = getenv("MEB_STEP_BATCH");
-        const int k = e ? atoi(e) : 2;
-        return k >= 1 && k <= 8 ? k : 2;
+        const char* s = getenv("MEB_STEP_BATCH");
+        const int k = s ? atoi(s) : 0;
+        return k >= 1 && k <= 8 ? k : 0;
     }();
-    return v;
+    if (v) return v;
+    return (e.sl.n1 >= MCHOL_MIN_N || e.cg_iters > 0) ? 1 : 2;
 }
 
 int drive_sync(Job& j, hipStream_t s) {
@@ -840,7 +843,7 @@ int drive_sync(Job& j, hipStream_t s) {
             const bool copy_hdr = j.o.verbose != 0;
             if (inflight == 0) *reinterpret_cast<volatile int*>(ps.mode) = PM_EVAL;
             while (inflight < 2) {
-                const int batch = step_batch();
+                const int batch = step_batch(*j.e);
                 for (int b = 0; b < batch; ++b) {
                     hipEvent_t e0 = nullptr, e1 = nullptr;
                     if (prof) {
